@@ -1,0 +1,183 @@
+/*
+ * chem.h -- C ABI of the MI355X chemistry-step library.
+ *
+ * The library advances, cell by cell, the temperature T and species mass
+ * fractions Y_k of an adiabatic, constant-pressure, ideal-gas cell over one
+ * flow time step dt under detailed finite-rate chemistry: the species
+ * production rates omega_k and heat release Q of the governing equations
+ * (Appendix A, eqs. (20)-(21)) with the detailed-chemistry model of Sec. 2.1,
+ * integrated as the operator-split energy/species stage of the solver
+ * (Sec. 2.1, PIMPLE description).  Per cell:
+ *     dY_k/dt = W_k omega_k / rho,
+ *     dT/dt   = -sum_k H_k omega_k / (rho c_p),      p fixed,
+ * with NASA-7 thermo, modified-Arrhenius forward rates, reverse rates from
+ * equilibrium constants (1 atm standard state), third-body efficiencies and
+ * Lindemann/Troe falloff, integrated by RODAS4 (Hairer & Wanner) with an
+ * analytic Jacobian, dense LU with partial pivoting, RMS error control
+ * (scale atol + rtol max(|y|, |y_new|)) and h <- h clip(0.9 err^-1/4, 0.2, 6).
+ *
+ * Conventions for every function:
+ *   - Return 0 (CHEM_OK) or a negative CHEM_E_* code; chem_last_error() then
+ *     holds a message (thread-local).
+ *   - Arrays named "device" must be device (or managed) memory on the current
+ *     HIP device; host pointers there give CHEM_E_INVAL and nothing runs.
+ *     The caller owns every array it passes; the library never frees them.
+ *   - Layout: T[ncell], p[ncell] (Pa), Y[ncell * ns] row-major (cell-major,
+ *     species fastest), all IEEE double.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *     stream) and is asynchronous, unless a stats pointer is given, which
+ *     synchronises the stream before return.
+ *   - ncell = 0 is a valid no-op.
+ *   - A mechanism handle may be used from several host threads; calls on it
+ *     are serialised internally.
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHEM_MAX_SPECIES 48
+
+typedef struct chem_mechanism chem_mechanism;   /* opaque, library-owned */
+
+enum chem_error {
+    CHEM_OK = 0,
+    CHEM_E_INVAL = -1,          /* bad argument; nothing was launched */
+    CHEM_E_PARSE = -2,          /* mechanism file syntax */
+    CHEM_E_MECH_INVALID = -3,   /* mechanism content (e.g. element balance) */
+    CHEM_E_HIP = -4,            /* HIP runtime failure */
+    CHEM_E_NOMEM = -5,          /* device allocation failed */
+    CHEM_E_CELL_FAILED = -6,    /* ran; at least one cell has a non-OK status */
+    CHEM_E_COMPILE = -7,        /* device code generation or compilation failed */
+    CHEM_E_UNSUPPORTED = -8     /* e.g. more than CHEM_MAX_SPECIES species */
+};
+
+/* Per-cell status (int32 per cell).  A failed cell keeps its last accepted
+   state; a BADINPUT cell is left untouched. */
+enum chem_cell_status {
+    CHEM_CELL_OK = 0,
+    CHEM_CELL_MAXSTEPS = 1,     /* max_substeps attempts without reaching dt */
+    CHEM_CELL_HMIN = 2,         /* step size fell below hmin_rel * dt */
+    CHEM_CELL_NONFINITE = 3,    /* reserved */
+    CHEM_CELL_BADINPUT = 4      /* T <= 0, p <= 0 or a non-finite input */
+};
+
+enum chem_form {
+    CHEM_FORM_AUTO = 0,         /* plain for a single field */
+    CHEM_FORM_PLAIN = 1,        /* one cell per lane, one launch per field */
+    CHEM_FORM_PERSISTENT = 2    /* persistent work-stealing launch in a HIP graph */
+};
+
+typedef struct {
+    int form;                   /* enum chem_form */
+    int max_substeps;           /* attempts per cell; <= 0 means 100000 */
+    double hmin_rel;            /* fail below hmin_rel * dt; <= 0 means 1e-20 */
+    const double *h0;           /* nullable device [ncell]: first trial step; else dt */
+    int checkpoint_every;       /* adjoint: accepted steps per checkpoint; <= 0 means 4 */
+    int block;                  /* persistent: lanes per workgroup (64..256); 0 = tuned */
+    int waves_per_simd;         /* persistent: resident waves per SIMD (1..2); 0 = tuned */
+    int refill;                 /* persistent: idle lanes that trigger a refill; 0 = tuned */
+} chem_options;
+
+typedef struct {
+    int64_t cells;              /* cells processed */
+    int64_t accepted;           /* accepted substeps, summed over cells */
+    int64_t rejected;           /* rejected substeps, summed over cells */
+    int64_t max_substeps;       /* largest accepted + rejected of any cell */
+    int64_t failed;             /* cells with a non-OK status */
+    double kernel_ms;           /* device time of the integration launches */
+} chem_stats;
+
+/* Read and validate a `chemmi-mech 1` file (format: NASA-7 species thermo and
+   reversible reactions; the "reactions and thermo data" of Sec. 2.1), check the
+   element balance of every reaction exactly, convert A from cm-mol-s to SI by
+   (1e-6)^(order-1) and Ea from kJ/mol, and build the device code for it
+   (generated mechanism-specific source compiled for gfx950 with hipRTC, with an
+   on-disk cache in $CHEM_KERNEL_CACHE or a kcache/ folder beside the library).
+   *out is owned by the caller until chem_free_mechanism.  Errors:
+   CHEM_E_INVAL (unreadable path), CHEM_E_PARSE, CHEM_E_MECH_INVALID,
+   CHEM_E_UNSUPPORTED, CHEM_E_COMPILE. */
+int chem_load_mechanism(const char *path, chem_mechanism **out);
+
+/* Free the handle and every device resource the library holds for it. */
+void chem_free_mechanism(chem_mechanism *m);
+
+/* Species and reaction counts. */
+int chem_mechanism_info(const chem_mechanism *m, int *n_species, int *n_reactions);
+
+/* Arrhenius parameters of each reaction's main (high-pressure) rate
+   k = A T^b exp(-Ea/RT): host arrays [n_reactions] of ln A (SI), b and Ea
+   (J/mol).  chem_set_params replaces them for every later call (the kernels
+   read them from device memory, so no recompilation happens). */
+int chem_get_params(const chem_mechanism *m, double *lnA, double *b, double *Ea);
+int chem_set_params(chem_mechanism *m, const double *lnA, const double *b, const double *Ea);
+
+/* Source terms f = dy/dt (y = (T, Y_1..Y_ns), n = ns + 1) of eqs. (20)-(21) at
+   constant p, and optionally their analytic Jacobian, at given states.
+   Device: T, p, Y (in), f[ncell * n] (out), J[ncell * n * n] (out, row-major
+   df_i/dy_j, nullable). */
+int chem_eval_source(const chem_mechanism *m, int64_t ncell, const double *T, const double *p,
+                     const double *Y, double *f, double *J, void *stream);
+
+/* One RODAS4 step of fixed size h per cell (no step-size control).  Device:
+   T, p, Y (in); ynew[ncell * n], errnorm[ncell] (the RMS error norm with the
+   given rtol, atol), ok[ncell] int32 (0 if the step matrix was singular or a
+   result not finite). */
+int chem_step_fixed(const chem_mechanism *m, int64_t ncell, const double *T, const double *p,
+                    const double *Y, double h, double rtol, double atol, double *ynew,
+                    double *errnorm, int32_t *ok, void *stream);
+
+/* Integrate every cell over [0, dt] (adaptive RODAS4).  Device: T, Y in/out;
+   p in; cell_status[ncell] (nullable, out); nacc/nrej[ncell] (nullable, out:
+   accepted and rejected substeps per cell).  opt and stats are host pointers
+   and may be NULL.  dt > 0, rtol > 0, atol >= 0 or CHEM_E_INVAL.  Returns
+   CHEM_E_CELL_FAILED when stats is given and a cell failed (without stats the
+   call does not wait for the result and returns CHEM_OK). */
+int chem_integrate(const chem_mechanism *m, int64_t ncell, double *T, const double *p,
+                   double *Y, double dt, double rtol, double atol, const chem_options *opt,
+                   chem_stats *stats, int32_t *cell_status, int32_t *nacc, int32_t *nrej,
+                   void *stream);
+
+/* Integrate nfield independent fields (e.g. the cell sets of different mesh
+   refinement levels) of sizes ncell[f] in one launch.  T, p, Y are host
+   arrays of nfield device pointers.  With CHEM_FORM_PERSISTENT (the default
+   here) one persistent work-stealing kernel processes all fields: waves pull
+   cells from per-XCD queues, steal from the others when theirs is empty, and
+   refill idle lanes at substep boundaries, so cells of very different cost
+   share the machine evenly; the launch is captured once in a HIP graph and
+   replayed.  Results are bitwise identical to chem_integrate on each field. */
+int chem_integrate_batched(const chem_mechanism *m, int nfield, double *const *T,
+                           const double *const *p, double *const *Y, const int64_t *ncell,
+                           double dt, double rtol, double atol, const chem_options *opt,
+                           chem_stats *stats, void *stream);
+
+/* Discrete adjoint of the frozen-step map y0 -> y(dt): the accepted step
+   sizes of the forward solve are held fixed and every RODAS4 step is
+   differentiated exactly.  Device inputs: T0, p, Y0 (the start state),
+   gT[ncell], gY[ncell * ns] (dL/dT_end, dL/dY_end).  Device outputs: gT0,
+   gY0 (dL/dT0, dL/dY0 per cell) and g_lnA, g_b, g_Ea [n_reactions]: dL with
+   respect to each reaction's ln A, b and Ea (J/mol), summed over cells in a
+   fixed order (deterministic).  T_end/Y_end (nullable device) receive the
+   forward result.  The forward solve stores its state every
+   opt->checkpoint_every accepted steps and recomputes in between. */
+int chem_integrate_adjoint(const chem_mechanism *m, int64_t ncell, const double *T0,
+                           const double *p, const double *Y0, double dt, double rtol,
+                           double atol, const double *gT, const double *gY, double *gT0,
+                           double *gY0, double *g_lnA, double *g_b, double *g_Ea,
+                           double *T_end, double *Y_end, const chem_options *opt,
+                           chem_stats *stats, void *stream);
+
+/* Message of the last non-zero return on this thread ("" if none). */
+const char *chem_last_error(void);
+
+/* Library version string. */
+const char *chem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEM_H */

@@ -1,0 +1,230 @@
+"""MI355X (gfx950) per-cell stiff-chemistry step.
+
+Python binding of libchemmi.so: torch supplies device memory and streams, the
+library's HIP kernels do every step of the computation.  Nothing here falls
+back to the CPU: without the built library (or without a gfx950 device) the
+calls raise.
+
+    mech = Mechanism("workloads/mech/m9.mech")
+    T, Y, stats = integrate(mech, T, p, Y, dt=5e-9, rtol=1e-8, atol=1e-12)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN
+
+__all__ = ["Mechanism", "integrate", "integrate_batched", "integrate_adjoint", "eval_source",
+           "step_fixed", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
+           "FORM_PERSISTENT", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def version() -> str:
+    return _lib.lib().chem_version().decode()
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, shape=None, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != (dtype or torch.float64):
+        raise ValueError(f"{name} must be {dtype or torch.float64}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Mechanism:
+    """A loaded mechanism (chem_load_mechanism)."""
+
+    def __init__(self, path):
+        self.path = str(path)
+        self.h = _lib.load_mechanism_handle(self.path)
+        ns, nr = C.c_int(), C.c_int()
+        _lib.check(_lib.lib().chem_mechanism_info(self.h, C.byref(ns), C.byref(nr)))
+        self.ns, self.nr = ns.value, nr.value
+        self.n = self.ns + 1
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib._lib is not None:
+            _lib._lib.chem_free_mechanism(h)
+            self.h = None
+
+    def get_params(self):
+        import numpy as np
+        a, b, e = (np.zeros(self.nr) for _ in range(3))
+        _lib.check(_lib.lib().chem_get_params(self.h, a.ctypes.data, b.ctypes.data, e.ctypes.data))
+        return a, b, e
+
+    def set_params(self, lnA, b, Ea):
+        import numpy as np
+        a, bb, e = (np.ascontiguousarray(np.asarray(x, dtype=float).reshape(self.nr)) for x in (lnA, b, Ea))
+        _lib.check(_lib.lib().chem_set_params(self.h, a.ctypes.data, bb.ctypes.data, e.ctypes.data))
+
+
+def _options(form=FORM_AUTO, max_substeps=0, hmin_rel=0.0, h0=None, checkpoint_every=0, block=0,
+             waves_per_simd=0, refill=0):
+    return _lib.Options(form, max_substeps, hmin_rel, None if h0 is None else h0.data_ptr(),
+                        checkpoint_every, block, waves_per_simd, refill)
+
+
+def integrate(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stats=True,
+              inplace=False, return_counts=False, stream=None, allow_failed=False, **opts):
+    """Advance every cell over dt.  T, p: [ncell], Y: [ncell, ns], float64 on
+    the GPU.  Returns (T_end, Y_end, stats dict or None[, status, nacc, nrej])."""
+    torch = _torch()
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    if not inplace:
+        T, Y = T.clone(), Y.clone()
+    st = nacc = nrej = None
+    if return_counts:
+        st, nacc, nrej = (torch.empty(n, dtype=torch.int32, device=T.device) for _ in range(3))
+    s = _lib.Stats() if stats else None
+    o = _options(form=form, **opts)
+    rc = _lib.lib().chem_integrate(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt), float(rtol),
+                                   float(atol), C.byref(o), C.byref(s) if s is not None else None,
+                                   _ptr(st), _ptr(nacc), _ptr(nrej), _stream(stream))
+    _lib.check(rc, allow=(-6,) if allow_failed else ())
+    out = (T, Y, s.as_dict() if s is not None else None)
+    return out + (st, nacc, nrej) if return_counts else out
+
+
+def integrate_batched(mech: Mechanism, Ts, ps, Ys, dt, rtol, atol, *, form=FORM_PERSISTENT,
+                      stats=True, stream=None, allow_failed=False, **opts):
+    """Advance several fields in one launch (in place).  Returns stats."""
+    nf = len(Ts)
+    for i in range(nf):
+        n = Ts[i].shape[0]
+        _check_tensor(Ts[i], f"T[{i}]", (n,))
+        _check_tensor(ps[i], f"p[{i}]", (n,))
+        _check_tensor(Ys[i], f"Y[{i}]", (n, mech.ns))
+    arr = C.c_void_p * max(nf, 1)
+    Tp = arr(*[t.data_ptr() for t in Ts])
+    pp = arr(*[t.data_ptr() for t in ps])
+    Yp = arr(*[t.data_ptr() for t in Ys])
+    nc = (C.c_int64 * max(nf, 1))(*[t.shape[0] for t in Ts])
+    s = _lib.Stats() if stats else None
+    o = _options(form=form, **opts)
+    rc = _lib.lib().chem_integrate_batched(mech.h, nf, Tp, pp, Yp, nc, float(dt), float(rtol),
+                                           float(atol), C.byref(o),
+                                           C.byref(s) if s is not None else None, _stream(stream))
+    _lib.check(rc, allow=(-6,) if allow_failed else ())
+    return s.as_dict() if s is not None else None
+
+
+def eval_source(mech: Mechanism, T, p, Y, jacobian=True, stream=None):
+    """Source terms f = dy/dt [ncell, n] and Jacobian [ncell, n, n] (or None)."""
+    torch = _torch()
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    f = torch.empty((n, mech.n), dtype=torch.float64, device=T.device)
+    J = torch.empty((n, mech.n, mech.n), dtype=torch.float64, device=T.device) if jacobian else None
+    _lib.check(_lib.lib().chem_eval_source(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(f), _ptr(J),
+                                           _stream(stream)))
+    return f, J
+
+
+def step_fixed(mech: Mechanism, T, p, Y, h, rtol=1e-8, atol=1e-12, stream=None):
+    """One RODAS4 step of size h: (ynew [ncell, n], errnorm [ncell], ok [ncell])."""
+    torch = _torch()
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    yn = torch.empty((n, mech.n), dtype=torch.float64, device=T.device)
+    en = torch.empty(n, dtype=torch.float64, device=T.device)
+    ok = torch.empty(n, dtype=torch.int32, device=T.device)
+    _lib.check(_lib.lib().chem_step_fixed(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), float(h), float(rtol),
+                                          float(atol), _ptr(yn), _ptr(en), _ptr(ok), _stream(stream)))
+    return yn, en, ok
+
+
+def integrate_adjoint(mech: Mechanism, T0, p, Y0, dt, rtol, atol, gT, gY, *, stats=True,
+                      stream=None, checkpoint_every=0, **opts):
+    """Discrete adjoint of the frozen-step map.  Returns
+    (gT0, gY0, g_lnA, g_b, g_Ea, T_end, Y_end, stats)."""
+    torch = _torch()
+    n = T0.shape[0]
+    for t, nm, sh in ((T0, "T0", (n,)), (p, "p", (n,)), (Y0, "Y0", (n, mech.ns)),
+                      (gT, "gT", (n,)), (gY, "gY", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    dev = T0.device
+    gT0 = torch.empty(n, dtype=torch.float64, device=dev)
+    gY0 = torch.empty((n, mech.ns), dtype=torch.float64, device=dev)
+    ga, gb, ge = (torch.empty(mech.nr, dtype=torch.float64, device=dev) for _ in range(3))
+    Te = torch.empty(n, dtype=torch.float64, device=dev)
+    Ye = torch.empty((n, mech.ns), dtype=torch.float64, device=dev)
+    s = _lib.Stats() if stats else None
+    o = _options(checkpoint_every=checkpoint_every, **opts)
+    _lib.check(_lib.lib().chem_integrate_adjoint(
+        mech.h, n, _ptr(T0), _ptr(p), _ptr(Y0), float(dt), float(rtol), float(atol), _ptr(gT),
+        _ptr(gY), _ptr(gT0), _ptr(gY0), _ptr(ga), _ptr(gb), _ptr(ge), _ptr(Te), _ptr(Ye),
+        C.byref(o), C.byref(s) if s is not None else None, _stream(stream)))
+    return gT0, gY0, ga, gb, ge, Te, Ye, (s.as_dict() if s is not None else None)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class ChemIntegrate(torch.autograd.Function):
+        """(T_end, Y_end) = step(T, Y; p, lnA, b, Ea) with the discrete adjoint
+        as backward.  lnA, b, Ea: [n_reactions] tensors (their values are
+        loaded into the mechanism before the forward)."""
+
+        @staticmethod
+        def forward(ctx, mech, T, p, Y, lnA, b, Ea, dt, rtol, atol):
+            mech.set_params(lnA.detach().cpu().numpy(), b.detach().cpu().numpy(),
+                            Ea.detach().cpu().numpy())
+            Te, Ye, _ = integrate(mech, T.detach(), p.detach(), Y.detach(), dt, rtol, atol,
+                                  stats=False)
+            ctx.mech, ctx.dt, ctx.rtol, ctx.atol = mech, dt, rtol, atol
+            ctx.save_for_backward(T.detach(), p.detach(), Y.detach())
+            ctx.params = (lnA.detach().cpu().numpy(), b.detach().cpu().numpy(), Ea.detach().cpu().numpy())
+            return Te, Ye
+
+        @staticmethod
+        def backward(ctx, gTe, gYe):
+            T, p, Y = ctx.saved_tensors
+            mech = ctx.mech
+            mech.set_params(*ctx.params)
+            gTe = torch.zeros_like(T) if gTe is None else gTe.contiguous().to(torch.float64)
+            gYe = torch.zeros_like(Y) if gYe is None else gYe.contiguous().to(torch.float64)
+            gT0, gY0, ga, gb, ge, _, _, _ = integrate_adjoint(mech, T, p, Y, ctx.dt, ctx.rtol,
+                                                              ctx.atol, gTe, gYe, stats=False)
+            return None, gT0, None, gY0, ga, gb, ge, None, None, None
+
+    return ChemIntegrate
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_autograd()
+        return getattr(_Lazy._cls, name)
+
+
+ChemIntegrate = _Lazy()

@@ -1,0 +1,278 @@
+// capi.cpp -- the C ABI (include/chem.h): argument checks, per-device state,
+// and the launches of the plain, source-term and fixed-step kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "codegen.hpp"
+#include "mechanism.hpp"
+#include "module.hpp"
+#include "runtime.hpp"
+
+using namespace chemmi;
+
+namespace {
+// a cell's state, Jacobian and LU factors live in one lane's registers
+constexpr int kMaxLaneSpecies = 20;
+}  // namespace
+
+namespace chemmi {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    if (std::getenv("CHEM_LOG")) std::fprintf(stderr, "[chem] error %d: %s\n", code, msg.c_str());
+    return code;
+}
+
+int hip_error(hipError_t e, const char* what)
+{
+    return set_error(e == hipErrorOutOfMemory ? CHEM_E_NOMEM : CHEM_E_HIP,
+                     std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
+}
+
+int check_device_ptrs(std::initializer_list<std::pair<const void*, const char*>> ptrs)
+{
+    for (auto& pr : ptrs)
+        if (!is_device_ptr(pr.first))
+            return set_error(CHEM_E_INVAL, std::string(pr.second) + " is not a device pointer");
+    return 0;
+}
+
+int check_tolerances(double dt, double rtol, double atol)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(CHEM_E_INVAL, "dt must be positive and finite");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return set_error(CHEM_E_INVAL, "rtol must be positive");
+    if (!(atol >= 0.0) || !std::isfinite(atol)) return set_error(CHEM_E_INVAL, "atol must be >= 0");
+    return 0;
+}
+
+Options resolve_options(const chem_options* o)
+{
+    Options r;
+    if (o) {
+        r.form = o->form;
+        if (o->max_substeps > 0) r.max_substeps = o->max_substeps;
+        if (o->hmin_rel > 0.0) r.hmin_rel = o->hmin_rel;
+        r.h0 = o->h0;
+        if (o->checkpoint_every > 0) r.checkpoint_every = o->checkpoint_every;
+        r.block = o->block;
+        r.waves_per_simd = o->waves_per_simd;
+        r.refill = o->refill;
+    }
+    return r;
+}
+
+}  // namespace chemmi
+
+extern "C" {
+
+const char* chem_last_error(void) { return g_last_error.c_str(); }
+
+const char* chem_version(void) { return "chemmi 0.1 (gfx950, RODAS4, FP64)"; }
+
+int chem_load_mechanism(const char* path, chem_mechanism** out)
+{
+    g_last_error.clear();
+    if (!path || !out) return set_error(CHEM_E_INVAL, "null argument");
+    *out = nullptr;
+    auto m = std::make_unique<chem_mechanism>();
+    std::string err;
+    if (int rc = parse_mechanism(path, m->data, err)) return set_error(rc, err);
+    if (m->data.ns() > kMaxLaneSpecies)
+        return set_error(CHEM_E_UNSUPPORTED, "one-cell-per-lane kernels hold at most " +
+                                                 std::to_string(kMaxLaneSpecies) + " species");
+    m->params = pack_params(m->data);
+    m->source = device_source(generate_mechanism_source(m->data));
+    if (int rc = build_code_object(m->source, m->code, err, &m->cache_file)) return set_error(rc, err);
+    *out = m.release();
+    return CHEM_OK;
+}
+
+void chem_free_mechanism(chem_mechanism* m)
+{
+    if (!m) return;
+    release_device_state(m);
+    delete m;
+}
+
+int chem_mechanism_info(const chem_mechanism* m, int* ns, int* nr)
+{
+    if (!m) return set_error(CHEM_E_INVAL, "null mechanism");
+    if (ns) *ns = m->data.ns();
+    if (nr) *nr = m->data.nr();
+    return CHEM_OK;
+}
+
+int chem_get_params(const chem_mechanism* m, double* lnA, double* b, double* Ea)
+{
+    if (!m || !lnA || !b || !Ea) return set_error(CHEM_E_INVAL, "null argument");
+    const int nr = m->data.nr();
+    for (int j = 0; j < nr; ++j) {
+        lnA[j] = m->params[j];
+        b[j] = m->params[nr + j];
+        Ea[j] = m->params[2 * nr + j] * kRu;
+    }
+    return CHEM_OK;
+}
+
+int chem_set_params(chem_mechanism* m, const double* lnA, const double* b, const double* Ea)
+{
+    if (!m || !lnA || !b || !Ea) return set_error(CHEM_E_INVAL, "null argument");
+    const int nr = m->data.nr();
+    for (int j = 0; j < nr; ++j)
+        if (!std::isfinite(lnA[j]) || !std::isfinite(b[j]) || !std::isfinite(Ea[j]))
+            return set_error(CHEM_E_INVAL, "non-finite parameter");
+    std::lock_guard<std::mutex> lk(m->mu);
+    for (int j = 0; j < nr; ++j) {
+        m->params[j] = lnA[j];
+        m->params[nr + j] = b[j];
+        m->params[2 * nr + j] = Ea[j] / kRu;
+    }
+    ++m->params_version;
+    return CHEM_OK;
+}
+
+int chem_eval_source(const chem_mechanism* mc, int64_t ncell, const double* T, const double* p,
+                     const double* Y, double* f, double* J, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {f, "f"}})) return rc;
+    if (J && !is_device_ptr(J)) return set_error(CHEM_E_INVAL, "J is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    DeviceState* d;
+    if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
+    EvalArgs a{d->par, T, p, Y, (long)ncell, f, J};
+    return launch_1d(d->f_eval, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_eval");
+}
+
+int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, const double* p,
+                    const double* Y, double h, double rtol, double atol, double* ynew,
+                    double* errnorm, int32_t* ok, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (int rc = check_tolerances(h, rtol, atol)) return rc;
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {ynew, "ynew"},
+                                    {errnorm, "errnorm"}, {ok, "ok"}}))
+        return rc;
+    std::lock_guard<std::mutex> lk(m->mu);
+    DeviceState* d;
+    if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
+    FixedStepArgs a{d->par, T, p, Y, (long)ncell, h, ynew, errnorm, rtol, atol, ok};
+    return launch_1d(d->f_fixed, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_fixed_step");
+}
+
+int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const double* p, double* Y,
+                   double dt, double rtol, double atol, const chem_options* opt, chem_stats* stats,
+                   int32_t* cell_status, int32_t* nacc, int32_t* nrej, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}})) return rc;
+    for (auto pr : {std::make_pair((const void*)cell_status, "cell_status"),
+                    std::make_pair((const void*)nacc, "nacc"), std::make_pair((const void*)nrej, "nrej")})
+        if (pr.first && !is_device_ptr(pr.first))
+            return set_error(CHEM_E_INVAL, std::string(pr.second) + " is not a device pointer");
+    Options o = resolve_options(opt);
+    if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (o.form == CHEM_FORM_PERSISTENT) {
+        FieldView fv{T, p, Y, ncell, cell_status, nacc, nrej, o.h0};
+        return run_persistent(m, &fv, 1, dt, rtol, atol, o, stats, (hipStream_t)stream);
+    }
+    return run_plain(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, nacc, nrej,
+                     (hipStream_t)stream);
+}
+
+int chem_integrate_batched(const chem_mechanism* mc, int nfield, double* const* T,
+                           const double* const* p, double* const* Y, const int64_t* ncell, double dt,
+                           double rtol, double atol, const chem_options* opt, chem_stats* stats,
+                           void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || nfield < 0 || (nfield > 0 && (!T || !p || !Y || !ncell)))
+        return set_error(CHEM_E_INVAL, "bad arguments");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    std::vector<FieldView> fields;
+    for (int f = 0; f < nfield; ++f) {
+        if (ncell[f] < 0) return set_error(CHEM_E_INVAL, "negative field size");
+        if (ncell[f] == 0) continue;
+        if (int rc = check_device_ptrs({{T[f], "T[f]"}, {p[f], "p[f]"}, {Y[f], "Y[f]"}})) return rc;
+        fields.push_back(FieldView{T[f], p[f], Y[f], ncell[f], nullptr, nullptr, nullptr, nullptr});
+    }
+    if (fields.empty()) return CHEM_OK;
+    Options o = resolve_options(opt);
+    if (o.h0) return set_error(CHEM_E_INVAL, "h0 is per field; not supported by the batched call");
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (o.form == CHEM_FORM_PLAIN) {
+        chem_stats total{};
+        for (auto& fv : fields) {
+            chem_stats s{};
+            int rc = run_plain(m, fv.ncell, fv.T, fv.p, fv.Y, dt, rtol, atol, o, stats ? &s : nullptr,
+                               nullptr, nullptr, nullptr, (hipStream_t)stream);
+            if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+            total.cells += s.cells;
+            total.accepted += s.accepted;
+            total.rejected += s.rejected;
+            total.failed += s.failed;
+            total.max_substeps = std::max(total.max_substeps, s.max_substeps);
+            total.kernel_ms += s.kernel_ms;
+        }
+        if (stats) {
+            *stats = total;
+            if (total.failed) return set_error(CHEM_E_CELL_FAILED, "some cells failed");
+        }
+        return CHEM_OK;
+    }
+    return run_persistent(m, fields.data(), (int)fields.size(), dt, rtol, atol, o, stats,
+                          (hipStream_t)stream);
+}
+
+int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double* T0, const double* p,
+                           const double* Y0, double dt, double rtol, double atol, const double* gT,
+                           const double* gY, double* gT0, double* gY0, double* g_lnA, double* g_b,
+                           double* g_Ea, double* T_end, double* Y_end, const chem_options* opt,
+                           chem_stats* stats, void* stream)
+{
+    g_last_error.clear();
+    (void)mc; (void)ncell; (void)T0; (void)p; (void)Y0; (void)dt; (void)rtol; (void)atol; (void)gT;
+    (void)gY; (void)gT0; (void)gY0; (void)g_lnA; (void)g_b; (void)g_Ea; (void)T_end; (void)Y_end;
+    (void)opt; (void)stats; (void)stream;
+    return set_error(CHEM_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

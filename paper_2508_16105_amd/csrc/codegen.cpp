@@ -1,0 +1,355 @@
+// codegen.cpp -- emits the mechanism-specific device code (namespace mech):
+// NASA-7 thermo, modified-Arrhenius forward rates, equilibrium-constant
+// reverse rates, third-body and Lindemann/Troe falloff, the constant-pressure
+// source terms (species production rates and heat release, Appendix A
+// eqs. (20)-(21)) and their analytic Jacobian, all as straight-line code with
+// compile-time species indices so each lane keeps its cell in registers.
+//
+// The Arrhenius parameters (ln A, b, Ea/R) are read from a device buffer so
+// they can change without recompiling; every other constant is a literal.
+#include "codegen.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <sstream>
+
+namespace chemmi {
+namespace {
+
+std::string lit(double v)
+{
+    char buf[40];
+    std::snprintf(buf, sizeof buf, "%.17g", v);
+    std::string s(buf);
+    if (s.find_first_of(".eEn") == std::string::npos) s += ".0";
+    return s;
+}
+
+// C[k] written as a product term for stoichiometric coefficient nu
+std::string powc(int k, int nu)
+{
+    std::string s = "C[" + std::to_string(k) + "]";
+    std::string r = s;
+    for (int i = 1; i < nu; ++i) r += "*" + s;
+    return r;
+}
+
+// product of C^nu over a side, optionally skipping one occurrence of species `skip`
+// (the derivative of C_m^nu is nu C_m^(nu-1))
+std::string side_product(const std::vector<Term>& side, int dsp = -1)
+{
+    std::string r;
+    bool hit = false;
+    for (const auto& t : side) {
+        int nu = t.nu;
+        std::string factor;
+        if (t.sp == dsp) {
+            hit = true;
+            if (nu > 1) factor = lit((double)nu) + (nu - 1 > 0 ? "*" + powc(t.sp, nu - 1) : "");
+            else factor = "1.0";
+        } else {
+            factor = powc(t.sp, nu);
+        }
+        r += (r.empty() ? "" : "*") + factor;
+    }
+    if (dsp >= 0 && !hit) return "";
+    return r.empty() ? "1.0" : r;
+}
+
+struct Emitter {
+    const MechanismData& m;
+    std::ostringstream o;
+    int ns, nr;
+
+    explicit Emitter(const MechanismData& mm) : m(mm), ns(mm.ns()), nr(mm.nr()) {}
+
+    void thermo(bool with_dcp)
+    {
+        // group species by T_mid: one branch per group
+        std::vector<double> tmids;
+        for (auto& s : m.species) {
+            bool seen = false;
+            for (double t : tmids) seen = seen || t == s.tmid;
+            if (!seen) tmids.push_back(s.tmid);
+        }
+        for (double tm : tmids) {
+            for (int half = 0; half < 2; ++half) {
+                o << (half == 0 ? "  if (T < " + lit(tm) + ") {\n" : "  } else {\n");
+                for (int k = 0; k < ns; ++k) {
+                    const auto& s = m.species[k];
+                    if (s.tmid != tm) continue;
+                    const double* a = half == 0 ? s.lo : s.hi;
+                    o << "    cpR[" << k << "] = " << lit(a[0]) << " + T*(" << lit(a[1]) << " + T*("
+                      << lit(a[2]) << " + T*(" << lit(a[3]) << " + T*" << lit(a[4]) << ")));\n";
+                    o << "    HRT[" << k << "] = " << lit(a[0]) << " + T*(" << lit(a[1] / 2) << " + T*("
+                      << lit(a[2] / 3) << " + T*(" << lit(a[3] / 4) << " + T*" << lit(a[4] / 5)
+                      << "))) + " << lit(a[5]) << "*iT;\n";
+                    // G = S/R - H/RT
+                    o << "    G[" << k << "] = " << lit(a[0]) << "*(lnT - 1.0) + T*(" << lit(a[1] / 2)
+                      << " + T*(" << lit(a[2] / 6) << " + T*(" << lit(a[3] / 12) << " + T*"
+                      << lit(a[4] / 20) << "))) + (" << lit(a[6]) << " - " << lit(a[5]) << "*iT);\n";
+                    if (with_dcp)
+                        o << "    dcpR[" << k << "] = " << lit(a[1]) << " + T*(" << lit(2 * a[2])
+                          << " + T*(" << lit(3 * a[3]) << " + T*" << lit(4 * a[4]) << "));\n";
+                }
+            }
+            o << "  }\n";
+        }
+    }
+
+    // state common to rhs and rhs_jac
+    void prologue(bool jac)
+    {
+        o << "  const double T = y[0];\n"
+             "  const double lnT = log(T);\n"
+             "  const double iT = 1.0 / T;\n"
+             "  double cpR[NS], HRT[NS], G[NS];\n";
+        if (jac) o << "  double dcpR[NS];\n";
+        thermo(jac);
+        o << "  double sig = 0.0;\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  sig = fma(y[" << 1 + k << "], " << lit(1.0 / m.species[k].W) << ", sig);\n";
+        o << "  const double Wbar = 1.0 / sig;\n"
+             "  const double rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
+             "  const double ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
+             "  double C[NS];\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  C[" << k << "] = rho * (y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W) << ");\n";
+        o << "  const double lnPRT = " << lit(std::log(kPatm / kRu)) << " - lnT;\n"
+             "  double wd[NS];\n"
+             "#pragma unroll\n  for (int k = 0; k < NS; ++k) wd[k] = 0.0;\n";
+    }
+
+    std::string third_body_sum(const ReactionData& r)
+    {
+        std::string s = "ctot";
+        for (int k = 0; k < ns; ++k)
+            if (r.eff[k] != 1.0) s += " + " + lit(r.eff[k] - 1.0) + "*C[" + std::to_string(k) + "]";
+        return s;
+    }
+
+    void reaction(int j, bool jac)
+    {
+        const auto& r = m.reactions[j];
+        o << "  { // reaction " << j << "\n";
+        o << "    const double lnk = par[" << j << "] + par[" << nr + j << "]*lnT - par[" << 2 * nr + j
+          << "]*iT;\n";
+        // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
+        std::string lnkc;
+        for (auto& t : r.prod) lnkc += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
+        for (auto& t : r.reac) lnkc += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
+        if (r.dnu != 0) lnkc += " + " + lit(r.dnu) + "*lnPRT";
+        o << "    const double lnKc = 0.0" << lnkc << ";\n";
+        const bool falloff = r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe;
+        if (r.kind != RxnKind::Elementary) o << "    const double Mc = " << third_body_sum(r) << ";\n";
+        if (!falloff) {
+            o << "    const double kf = exp(lnk);\n"
+                 "    const double kr = exp(lnk - lnKc);\n";
+        } else {
+            // P_r = k0 [M] / k_inf, one exponential for the ratio
+            o << "    const double kinf = exp(lnk);\n"
+                 "    const double lnr0 = " << lit(r.lnA0) << " + " << lit(r.b0) << "*lnT - "
+              << lit(r.EaR0) << "*iT - lnk;\n"
+                 "    const double r0 = exp(lnr0);\n"
+                 "    const double Pr = r0 * Mc;\n"
+                 "    const bool floored = !(Pr >= 1e-300);\n"
+                 "    const double logPr = floored ? -300.0 : log10(Pr);\n";
+            if (r.kind == RxnKind::Troe) {
+                o << "    const double e3 = exp(-T * " << lit(1.0 / r.T3) << ");\n"
+                     "    const double e1 = exp(-T * " << lit(1.0 / r.T1) << ");\n";
+                o << "    double Fc = " << lit(1.0 - r.alpha) << "*e3 + " << lit(r.alpha) << "*e1;\n";
+                if (jac)
+                    o << "    double dFc = " << lit(-(1.0 - r.alpha) / r.T3) << "*e3 + "
+                      << lit(-r.alpha / r.T1) << "*e1;\n";
+                if (r.has_T2) {
+                    o << "    const double e2 = exp(" << lit(-r.T2) << " * iT);\n"
+                         "    Fc += e2;\n";
+                    if (jac) o << "    dFc += " << lit(r.T2) << "*iT*iT*e2;\n";
+                }
+                o << "    const double logFc = log10(Fc);\n"
+                     "    const double tc = -0.4 - 0.67*logFc;\n"
+                     "    const double tn = 0.75 - 1.27*logFc;\n"
+                     "    const double tu = logPr + tc;\n"
+                     "    const double tden = tn - 0.14*tu;\n"
+                     "    const double tx = tu / tden;\n"
+                     "    const double opx2 = 1.0 + tx*tx;\n"
+                     "    const double logF = logFc / opx2;\n"
+                     "    const double Fb = exp(" << lit(std::log(10.0)) << " * logF);\n";
+                if (jac) {
+                    o << "    const double tg = -logFc * 2.0 * tx / (opx2*opx2);\n"
+                         "    const double dF_dPr = floored ? 0.0 : tg * tn / (tden*tden);\n"
+                         "    const double dF_dFc = 1.0/opx2 + tg * (-0.67*tn + 1.27*tu) / (tden*tden);\n"
+                         "    const double dlogFc_dT = dFc / (Fc * " << lit(std::log(10.0)) << ");\n";
+                }
+            } else {
+                o << "    const double Fb = 1.0;\n";
+                if (jac) o << "    const double dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
+            }
+            o << "    const double ipr1 = 1.0 / (1.0 + Pr);\n"
+                 "    const double kf = kinf * Pr * ipr1 * Fb;\n"
+                 "    const double iKc = exp(-lnKc);\n"
+                 "    const double kr = kf * iKc;\n";
+        }
+        o << "    const double pf = " << side_product(r.reac) << ";\n"
+             "    const double pr = " << side_product(r.prod) << ";\n"
+             "    const double fwd = kf * pf;\n"
+             "    const double rev = kr * pr;\n";
+        if (r.kind == RxnKind::ThirdBody) o << "    const double q = Mc * (fwd - rev);\n";
+        else o << "    const double q = fwd - rev;\n";
+        // production rates
+        std::vector<int> nu(ns, 0);
+        for (auto& t : r.reac) nu[t.sp] -= t.nu;
+        for (auto& t : r.prod) nu[t.sp] += t.nu;
+        for (int k = 0; k < ns; ++k)
+            if (nu[k]) o << "    wd[" << k << "] = fma(" << lit(nu[k]) << ", q, wd[" << k << "]);\n";
+        if (jac) {
+            // d ln k_f / dT at fixed [M]; d ln K_c / dT = (sum nu H/RT - dnu) / T
+            std::string sh;
+            for (auto& t : r.prod) sh += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
+            for (auto& t : r.reac) sh += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
+            o << "    const double dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
+            o << "    const double dlnkinf = (par[" << nr + j << "] + par[" << 2 * nr + j << "]*iT) * iT;\n";
+            if (!falloff) {
+                o << "    const double dlnkf = dlnkinf;\n";
+            } else {
+                o << "    const double dlnk0 = (" << lit(r.b0) << " + " << lit(r.EaR0) << "*iT) * iT;\n"
+                     "    const double dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + "
+                  << lit(std::log(10.0)) << " * dF_dFc * dlogFc_dT;\n"
+                     "    const double dkdM = kinf * r0 * Fb * (ipr1*ipr1 + dF_dPr*ipr1);\n";
+            }
+            std::string fac = r.kind == RxnKind::ThirdBody ? "Mc * " : "";
+            o << "    const double dqT = " << fac << "(dlnkf * fwd - (dlnkf - dlnKc) * rev);\n";
+            // d q / d C_m (dense over the species that enter)
+            std::vector<std::string> dq(ns);
+            for (int mm = 0; mm < ns; ++mm) {
+                std::string t;
+                std::string a = side_product(r.reac, mm);
+                std::string b = side_product(r.prod, mm);
+                if (!a.empty()) t += "kf*(" + a + ")";
+                if (!b.empty()) t += (t.empty() ? "-" : " - ") + std::string("kr*(") + b + ")";
+                if (!t.empty() && r.kind == RxnKind::ThirdBody) t = "Mc*(" + t + ")";
+                if (r.kind == RxnKind::ThirdBody && r.eff[mm] != 0.0)
+                    t += (t.empty() ? "" : " + ") + lit(r.eff[mm]) + "*(fwd - rev)";
+                if (falloff && r.eff[mm] != 0.0)
+                    t += (t.empty() ? "" : " + ") + lit(r.eff[mm]) + "*dMterm";
+                dq[mm] = t;
+            }
+            // k_r = k_f / K_c, so both directions scale with d k_f / d[M]
+            if (falloff) o << "    const double dMterm = dkdM*(pf - iKc*pr);\n";
+            for (int mm = 0; mm < ns; ++mm)
+                if (!dq[mm].empty()) o << "    const double dq" << mm << " = " << dq[mm] << ";\n";
+            for (int k = 0; k < ns; ++k) {
+                if (!nu[k]) continue;
+                for (int mm = 0; mm < ns; ++mm)
+                    if (!dq[mm].empty())
+                        o << "    J[" << 1 + k << "][" << 1 + mm << "] = fma(" << lit(nu[k]) << ", dq" << mm
+                          << ", J[" << 1 + k << "][" << 1 + mm << "]);\n";
+                o << "    J[" << 1 + k << "][0] = fma(" << lit(nu[k]) << ", dqT, J[" << 1 + k << "][0]);\n";
+            }
+        }
+        o << "  }\n";
+    }
+
+    void rhs_tail()
+    {
+        o << "  const double rcpinv = 1.0 / (rho * cp);\n";
+        o << "  double hw = 0.0;\n";
+        for (int k = 0; k < ns; ++k) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
+        o << "  const double irho = 1.0 / rho;\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  f[" << 1 + k << "] = " << lit(m.species[k].W) << " * irho * wd[" << k << "];\n";
+        o << "  f[0] = -" << lit(kRu) << " * T * hw * rcpinv;\n";
+    }
+
+    void cp_sum(bool jac)
+    {
+        o << "  double cpm = 0.0;\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  cpm = fma(cpR[" << k << "], y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W) << ", cpm);\n";
+        o << "  const double cp = " << lit(kRu) << " * cpm;\n";
+        if (jac) {
+            o << "  double dcpm = 0.0;\n";
+            for (int k = 0; k < ns; ++k)
+                o << "  dcpm = fma(dcpR[" << k << "], y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W)
+                  << ", dcpm);\n";
+            o << "  const double dcp = " << lit(kRu) << " * dcpm;\n";
+        }
+    }
+
+    void chain_rule()
+    {
+        // J holds Jc_km = d wdot_k / d C_m (at fixed T) in its species block and
+        // wT_k = d wdot_k / dT (at fixed C) in column 0 of the species rows.
+        // With S_k = sum_l Jc_kl C_l:
+        //   J_km = (W_k/W_m) Jc_km + (Wbar/W_m)(f_k - W_k S_k / rho)
+        //   J_k0 = (W_k / rho)(wT_k - S_k / T) + f_k / T
+        //   J_0m = -R T (rho HJ_m - Wbar HS) / (W_m rho cp) - f_T (cp_m / cp - Wbar / W_m)
+        //   J_00 = -R (cpw + T HwT - HS) / (rho cp) - f_T (dcp / cp - 1/T)
+        // where HJ_m = sum_k H_k/RT Jc_km, HS = sum_k H_k/RT S_k, HwT = sum_k H_k/RT wT_k,
+        // cpw = sum_k cp_k/R wdot_k.
+        o << "  double Sk[NS];\n";
+        for (int k = 0; k < ns; ++k) {
+            o << "  Sk[" << k << "] = 0.0";
+            for (int l = 0; l < ns; ++l) o << " + J[" << 1 + k << "][" << 1 + l << "]*C[" << l << "]";
+            o << ";\n";
+        }
+        o << "  double HS = 0.0, HwT = 0.0, cpw = 0.0;\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  HS = fma(HRT[" << k << "], Sk[" << k << "], HS); HwT = fma(HRT[" << k << "], J[" << 1 + k
+              << "][0], HwT); cpw = fma(cpR[" << k << "], wd[" << k << "], cpw);\n";
+        o << "  const double fT = f[0];\n"
+             "  const double RT = " << lit(kRu) << " * T;\n"
+             "  const double icp = 1.0 / cp;\n";
+        for (int mm = 0; mm < ns; ++mm) {
+            o << "  { double HJ = 0.0";
+            for (int k = 0; k < ns; ++k) o << " + HRT[" << k << "]*J[" << 1 + k << "][" << 1 + mm << "]";
+            o << ";\n    J[0][" << 1 + mm << "] = -RT * (rho*HJ - Wbar*HS) * " << lit(1.0 / m.species[mm].W)
+              << " * rcpinv - fT * (cpR[" << mm << "] * " << lit(kRu / m.species[mm].W) << " * icp - Wbar * "
+              << lit(1.0 / m.species[mm].W) << "); }\n";
+        }
+        o << "  J[0][0] = -" << lit(kRu) << " * (cpw + T*HwT - HS) * rcpinv - fT * (dcp * icp - iT);\n";
+        for (int k = 0; k < ns; ++k) {
+            const double Wk = m.species[k].W;
+            o << "  { const double g = f[" << 1 + k << "] - " << lit(Wk) << " * Sk[" << k << "] * irho;\n";
+            for (int mm = 0; mm < ns; ++mm)
+                o << "    J[" << 1 + k << "][" << 1 + mm << "] = " << lit(Wk / m.species[mm].W) << " * J["
+                  << 1 + k << "][" << 1 + mm << "] + Wbar * " << lit(1.0 / m.species[mm].W) << " * g;\n";
+            o << "    J[" << 1 + k << "][0] = " << lit(Wk) << " * irho * (J[" << 1 + k << "][0] - Sk[" << k
+              << "] * iT) + f[" << 1 + k << "] * iT; }\n";
+        }
+    }
+
+    std::string run()
+    {
+        o << "// generated mechanism code: " << m.name << " (" << ns << " species, " << nr << " reactions)\n"
+          << "namespace mech {\n"
+          << "constexpr int NS = " << ns << ";\n"
+          << "constexpr int NR = " << nr << ";\n"
+          << "constexpr int N = NS + 1;\n\n";
+        // source terms only
+        o << "__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, "
+             "const double (&y)[N], double (&f)[N])\n{\n";
+        prologue(false);
+        for (int j = 0; j < nr; ++j) reaction(j, false);
+        cp_sum(false);
+        rhs_tail();
+        o << "}\n\n";
+        // source terms and Jacobian
+        o << "__device__ __forceinline__ void rhs_jac(const double* __restrict__ par, double p, "
+             "const double (&y)[N], double (&f)[N], double (&J)[N][N])\n{\n";
+        o << "#pragma unroll\n  for (int i = 0; i < N; ++i)\n#pragma unroll\n    for (int j = 0; j < N; ++j) J[i][j] = 0.0;\n";
+        prologue(true);
+        for (int j = 0; j < nr; ++j) reaction(j, true);
+        cp_sum(true);
+        rhs_tail();
+        chain_rule();
+        o << "}\n\n}  // namespace mech\n";
+        return o.str();
+    }
+};
+
+}  // namespace
+
+std::string generate_mechanism_source(const MechanismData& m) { return Emitter(m).run(); }
+
+}  // namespace chemmi

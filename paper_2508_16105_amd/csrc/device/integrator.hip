@@ -1,0 +1,523 @@
+// integrator.hip -- device side of the chemistry step for CDNA4 (gfx950).
+//
+// Compiled at mechanism-load time together with the mechanism-specific code
+// (namespace mech: sizes, thermo, source terms and analytic Jacobian with
+// every species index a compile-time constant), so one cell's state, its
+// Jacobian and LU factors live in the registers of one lane.
+//
+// Contents: dense LU with partial pivoting, the RODAS4 Rosenbrock step
+// (Hairer & Wanner, Solving ODEs II, Sec. IV.7 / VI.4), the step-size
+// controller, and the kernels (plain one-cell-per-lane, persistent
+// work-stealing with lane refill, fixed-step and source-term evaluation).
+//
+// The per-cell problem is the species/energy source of the governing
+// equations (Appendix A, eqs. (20)-(21)) at constant pressure over one flow
+// step dt, cell by cell.
+
+namespace chem {
+
+constexpr int N = mech::N;
+constexpr int NS = mech::NS;
+
+// ---- RODAS4 in the transformed variables u_i ----
+struct Rodas4 {
+    static constexpr int S = 6;
+    static constexpr double gamma = 0.25;
+};
+__device__ constexpr double RA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.544, 0, 0, 0, 0},
+    {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
+    {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.687886036105895, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.687886036105895, 1.0}};
+__device__ constexpr double RC[6][5] = {
+    {0, 0, 0, 0, 0},
+    {-5.6688, 0, 0, 0, 0},
+    {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
+    {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
+    {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.7089089320616, 0},
+    {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+     -6.058818238834054}};
+// y_new = y + sum_i m_i u_i with m = (a_51, a_52, a_53, a_54, 1, 1): the stage-6
+// argument plus u_6 (stiffly accurate); the error estimate is u_6.
+
+enum : int { CELL_OK = 0, CELL_MAXSTEPS = 1, CELL_HMIN = 2, CELL_NONFINITE = 3, CELL_BADINPUT = 4 };
+
+struct StepArgs {
+    double dt, rtol, atol, hmin;
+    int max_substeps;
+};
+
+// ---- dense LU with partial pivoting, one matrix per lane ----
+// Row interchanges are made with selects (the pivot row differs per lane), on
+// the trailing columns only; piv[k] records the row swapped into k at step k
+// (LINPACK order), and the solve replays the swaps step by step.
+__device__ __forceinline__ bool lu_factor(double (&A)[N][N], int (&piv)[N])
+{
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double amax = fabs(A[k][k]);
+        int p = k;
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const double v = fabs(A[i][k]);
+            const bool c = v > amax;
+            amax = c ? v : amax;
+            p = c ? i : p;
+        }
+        piv[k] = p;
+        ok = ok && (amax > 0.0);
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const bool s = (p == i);
+#pragma unroll
+            for (int j = k; j < N; ++j) {
+                const double akj = A[k][j], aij = A[i][j];
+                A[k][j] = s ? aij : akj;
+                A[i][j] = s ? akj : aij;
+            }
+        }
+        const double rp = 1.0 / A[k][k];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const double l = A[i][k] * rp;
+            A[i][k] = l;
+#pragma unroll
+            for (int j = k + 1; j < N; ++j) A[i][j] = fma(-l, A[k][j], A[i][j]);
+        }
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], double (&b)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int p = piv[k];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const bool s = (p == i);
+            const double bk = b[k], bi = b[i];
+            b[k] = s ? bi : bk;
+            b[i] = s ? bk : bi;
+        }
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) b[i] = fma(-A[i][k], b[k], b[i]);
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        double v = b[i];
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) v = fma(-A[i][j], b[j], v);
+        b[i] = v / A[i][i];
+    }
+}
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+// One RODAS4 step from y with step h.  Returns false if the step matrix is
+// singular or anything is not finite; otherwise ynew and the RMS error norm.
+__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p,
+                                         const double (&y)[N], double h, double rtol,
+                                         double atol, double (&ynew)[N], double& errn)
+{
+    double M[N][N], f[N];
+    mech::rhs_jac(par, p, y, f, M);
+    const double ghinv = 1.0 / (h * Rodas4::gamma);
+    const double hinv = 1.0 / h;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) M[i][j] = -M[i][j];
+        M[i][i] += ghinv;
+    }
+    int piv[N];
+    bool ok = lu_factor(M, piv);
+
+    double u[Rodas4::S][N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) u[0][k] = f[k];
+    lu_solve(M, piv, u[0]);
+#pragma unroll
+    for (int s = 1; s < Rodas4::S; ++s) {
+        double Ys[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double v = y[k];
+#pragma unroll
+            for (int j = 0; j < s; ++j) v = fma(RA[s][j], u[j][k], v);
+            Ys[k] = v;
+        }
+        if (s == Rodas4::S - 1) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) ynew[k] = Ys[k];     // stiffly accurate: y_new = Y_6 + u_6
+        }
+        double fs[N];
+        mech::rhs(par, p, Ys, fs);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double v = fs[k];
+#pragma unroll
+            for (int j = 0; j < s; ++j) v = fma(RC[s][j] * hinv, u[j][k], v);
+            u[s][k] = v;
+        }
+        lu_solve(M, piv, u[s]);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        ynew[k] += u[Rodas4::S - 1][k];
+        const double sc = atol + rtol * fmax(fabs(y[k]), fabs(ynew[k]));
+        const double e = u[Rodas4::S - 1][k] / sc;
+        acc = fma(e, e, acc);
+        ok = ok && finite(ynew[k]);
+    }
+    errn = sqrt(acc * (1.0 / N));
+    return ok && finite(errn);
+}
+
+// Per-lane integration state.
+struct Cell {
+    double y[N];
+    double p, t, h;
+    int nacc, nrej, status;
+    bool rej_last, done;
+};
+
+__device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const double* __restrict__ Y,
+                                           long stride, double h0)
+{
+    c.y[0] = T;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) c.y[1 + k] = Y[k * stride];
+    c.p = p;
+    c.t = 0.0;
+    c.h = h0;
+    c.nacc = 0;
+    c.nrej = 0;
+    c.rej_last = false;
+    bool bad = !(T > 0.0) || !(p > 0.0) || !finite(p);
+#pragma unroll
+    for (int k = 0; k < N; ++k) bad = bad || !finite(c.y[k]);
+    c.status = bad ? CELL_BADINPUT : CELL_OK;
+    c.done = bad;
+}
+
+// One attempted substep (accepted or rejected), with the controller:
+// accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
+// a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)
+// or 0.2; the final step is truncated to land on dt.
+__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a)
+{
+    if (c.done) return;
+    if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return; }
+    if (c.h < a.hmin) { c.status = CELL_HMIN; c.done = true; return; }
+    bool last = false;
+    double h = c.h;
+    if (h >= a.dt - c.t) { h = a.dt - c.t; last = true; }
+    double ynew[N], en;
+    const bool ok = ros_step(par, c.p, c.y, h, a.rtol, a.atol, ynew, en);
+    if (ok && en <= 1.0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) c.y[k] = ynew[k];
+        c.t = last ? a.dt : c.t + h;
+        double fac = 0.9 * pow(fmax(en, 1e-16), -0.25);
+        fac = fmin(6.0, fmax(0.2, fac));
+        if (c.rej_last) fac = fmin(1.0, fac);
+        c.h = h * fac;
+        c.rej_last = false;
+        ++c.nacc;
+        if (last) c.done = true;
+    } else {
+        ++c.nrej;
+        c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
+        c.rej_last = true;
+    }
+}
+
+struct IntegrateArgs {
+    const double* par;
+    double* T;
+    const double* p;
+    double* Y;
+    long ncell;
+    const double* h0;          // nullable: per-cell first step, else dt
+    int* status;
+    int* nacc;
+    int* nrej;
+    StepArgs step;
+};
+
+__device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T, double* __restrict__ Y,
+                                           long cell, int* status, int* nacc, int* nrej)
+{
+    if (c.status != CELL_BADINPUT) {
+        T[cell] = c.y[0];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Y[cell * NS + k] = c.y[1 + k];
+    }
+    status[cell] = c.status;
+    nacc[cell] = c.nacc;
+    nrej[cell] = c.nrej;
+}
+
+}  // namespace chem
+
+// ---- plain form: one cell per lane, cells in index order ----
+extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateArgs a)
+{
+    using namespace chem;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    Cell c;
+    cell_begin(c, a.T[cell], a.p[cell], a.Y + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
+    while (!c.done) cell_attempt(c, a.par, a.step);
+    cell_store(c, a.T, a.Y, cell, a.status, a.nacc, a.nrej);
+}
+
+// ---- source terms and Jacobian at given states (no integration) ----
+struct EvalArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double* f;      // [ncell][N]
+    double* J;      // [ncell][N][N] or null
+};
+
+extern "C" __global__ void __launch_bounds__(64, 1) chem_eval(EvalArgs a)
+{
+    using namespace chem;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    double y[N], f[N];
+    y[0] = a.T[cell];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) y[1 + k] = a.Y[cell * NS + k];
+    if (a.J) {
+        double J[N][N];
+        mech::rhs_jac(a.par, a.p[cell], y, f, J);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) a.J[(cell * N + i) * N + j] = J[i][j];
+    } else {
+        mech::rhs(a.par, a.p[cell], y, f);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) a.f[cell * N + i] = f[i];
+}
+
+// ---- one fixed step of size h per cell (y_new and the error vector) ----
+struct FixedStepArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double h;
+    double* ynew;   // [ncell][N]
+    double* err;    // [ncell] RMS norm with rtol = 1, atol = 0 ... see host
+    double rtol, atol;
+    int* ok;
+};
+
+extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArgs a)
+{
+    using namespace chem;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    double y[N], yn[N], en;
+    y[0] = a.T[cell];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) y[1 + k] = a.Y[cell * NS + k];
+    const bool ok = ros_step(a.par, a.p[cell], y, a.h, a.rtol, a.atol, yn, en);
+#pragma unroll
+    for (int k = 0; k < N; ++k) a.ynew[cell * N + k] = yn[k];
+    a.err[cell] = en;
+    a.ok[cell] = ok ? 1 : 0;
+}
+
+// ---- counters: sums of accepted / rejected substeps, failed cells, max attempts ----
+extern "C" __global__ void __launch_bounds__(256) chem_zero_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+extern "C" __global__ void __launch_bounds__(256) chem_reduce_stats(const int* __restrict__ status,
+                                                                    const int* __restrict__ nacc,
+                                                                    const int* __restrict__ nrej,
+                                                                    long ncell,
+                                                                    unsigned long long* __restrict__ out)
+{
+    unsigned long long acc = 0, rej = 0, fail = 0, mx = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (long)gridDim.x * blockDim.x) {
+        const int a = nacc[i], r = nrej[i];
+        acc += (unsigned long long)a;
+        rej += (unsigned long long)r;
+        fail += status[i] != 0 ? 1ull : 0ull;
+        const unsigned long long t = (unsigned long long)(a + r);
+        mx = t > mx ? t : mx;
+    }
+    __shared__ unsigned long long s[4][256];
+    s[0][threadIdx.x] = acc;
+    s[1][threadIdx.x] = rej;
+    s[2][threadIdx.x] = fail;
+    s[3][threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+            s[2][threadIdx.x] += s[2][threadIdx.x + w];
+            s[3][threadIdx.x] = s[3][threadIdx.x] > s[3][threadIdx.x + w] ? s[3][threadIdx.x] : s[3][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], s[0][0]);
+        atomicAdd(&out[1], s[1][0]);
+        atomicAdd(&out[2], s[2][0]);
+        atomicMax(&out[3], s[3][0]);
+    }
+}
+
+// ---- persistent form ----
+// Cells of all fields form one global index space [0, total), split into nq
+// contiguous queues (one per XCD).  Each wave pulls cells from the queue of
+// its XCD (workgroups are dealt to the XCDs round-robin), moves on to the
+// next queue when its own is empty, and refills idle lanes at substep
+// boundaries, so a lane never waits for the slowest cell of its wave.
+struct FieldDesc {
+    double* T;
+    const double* p;
+    double* Y;
+    int* status;
+    int* nacc;
+    int* nrej;
+    long ncell;
+    long start;               // first global index of this field
+};
+
+struct PersistBlock {
+    long total;
+    long qchunk;              // cells per queue
+    int nfield;
+    int nq;
+    int refill;               // idle lanes that trigger a refill
+    int pad;
+    chem::StepArgs step;
+    FieldDesc fields[1];      // nfield entries
+};
+
+extern "C" __global__ void chem_reset_heads(unsigned long long* heads, int nq)
+{
+    const int i = threadIdx.x;
+    if (i < nq) heads[i] = 0ull;
+}
+
+template <int WAVES_PER_SIMD>
+__device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__ blk,
+                                                unsigned long long* __restrict__ heads,
+                                                const double* __restrict__ par)
+{
+    using namespace chem;
+    const int lane = threadIdx.x & 63;
+    const long total = blk->total;
+    const long qchunk = blk->qchunk;
+    const int nq = blk->nq;
+    const int nfield = blk->nfield;
+    const int refill = blk->refill;
+    const StepArgs step = blk->step;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    int q = (int)(blockIdx.x % (unsigned)nq);     // home queue: this workgroup's XCD
+    int tried = 0;
+    bool exhausted = false;
+    bool have = false;
+    int fidx = 0;
+    long local = 0;
+    Cell c;
+    c.done = true;
+
+    while (true) {
+        const unsigned long long idle = __ballot(!have);
+        const int nidle = __popcll(idle);
+        if (!exhausted && (nidle >= refill || nidle == 64)) {
+            int need = nidle;
+            int assigned = 0;
+            const int rank = __popcll(idle & below);
+            long my_g = -1;
+            while (need > 0 && !exhausted) {
+                const int leader = __ffsll((long long)idle) - 1;
+                unsigned long long old = 0;
+                if (lane == leader) old = atomicAdd(&heads[q], (unsigned long long)need);
+                old = __shfl(old, leader);
+                const long qbeg = (long)q * qchunk;
+                const long qsize = (total - qbeg < qchunk) ? total - qbeg : qchunk;
+                const long avail = qsize - (long)old;
+                const int got = avail <= 0 ? 0 : (avail < (long)need ? (int)avail : need);
+                if (!have && rank >= assigned && rank < assigned + got)
+                    my_g = qbeg + (long)old + (rank - assigned);
+                assigned += got;
+                if (got < need) {
+                    q = (q + 1 == nq) ? 0 : q + 1;
+                    if (++tried >= nq) exhausted = true;
+                }
+                need -= got;
+            }
+            if (my_g >= 0) {
+                int f = 0;
+                while (f + 1 < nfield && blk->fields[f + 1].start <= my_g) ++f;
+                fidx = f;
+                const FieldDesc& fd = blk->fields[f];
+                local = my_g - fd.start;
+                cell_begin(c, fd.T[local], fd.p[local], fd.Y + local * NS, 1, step.dt);
+                have = true;
+            }
+        }
+        if (!__any(have)) {
+            if (exhausted) break;
+            continue;
+        }
+        if (have) {
+            cell_attempt(c, par, step);
+            if (c.done) {
+                const FieldDesc& fd = blk->fields[fidx];
+                cell_store(c, fd.T, fd.Y, local, fd.status, fd.nacc, fd.nrej);
+                have = false;
+            }
+        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(256, 1)
+chem_persistent(const PersistBlock* __restrict__ blk, unsigned long long* __restrict__ heads,
+                const double* __restrict__ par)
+{
+    persistent_body<1>(blk, heads, par);
+}
+
+// gather every stride-th cell of the global index space into contiguous
+// buffers (the autotuner's sample)
+extern "C" __global__ void __launch_bounds__(256) chem_gather_sample(const PersistBlock* __restrict__ blk,
+                                                                    long stride, long count,
+                                                                    double* __restrict__ T,
+                                                                    double* __restrict__ p,
+                                                                    double* __restrict__ Y)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const long g = i * stride;
+    int f = 0;
+    while (f + 1 < blk->nfield && blk->fields[f + 1].start <= g) ++f;
+    const FieldDesc& fd = blk->fields[f];
+    const long l = g - fd.start;
+    T[i] = fd.T[l];
+    p[i] = fd.p[l];
+    for (int k = 0; k < chem::NS; ++k) Y[i * chem::NS + k] = fd.Y[l * chem::NS + k];
+}

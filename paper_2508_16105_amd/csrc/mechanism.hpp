@@ -1,0 +1,59 @@
+// mechanism.hpp -- host representation of a reaction mechanism read from a
+// `chemmi-mech 1` file: species with NASA-7 thermo, reversible reactions with
+// modified-Arrhenius rates, third-body efficiencies and Lindemann/Troe falloff
+// (the "reactions and thermo data" of the detailed-chemistry model, Sec. 2.1).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace chemmi {
+
+constexpr double kRu = 8.314462618;      // J/(mol K)
+constexpr double kPatm = 101325.0;       // Pa, standard state of the equilibrium constants
+
+enum class RxnKind { Elementary, ThirdBody, Lindemann, Troe };
+
+struct SpeciesData {
+    std::string name;
+    std::vector<int> atoms;              // per element
+    double W = 0.0;                      // kg/mol
+    double tmid = 1000.0;
+    double lo[7] = {0}, hi[7] = {0};     // NASA-7, T < tmid and T >= tmid
+    bool has_thermo = false;
+};
+
+struct Term {
+    int sp;
+    int nu;
+};
+
+struct ReactionData {
+    RxnKind kind = RxnKind::Elementary;
+    std::vector<Term> reac, prod;
+    int dnu = 0;                         // sum nu'' - sum nu'
+    double lnA = 0.0, b = 0.0, EaR = 0.0; // main rate, SI, Ea/R in K
+    double lnA0 = 0.0, b0 = 0.0, EaR0 = 0.0;   // low-pressure limit (falloff)
+    double alpha = 0.0, T3 = 1.0, T1 = 1.0, T2 = 0.0;
+    bool has_T2 = false;
+    std::vector<double> eff;             // per species (third-body and falloff)
+};
+
+struct MechanismData {
+    std::string name;
+    std::vector<std::string> elements;
+    std::vector<double> element_w;       // g/mol
+    std::vector<SpeciesData> species;
+    std::vector<ReactionData> reactions;
+    int ns() const { return (int)species.size(); }
+    int nr() const { return (int)reactions.size(); }
+};
+
+// Parse and validate.  Returns 0, or a negative chem error code with `err` set.
+int parse_mechanism(const std::string& path, MechanismData& out, std::string& err);
+
+// Arrhenius parameters in the layout the kernels read: lnA[nr], b[nr], EaR[nr].
+std::vector<double> pack_params(const MechanismData& m);
+
+}  // namespace chemmi

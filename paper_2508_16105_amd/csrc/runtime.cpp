@@ -1,0 +1,410 @@
+// runtime.cpp -- per-device module and workspace, plain and persistent launches,
+// the HIP-graph cache and the launch-shape autotuner.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <tuple>
+
+namespace chemmi {
+
+namespace {
+
+#define HIPCHECK(expr, what)                          \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_error(e_, what); \
+    } while (0)
+
+int load_function(hipModule_t mod, const char* name, hipFunction_t* f)
+{
+    hipError_t e = hipModuleGetFunction(f, mod, name);
+    if (e != hipSuccess) return hip_error(e, name);
+    return 0;
+}
+
+template <class T>
+int grow(T** ptr, size_t* cap, size_t want, const char* what)
+{
+    if (*cap >= want && *ptr) return 0;
+    if (*ptr) (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+    size_t n = std::max<size_t>(want, 1);
+    HIPCHECK(hipMalloc((void**)ptr, n * sizeof(T)), what);
+    *cap = n;
+    return 0;
+}
+
+int64_t size_bucket(int64_t total)
+{
+    int64_t b = 0;
+    while ((int64_t(1) << (b + 1)) <= total) ++b;
+    return b;
+}
+
+}  // namespace
+
+int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,
+              const char* what)
+{
+    void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
+                   HIP_LAUNCH_PARAM_END};
+    const int64_t grid = (n + block - 1) / block;
+    if (grid > 0x7fffffff) return set_error(CHEM_E_INVAL, "too many cells for one launch");
+    HIPCHECK(hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, block, 1, 1, 0, stream, nullptr, cfg), what);
+    return 0;
+}
+
+int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
+{
+    (void)stream;
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev), "hipGetDevice");
+    DeviceState& d = m->devices[dev];
+    if (!d.module) {
+        d.device = dev;
+        hipDeviceProp_t prop;
+        HIPCHECK(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+            return set_error(CHEM_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                                     "; this library is built for gfx950");
+        d.num_cu = prop.multiProcessorCount;
+        HIPCHECK(hipModuleLoadData(&d.module, m->code.data()), "hipModuleLoadData");
+        int rc = 0;
+        rc = rc ? rc : load_function(d.module, "chem_plain", &d.f_plain);
+        rc = rc ? rc : load_function(d.module, "chem_eval", &d.f_eval);
+        rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
+        rc = rc ? rc : load_function(d.module, "chem_zero_u64", &d.f_zero);
+        rc = rc ? rc : load_function(d.module, "chem_reduce_stats", &d.f_stats);
+        rc = rc ? rc : load_function(d.module, "chem_persistent", &d.f_persistent);
+        rc = rc ? rc : load_function(d.module, "chem_reset_heads", &d.f_reset);
+        rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
+        if (rc) return rc;
+        HIPCHECK(hipMalloc((void**)&d.par, sizeof(double) * std::max<size_t>(m->params.size(), 1)), "hipMalloc par");
+        HIPCHECK(hipMalloc((void**)&d.stats, sizeof(unsigned long long) * 4), "hipMalloc stats");
+        HIPCHECK(hipMalloc((void**)&d.heads, sizeof(unsigned long long) * 64), "hipMalloc heads");
+        HIPCHECK(hipEventCreate(&d.ev0), "hipEventCreate");
+        HIPCHECK(hipEventCreate(&d.ev1), "hipEventCreate");
+        d.par_version = 0;
+    }
+    if (d.par_version != m->params_version) {
+        // stream-ordered after earlier work that read the old parameters
+        HIPCHECK(hipMemcpyAsync(d.par, m->params.data(), sizeof(double) * m->params.size(),
+                                hipMemcpyHostToDevice, stream),
+                 "copy parameters");
+        HIPCHECK(hipStreamSynchronize(stream), "sync parameters");
+        d.par_version = m->params_version;
+    }
+    *out = &d;
+    return 0;
+}
+
+void release_device_state(chem_mechanism* m)
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : m->devices) {
+        DeviceState& d = kv.second;
+        (void)hipSetDevice(d.device);
+        for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
+        if (d.capture_stream) (void)hipStreamDestroy(d.capture_stream);
+        for (void* p : {(void*)d.par, (void*)d.stats, (void*)d.heads, (void*)d.block_buf,
+                        (void*)d.cells_i32, (void*)d.sample})
+            if (p) (void)hipFree(p);
+        if (d.ev0) (void)hipEventDestroy(d.ev0);
+        if (d.ev1) (void)hipEventDestroy(d.ev1);
+        if (d.module) (void)hipModuleUnload(d.module);
+    }
+    m->devices.clear();
+    (void)hipSetDevice(cur);
+}
+
+namespace {
+
+// Reduce per-cell counters into stats (synchronises the stream).
+int collect_stats(DeviceState& d, const int32_t* status, const int32_t* nacc, const int32_t* nrej,
+                  int64_t ncell, float ms, chem_stats* stats, hipStream_t stream)
+{
+    int n4 = 4;
+    unsigned long long* sp = d.stats;
+    struct { unsigned long long* p; int n; } za{sp, n4};
+    if (int rc = launch_1d(d.f_zero, 4, 64, &za, sizeof za, stream, "chem_zero_u64")) return rc;
+    struct {
+        const int32_t* s;
+        const int32_t* a;
+        const int32_t* r;
+        long n;
+        unsigned long long* out;
+    } ra{status, nacc, nrej, (long)ncell, sp};
+    const int64_t threads = std::min<int64_t>(ncell, (int64_t)d.num_cu * 4 * 256);
+    if (int rc = launch_1d(d.f_stats, threads, 256, &ra, sizeof ra, stream, "chem_reduce_stats")) return rc;
+    unsigned long long h[4];
+    HIPCHECK(hipMemcpyAsync(h, sp, sizeof h, hipMemcpyDeviceToHost, stream), "copy stats");
+    HIPCHECK(hipStreamSynchronize(stream), "sync stats");
+    stats->cells = ncell;
+    stats->accepted = (int64_t)h[0];
+    stats->rejected = (int64_t)h[1];
+    stats->failed = (int64_t)h[2];
+    stats->max_substeps = (int64_t)h[3];
+    stats->kernel_ms = ms;
+    if (stats->failed) return set_error(CHEM_E_CELL_FAILED, std::to_string(stats->failed) + " cells failed");
+    return 0;
+}
+
+StepArgs step_args(double dt, double rtol, double atol, const Options& o)
+{
+    return StepArgs{dt, rtol, atol, o.hmin_rel * dt, o.max_substeps};
+}
+
+}  // namespace
+
+int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+              double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
+              int32_t* nacc, int32_t* nrej, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    // per-cell counters the caller did not ask for go to the workspace
+    if (!status || !nacc || !nrej)
+        if (int rc = grow(&d->cells_i32, &d->cells_cap, 3 * (size_t)ncell, "workspace")) return rc;
+    int32_t* st = status ? status : d->cells_i32;
+    int32_t* na = nacc ? nacc : d->cells_i32 + ncell;
+    int32_t* nr = nrej ? nrej : d->cells_i32 + 2 * ncell;
+    IntegrateArgs a{d->par, T, p, Y, (long)ncell, o.h0, st, na, nr, step_args(dt, rtol, atol, o)};
+    if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
+    if (int rc = launch_1d(d->f_plain, ncell, 64, &a, sizeof a, stream, "chem_plain")) return rc;
+    if (!stats) return 0;
+    HIPCHECK(hipEventRecord(d->ev1, stream), "event");
+    HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, d->ev0, d->ev1), "elapsed");
+    return collect_stats(*d, st, na, nr, ncell, ms, stats, stream);
+}
+
+// ---------------- persistent form ----------------
+
+namespace {
+
+int write_block(DeviceState& d, const std::vector<FieldDesc>& fields, const PersistHeader& h,
+                hipStream_t stream)
+{
+    const size_t bytes = sizeof(PersistHeader) + fields.size() * sizeof(FieldDesc);
+    if (d.block_cap < bytes || !d.block_buf) {
+        if (d.block_buf) (void)hipFree(d.block_buf);
+        d.block_buf = nullptr;
+        d.block_cap = 0;
+        // graphs hold the old address
+        for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
+        d.graphs.clear();
+        const size_t cap = std::max<size_t>(bytes, sizeof(PersistHeader) + 64 * sizeof(FieldDesc));
+        HIPCHECK(hipMalloc((void**)&d.block_buf, cap), "hipMalloc field table");
+        d.block_cap = cap;
+    }
+    std::vector<char> host(bytes);
+    std::memcpy(host.data(), &h, sizeof h);
+    std::memcpy(host.data() + sizeof h, fields.data(), fields.size() * sizeof(FieldDesc));
+    // pageable source: the copy is staged before this call returns
+    HIPCHECK(hipMemcpyAsync(d.block_buf, host.data(), bytes, hipMemcpyHostToDevice, stream),
+             "copy field table");
+    return 0;
+}
+
+int grid_of(const DeviceState& d, const LaunchConfig& c)
+{
+    // resident workgroups: CUs x 4 SIMDs x waves per SIMD, 64-lane waves
+    const int waves = d.num_cu * 4 * c.waves_per_simd;
+    return std::max(1, waves * 64 / c.block);
+}
+
+// Launch [reset queue heads -> persistent kernel] as a graph built once per
+// launch shape (the kernels read everything call-specific from the field
+// table, whose device address is fixed).
+int launch_graph(DeviceState& d, const LaunchConfig& c, hipStream_t stream)
+{
+    auto it = d.graphs.find(c);
+    if (it == d.graphs.end()) {
+        if (!d.capture_stream) HIPCHECK(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "stream");
+        hipGraph_t g;
+        HIPCHECK(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        struct { unsigned long long* h; int n; } ra{d.heads, 64};
+        size_t rs = sizeof ra;
+        void* rcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &ra, HIP_LAUNCH_PARAM_BUFFER_SIZE, &rs, HIP_LAUNCH_PARAM_END};
+        hipError_t e = hipModuleLaunchKernel(d.f_reset, 1, 1, 1, 64, 1, 1, 0, d.capture_stream, nullptr, rcfg);
+        struct { const char* blk; unsigned long long* heads; const double* par; } pa{d.block_buf, d.heads, d.par};
+        size_t ps = sizeof pa;
+        void* pcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &pa, HIP_LAUNCH_PARAM_BUFFER_SIZE, &ps, HIP_LAUNCH_PARAM_END};
+        if (e == hipSuccess)
+            e = hipModuleLaunchKernel(d.f_persistent, grid_of(d, c), 1, 1, c.block, 1, 1, 0, d.capture_stream,
+                                      nullptr, pcfg);
+        hipError_t e2 = hipStreamEndCapture(d.capture_stream, &g);
+        if (e != hipSuccess) return hip_error(e, "capture persistent launch");
+        if (e2 != hipSuccess) return hip_error(e2, "end capture");
+        hipGraphExec_t ex;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return hip_error(e3, "graph instantiate");
+        it = d.graphs.emplace(c, ex).first;
+    }
+    HIPCHECK(hipGraphLaunch(it->second, stream), "graph launch");
+    return 0;
+}
+
+int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<FieldDesc>& out,
+                int64_t& total)
+{
+    total = 0;
+    for (int f = 0; f < nfield; ++f) total += fv[f].ncell;
+    if (int rc = grow(&d.cells_i32, &d.cells_cap, 3 * (size_t)total, "workspace")) return rc;
+    out.clear();
+    int64_t start = 0;
+    for (int f = 0; f < nfield; ++f) {
+        FieldDesc x;
+        x.T = fv[f].T;
+        x.p = fv[f].p;
+        x.Y = fv[f].Y;
+        x.status = fv[f].status ? fv[f].status : d.cells_i32 + start;
+        x.nacc = fv[f].nacc ? fv[f].nacc : d.cells_i32 + total + start;
+        x.nrej = fv[f].nrej ? fv[f].nrej : d.cells_i32 + 2 * total + start;
+        x.ncell = (long)fv[f].ncell;
+        x.start = (long)start;
+        out.push_back(x);
+        start += fv[f].ncell;
+    }
+    return 0;
+}
+
+PersistHeader header_for(const DeviceState& d, int64_t total, int nfield, const LaunchConfig& c,
+                         const StepArgs& s)
+{
+    (void)d;
+    PersistHeader h{};
+    h.total = (long)total;
+    h.nq = 8;                                        // one queue per XCD
+    h.qchunk = (long)((total + h.nq - 1) / h.nq);
+    h.nfield = nfield;
+    h.refill = std::max(1, std::min(64, c.refill));
+    h.step = s;
+    return h;
+}
+
+// Time candidate launch shapes on a strided sample of the input (copied, so
+// the caller's data is untouched) and keep the fastest per size bucket.
+int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fields, int64_t total,
+             const StepArgs& s, const Options& o, hipStream_t stream, LaunchConfig* best)
+{
+    const int64_t bucket = size_bucket(total);
+    auto hit = d.tuned.find(bucket);
+    if (hit != d.tuned.end()) {
+        *best = hit->second;
+        return 0;
+    }
+    const int ns = m->data.ns();
+    const int64_t want = std::min<int64_t>(total, std::max<int64_t>(65536, total / 16));
+    const int64_t stride = std::max<int64_t>(1, total / want);
+    const int64_t count = (total + stride - 1) / stride;
+    const size_t per = (size_t)count * (ns + 2);
+    if (int rc = grow(&d.sample, &d.sample_cap, 2 * per, "autotune sample")) return rc;
+    double* sT = d.sample;
+    double* sp = sT + count;
+    double* sY = sp + count;
+    double* wT = d.sample + per;                      // working copy
+    PersistHeader h = header_for(d, total, (int)fields.size(), LaunchConfig{}, s);
+    if (int rc = write_block(d, fields, h, stream)) return rc;
+    struct { const char* blk; long stride; long count; double* T; double* p; double* Y; } ga{
+        d.block_buf, (long)stride, (long)count, sT, sp, sY};
+    if (int rc = launch_1d(d.f_gather, count, 256, &ga, sizeof ga, stream, "chem_gather_sample")) return rc;
+
+    std::vector<LaunchConfig> cands;
+    for (int block : {64, 256})
+        for (int refill : {4, 16, 32})
+            cands.push_back(LaunchConfig{block, 1, refill});
+    if (o.block) for (auto& c : cands) c.block = o.block;
+    if (o.refill) for (auto& c : cands) c.refill = o.refill;
+    float best_ms = 1e30f;
+    *best = cands[0];
+    // count <= total, so the per-cell workspace (3 * total) already fits the sample
+    std::vector<FieldDesc> sf(1);
+    sf[0] = FieldDesc{wT, sp, wT + count, d.cells_i32, d.cells_i32 + count, d.cells_i32 + 2 * count,
+                      (long)count, 0};
+    for (const auto& c : cands) {
+        HIPCHECK(hipMemcpyAsync(wT, sT, sizeof(double) * count, hipMemcpyDeviceToDevice, stream), "sample copy");
+        HIPCHECK(hipMemcpyAsync(wT + count, sY, sizeof(double) * count * ns, hipMemcpyDeviceToDevice, stream),
+                 "sample copy");
+        PersistHeader hs = header_for(d, count, 1, c, s);
+        if (int rc = write_block(d, sf, hs, stream)) return rc;
+        HIPCHECK(hipEventRecord(d.ev0, stream), "event");
+        if (int rc = launch_graph(d, c, stream)) return rc;
+        HIPCHECK(hipEventRecord(d.ev1, stream), "event");
+        HIPCHECK(hipEventSynchronize(d.ev1), "event sync");
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, d.ev0, d.ev1), "elapsed");
+        if (std::getenv("CHEM_LOG"))
+            std::fprintf(stderr, "[chem] autotune block=%d refill=%d: %.3f ms\n", c.block, c.refill, ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = c;
+        }
+    }
+    d.tuned[bucket] = *best;
+    return 0;
+}
+
+}  // namespace
+
+int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt, double rtol,
+                   double atol, const Options& o, chem_stats* stats, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    for (int f = 0; f < nfield; ++f)
+        if (fv[f].h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the persistent form");
+    std::vector<FieldDesc> fields;
+    int64_t total = 0;
+    if (int rc = fill_fields(*d, fv, nfield, fields, total)) return rc;
+    const StepArgs s = step_args(dt, rtol, atol, o);
+    LaunchConfig c;
+    if (o.block && o.refill) {
+        c = LaunchConfig{o.block, std::max(1, o.waves_per_simd), o.refill};
+    } else if (int rc = autotune(m, *d, fields, total, s, o, stream, &c)) {
+        return rc;
+    }
+    if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
+    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s), stream)) return rc;
+    if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
+    if (int rc = launch_graph(*d, c, stream)) return rc;
+    if (!stats) return 0;
+    HIPCHECK(hipEventRecord(d->ev1, stream), "event");
+    HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, d->ev0, d->ev1), "elapsed");
+    if (nfield == 1)
+        return collect_stats(*d, fields[0].status, fields[0].nacc, fields[0].nrej, total, ms, stats, stream);
+    bool all_ws = true;
+    for (int f = 0; f < nfield; ++f) all_ws = all_ws && !fv[f].status && !fv[f].nacc && !fv[f].nrej;
+    if (all_ws)   // workspace counters are contiguous over the global index space
+        return collect_stats(*d, d->cells_i32, d->cells_i32 + total, d->cells_i32 + 2 * total, total, ms,
+                             stats, stream);
+    chem_stats tot{};
+    tot.kernel_ms = ms;
+    for (int f = 0; f < nfield; ++f) {
+        chem_stats sf{};
+        int rc = collect_stats(*d, fields[f].status, fields[f].nacc, fields[f].nrej, fields[f].ncell, ms, &sf, stream);
+        if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+        tot.cells += sf.cells;
+        tot.accepted += sf.accepted;
+        tot.rejected += sf.rejected;
+        tot.failed += sf.failed;
+        tot.max_substeps = std::max(tot.max_substeps, sf.max_substeps);
+    }
+    *stats = tot;
+    if (tot.failed) return set_error(CHEM_E_CELL_FAILED, std::to_string(tot.failed) + " cells failed");
+    return 0;
+}
+
+}  // namespace chemmi

@@ -1,0 +1,170 @@
+// runtime.hpp -- per-device state of a mechanism and the launch paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "mechanism.hpp"
+
+namespace chemmi {
+
+// Host mirrors of the kernel argument structs (same field order and types as
+// in device/integrator.hip).
+struct StepArgs {
+    double dt, rtol, atol, hmin;
+    int max_substeps;
+};
+
+struct IntegrateArgs {
+    const double* par;
+    double* T;
+    const double* p;
+    double* Y;
+    long ncell;
+    const double* h0;
+    int* status;
+    int* nacc;
+    int* nrej;
+    StepArgs step;
+};
+
+struct EvalArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double* f;
+    double* J;
+};
+
+struct FixedStepArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double h;
+    double* ynew;
+    double* err;
+    double rtol, atol;
+    int* ok;
+};
+
+struct FieldDesc {
+    double* T;
+    const double* p;
+    double* Y;
+    int* status;
+    int* nacc;
+    int* nrej;
+    long ncell;
+    long start;
+};
+
+struct PersistHeader {
+    long total;
+    long qchunk;
+    int nfield;
+    int nq;
+    int refill;
+    int pad;
+    StepArgs step;
+};
+
+struct Options {
+    int form = CHEM_FORM_AUTO;
+    int max_substeps = 100000;
+    double hmin_rel = 1e-20;
+    const double* h0 = nullptr;
+    int checkpoint_every = 4;
+    int block = 0;
+    int waves_per_simd = 0;
+    int refill = 0;
+};
+
+// One field of cells as the caller passed it.
+struct FieldView {
+    double* T;
+    const double* p;
+    double* Y;
+    int64_t ncell;
+    int32_t* status;
+    int32_t* nacc;
+    int32_t* nrej;
+    const double* h0;
+};
+
+struct LaunchConfig {
+    int block = 64;            // lanes per workgroup
+    int waves_per_simd = 1;
+    int refill = 16;
+    bool operator<(const LaunchConfig& o) const
+    {
+        return std::tie(block, waves_per_simd, refill) < std::tie(o.block, o.waves_per_simd, o.refill);
+    }
+};
+
+struct DeviceState {
+    int device = -1;
+    int num_cu = 256;
+    hipModule_t module = nullptr;
+    hipFunction_t f_plain = nullptr, f_eval = nullptr, f_fixed = nullptr, f_zero = nullptr,
+                  f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr;
+    double* par = nullptr;               // 3 * nr device doubles
+    uint64_t par_version = 0;
+    unsigned long long* stats = nullptr; // 4 counters
+    unsigned long long* heads = nullptr; // queue heads (persistent)
+    char* block_buf = nullptr;           // PersistBlock (header + fields)
+    size_t block_cap = 0;                // fields capacity
+    int32_t* cells_i32 = nullptr;        // status, nacc, nrej workspace [3 * cap]
+    size_t cells_cap = 0;
+    double* sample = nullptr;            // autotune sample buffers
+    size_t sample_cap = 0;
+    hipStream_t capture_stream = nullptr;
+    std::map<LaunchConfig, hipGraphExec_t> graphs;
+    std::map<int64_t, LaunchConfig> tuned;  // by log2 bucket of the total cell count
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+}  // namespace chemmi
+
+struct chem_mechanism {
+    chemmi::MechanismData data;
+    std::vector<double> params;          // lnA[nr], b[nr], Ea/R[nr]
+    uint64_t params_version = 1;
+    std::string source;
+    std::vector<char> code;
+    std::string cache_file;
+    std::mutex mu;
+    std::map<int, chemmi::DeviceState> devices;
+};
+
+namespace chemmi {
+
+int set_error(int code, const std::string& msg);
+int hip_error(hipError_t e, const char* what);
+bool is_device_ptr(const void* p);
+
+// Device state for the current device (module loaded, parameters current).
+int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out);
+void release_device_state(chem_mechanism* m);
+
+int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,
+              const char* what);
+
+int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+              double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
+              int32_t* nacc, int32_t* nrej, hipStream_t stream);
+
+int run_persistent(chem_mechanism* m, const FieldView* fields, int nfield, double dt, double rtol,
+                   double atol, const Options& o, chem_stats* stats, hipStream_t stream);
+
+}  // namespace chemmi

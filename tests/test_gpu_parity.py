@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: |dT| <= 1e-6 T and |dY_k| <= 1e-8 at rtol 1e-8, atol 1e-12 for
+integrated states; source terms and Jacobians to round-off (1e-11 relative to
+the row scale); the persistent and plain forms bitwise."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workloads import WORKLOADS, mech_path, mech_text  # noqa: E402
+from workloads.states import rde_field, uniform_cells  # noqa: E402
+
+DT, RTOL, ATOL = 5e-9, 1e-8, 1e-12
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def chem():
+    import paper_2508_16105_amd as chem
+    return chem
+
+
+@pytest.fixture(scope="module")
+def mechs(chem, oracle_lib):
+    out = {}
+    for name in ("m9", "m13"):
+        out[name] = (chem.Mechanism(mech_path(name)), oracle_lib.Mechanism(mech_path(name)))
+    return out
+
+
+def _g(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _assert_state_parity(Tg, Yg, To, Yo, what):
+    dT = np.abs(Tg - To)
+    dY = np.abs(Yg - Yo)
+    bad = (dT > 1e-6 * To) | np.any(dY > 1e-8, axis=1)
+    assert not bad.any(), (f"{what}: {bad.sum()} cells out of tolerance; max |dT|/T "
+                           f"{(dT / To).max():.3e}, max |dY| {dY.max():.3e}")
+
+
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_source_terms_and_jacobian_match_oracle(chem, mechs, dev, name):
+    gm, om = mechs[name]
+    T, p, Y = uniform_cells(mech_text(name), 200, 21)
+    f, J = chem.eval_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev))
+    f, J = f.cpu().numpy(), J.cpu().numpy()
+    for i in range(len(T)):
+        y = np.concatenate([[T[i]], Y[i]])
+        fo = om.rhs(p[i], y)
+        Jo = om.jac_cs(p[i], y)
+        assert np.all(np.abs(f[i] - fo) <= 1e-11 * np.abs(fo).max() + 1e-300), (i, f[i], fo)
+        sc = np.abs(Jo).max(axis=1, keepdims=True) * np.maximum(np.abs(y), 1e-3)[None, :] \
+            / np.maximum(np.abs(y), 1e-3).max()
+        assert np.all(np.abs(J[i] - Jo) <= 1e-10 * (np.abs(Jo) + sc)), (name, i)
+
+
+def test_fixed_step_matches_oracle(chem, mechs, dev):
+    gm, om = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), 128, 22)
+    for h in (1e-11, 1e-9):
+        yn, en, ok = chem.step_fixed(gm, _g(T, dev), _g(p, dev), _g(Y, dev), h, RTOL, ATOL)
+        yn = yn.cpu().numpy()
+        assert ok.cpu().numpy().all()
+        for i in range(len(T)):
+            yo, eo = om.step(p[i], np.concatenate([[T[i]], Y[i]]), h)
+            assert abs(yn[i, 0] - yo[0]) <= 1e-10 * yo[0]
+            assert np.all(np.abs(yn[i, 1:] - yo[1:]) <= 1e-12)
+
+
+def test_integrate_uniform4k_matches_oracle(chem, mechs, dev):
+    """The small parity workload in full: 4096 independent cells (64 waves, a
+    ragged last tile is covered by the ragged-size test)."""
+    w = WORKLOADS["uniform4k"]
+    gm, om = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), w["n"], w["seed"])
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), w["dt"],
+                                               w["rtol"], w["atol"], return_counts=True)
+    To, Yo, nao, nro, sto = om.integrate(T, p, Y, w["dt"], w["rtol"], w["atol"])
+    assert stats["failed"] == 0 and np.all(sto == 0) and np.all(st.cpu().numpy() == 0)
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, "uniform4k")
+    na, nr = na.cpu().numpy(), nr.cpu().numpy()
+    assert stats["accepted"] == na.sum() and stats["rejected"] == nr.sum()
+    differ = np.sum((na != nao) | (nr != nro))
+    assert differ <= 0.01 * len(T), f"{differ} cells took a different step sequence"
+
+
+def test_integrate_rde_field_matches_oracle(chem, mechs, dev):
+    """A 256 x 256 RDE-shaped field (fresh, front and burnt cells)."""
+    gm, om = mechs["m9"]
+    T, p, Y, reg = rde_field(mech_text("m9"), 256, 256, 101)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL)
+    To, Yo, _, _, sto = om.integrate(T, p, Y, DT, RTOL, ATOL)
+    assert stats["failed"] == 0 and np.all(sto == 0)
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, "rde 256x256")
+
+
+def test_m13_third_body_and_troe_integration(chem, mechs, dev):
+    gm, om = mechs["m13"]
+    T, p, Y = uniform_cells(mech_text("m13"), 1024, 31)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL)
+    To, Yo, _, _, sto = om.integrate(T, p, Y, 1e-8, RTOL, ATOL)
+    assert stats["failed"] == 0 and np.all(sto == 0)
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, "m13 uniform")
+
+
+def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev):
+    gm, _ = mechs["m9"]
+    T, p, Y, reg = rde_field(mech_text("m9"), 256, 256, 101)
+    Tp, Yp, sp, stp, nap, nrp = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL,
+                                               return_counts=True)
+    for block, refill in ((64, 1), (256, 16), (128, 64)):
+        Tq, Yq, sq, stq, naq, nrq = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL,
+                                                   ATOL, form=chem.FORM_PERSISTENT, block=block,
+                                                   refill=refill, return_counts=True)
+        assert torch.equal(Tp, Tq) and torch.equal(Yp, Yq)
+        assert torch.equal(nap, naq) and torch.equal(nrp, nrq) and torch.equal(stp, stq)
+        assert sq["accepted"] == sp["accepted"] and sq["cells"] == sp["cells"]
+
+
+def test_batched_fields_match_per_field_plain(chem, mechs, dev, oracle_lib):
+    gm, om = mechs["m9"]
+    sizes = [1000, 33, 70001, 1, 4097, 64]
+    fields = []
+    for i, n in enumerate(sizes):
+        from workloads.states import rde_field_n
+        T, p, Y, _ = rde_field_n(mech_text("m9"), n, 500 + i)
+        fields.append((T, p, Y))
+    Ts = [_g(f[0], dev) for f in fields]
+    ps = [_g(f[1], dev) for f in fields]
+    Ys = [_g(f[2], dev) for f in fields]
+    stats = chem.integrate_batched(gm, Ts, ps, Ys, DT, RTOL, ATOL)
+    assert stats["cells"] == sum(sizes) and stats["failed"] == 0
+    for (T, p, Y), Tb, Yb in zip(fields, Ts, Ys):
+        Tr, Yr, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL)
+        assert torch.equal(Tr, Tb) and torch.equal(Yr, Yb)
+    # oracle on a sample of every field
+    rng = np.random.default_rng(0)
+    for (T, p, Y), Tb, Yb in zip(fields, Ts, Ys):
+        idx = rng.choice(len(T), size=min(len(T), 200), replace=False)
+        To, Yo, _, _, _ = om.integrate(T[idx], p[idx], Y[idx], DT, RTOL, ATOL)
+        _assert_state_parity(Tb.cpu().numpy()[idx], Yb.cpu().numpy()[idx], To, Yo, "batched")
+
+
+def test_full_size_rde1m_sampled(chem, mechs, dev):
+    """The headline workload at full size in both launch forms: sampled cells
+    against the oracle, and properties that hold for every cell."""
+    w = WORKLOADS["rde1m"]
+    gm, om = mechs["m9"]
+    T, p, Y, reg = rde_field(mech_text("m9"), w["width"], w["height"], w["seed"])
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.choice(np.where(reg == r)[0], 300, replace=False) for r in (0, 1, 2)])
+    To, Yo, _, _, _ = om.integrate(T[idx], p[idx], Y[idx], w["dt"], w["rtol"], w["atol"])
+    out = {}
+    for form in (chem.FORM_PLAIN, chem.FORM_PERSISTENT):
+        Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), w["dt"],
+                                                   w["rtol"], w["atol"], form=form, return_counts=True)
+        assert stats["failed"] == 0 and stats["cells"] == len(T)
+        Tn, Yn = Tg.cpu().numpy(), Yg.cpu().numpy()
+        _assert_state_parity(Tn[idx], Yn[idx], To, Yo, f"rde1m form {form}")
+        nsub = (na + nr).cpu().numpy()
+        assert np.all(np.abs(Yn.sum(1) - 1.0) <= 1e-13 * np.maximum(nsub, 1) + 1e-14)
+        assert np.all(Tn > 0) and np.all(np.isfinite(Yn))
+        out[form] = (Tg, Yg)
+    assert torch.equal(out[chem.FORM_PLAIN][0], out[chem.FORM_PERSISTENT][0])
+    assert torch.equal(out[chem.FORM_PLAIN][1], out[chem.FORM_PERSISTENT][1])
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 4097])
+def test_ragged_sizes(chem, mechs, dev, n):
+    gm, om = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), n, 40 + n)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL)
+    To, Yo, _, _, _ = om.integrate(T, p, Y, 1e-8, RTOL, ATOL)
+    assert stats["cells"] == n
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, f"n={n}")
+
+
+def test_bad_cells_and_failure_codes(chem, mechs, dev):
+    gm, om = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), 8, 50)
+    T[2] = -10.0
+    Y[3, 4] = np.nan
+    p[5] = 0.0
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL,
+                                               ATOL, return_counts=True, allow_failed=True)
+    st = st.cpu().numpy()
+    assert list(np.where(st == 4)[0]) == [2, 3, 5] and stats["failed"] == 3
+    assert Tg[2].item() == -10.0 and np.isnan(Yg[3, 4].item())
+    with pytest.raises(chem.ChemError) as e:
+        chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL)
+    assert e.value.code == -6
+    # max_substeps = 1: hot cells cannot finish
+    T2, p2, Y2 = uniform_cells(mech_text("m9"), 64, 51)
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T2, dev), _g(p2, dev), _g(Y2, dev), 1e-8, RTOL,
+                                               ATOL, max_substeps=1, return_counts=True,
+                                               allow_failed=True)
+    _, _, nao, nro, sto = om.integrate(T2, p2, Y2, 1e-8, RTOL, ATOL, max_substeps=1)
+    assert np.array_equal(st.cpu().numpy(), sto)
+    assert np.all((na + nr).cpu().numpy() <= 1)
+
+
+def test_argument_errors(chem, mechs, dev):
+    gm, _ = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), 8, 52)
+    with pytest.raises(ValueError):
+        chem.integrate(gm, torch.tensor(T), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL)
+    import ctypes as C
+    from paper_2508_16105_amd import _lib
+    Th = np.ascontiguousarray(T)
+    rc = _lib.lib().chem_integrate(gm.h, 8, C.c_void_p(Th.ctypes.data), C.c_void_p(_g(p, dev).data_ptr()),
+                                   C.c_void_p(_g(Y, dev).data_ptr()), 1e-8, RTOL, ATOL, None, None,
+                                   None, None, None, None)
+    assert rc == -1 and b"device pointer" in _lib.lib().chem_last_error()
+
+
+def test_h0_option(chem, mechs, dev):
+    """A per-cell first trial step changes the step sequence, not the answer."""
+    gm, om = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), 256, 53)
+    h0 = _g(np.full(256, 1e-12), dev)
+    Tg, Yg, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL, h0=h0)
+    To, Yo, _, _, _ = om.integrate(T, p, Y, 1e-8, 1e-12, 1e-16)       # near-exact reference
+    # a different step sequence: agreement at the tolerance level, not bitwise
+    assert np.all(np.abs(Tg.cpu().numpy() - To) <= 1e-6 * To)
+    assert np.all(np.abs(Yg.cpu().numpy() - Yo) <= 1e-7)
