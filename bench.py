@@ -1,0 +1,169 @@
+"""Benchmark: chemistry cell-steps/s (FP64) on the RDE-shaped 1,048,576-cell
+field, persistent vs plain form at the same tolerance, with the FP64 ALU
+roofline of the integration kernel and the CPU oracle as a baseline.
+
+One step = every cell of the field advanced over one flow step dt = 5e-9 s
+(rtol 1e-8, atol 1e-12), starting each step from the same initial field (a
+device-to-device restore is part of the step).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6e12          # MI355X FP64 vector peak, FLOP/s
+RODAS4_STAGES = 6
+
+
+def flops_per_substep(ns: int, nr: int, s: int = RODAS4_STAGES) -> float:
+    """Algorithmic FP64 flops of one RODAS4 substep attempt (FMA = 2 flops):
+    Jacobian 50 nr + 4 n^2, LU (2/3) n^3, and per stage a source-term
+    evaluation 40 ns + 30 nr, two triangular solves 2 n^2 and the stage
+    combinations 2 s n.  Transcendentals (2 nr + 1 per source evaluation)
+    are not counted."""
+    n = ns + 1
+    f_rhs = 40 * ns + 30 * nr
+    f_jac = 50 * nr + 4 * n * n
+    return f_jac + (2.0 / 3.0) * n**3 + s * (f_rhs + 2 * n * n + 2 * s * n)
+
+
+def host_cores() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(T, p, Y, w, frac, seed=7):
+    """The oracle on a uniform random sample of the field (the same mix of
+    fresh, front and burnt cells), all host cores."""
+    import oracle
+    from workloads import mech_path
+    om = oracle.Mechanism(mech_path(w["mech"]))
+    rng = np.random.default_rng(seed)
+    n = max(1, int(frac * len(T)))
+    idx = np.sort(rng.choice(len(T), n, replace=False))
+    cores = host_cores()
+    t0 = time.perf_counter()
+    om.integrate(T[idx], p[idx], Y[idx], w["dt"], w["rtol"], w["atol"], nthreads=cores)
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} cells ({frac:.0%} uniform random sample of the field, seed {seed}), "
+                      f"{el:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rde1m")
+    ap.add_argument("--cpu-sample", type=float, default=0.05)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="persistent,plain")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (cells are "
+              f"independent, so a multi-GPU run would shard the field by predicted cost).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2508_16105_amd as chem
+    from workloads import WORKLOADS, mech_path, mech_text
+    from workloads.states import rde_field
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    mech = chem.Mechanism(mech_path(w["mech"]))
+    T, p, Y, reg = rde_field(mech_text(w["mech"]), w["width"], w["height"], w["seed"])
+    ncell = len(T)
+    T0 = torch.tensor(T, device=dev)
+    Y0 = torch.tensor(Y, device=dev)
+    pg = torch.tensor(p, device=dev)
+    Tw, Yw = T0.clone(), Y0.clone()
+    stream = torch.cuda.current_stream()
+    fper = flops_per_substep(mech.ns, mech.nr)
+    forms = {"persistent": chem.FORM_PERSISTENT, "plain": chem.FORM_PLAIN}
+
+    results = {}
+    for name in args.forms.split(","):
+        form = forms[name]
+
+        def step(stats=False):
+            Tw.copy_(T0)
+            Yw.copy_(Y0)
+            return chem.integrate(mech, Tw, pg, Yw, w["dt"], w["rtol"], w["atol"], form=form,
+                                  inplace=True, stats=stats)[2]
+
+        st = step(stats=True)                      # includes the autotune on first use
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            Tw.copy_(T0)
+            Yw.copy_(Y0)
+            ev[i][0].record(stream)
+            chem.integrate(mech, Tw, pg, Yw, w["dt"], w["rtol"], w["atol"], form=form,
+                           inplace=True, stats=False)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        subs = st["accepted"] + st["rejected"]
+        results[name] = dict(ms_per_step=1e3 * wall / args.steps, kernel_ms=kms,
+                             cell_steps_per_s=ncell * args.steps / wall,
+                             substeps=subs, accepted=st["accepted"], rejected=st["rejected"],
+                             max_substeps_cell=st["max_substeps"],
+                             achieved_tflops=subs * fper / (kms * 1e-3) / 1e12)
+
+    head = "persistent" if "persistent" in results else next(iter(results))
+    r = results[head]
+    line = {
+        "metric": "chemistry cell-steps/s (FP64) + % FP64 peak; persistent vs plain, same tol",
+        "value": r["cell_steps_per_s"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": ncell,
+                   "mechanism": f"{w['mech']} ({mech.ns} species, {mech.nr} reactions)",
+                   "dt": w["dt"], "rtol": w["rtol"], "atol": w["atol"], "form": head,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": r["achieved_tflops"], "peak": PEAK_FP64_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": r["achieved_tflops"] / (PEAK_FP64_VALU / 1e12),
+                     "traffic": None,
+                     "kernel": "chem_persistent" if head == "persistent" else "chem_plain",
+                     "kernel_ms": r["kernel_ms"],
+                     "flops_per_substep": fper, "substeps_per_launch": r["substeps"]},
+        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in results.items()},
+    }
+    if "plain" in results and "persistent" in results:
+        line["persistent_over_plain"] = results["plain"]["ms_per_step"] / results["persistent"]["ms_per_step"]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -187,7 +187,8 @@ int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, co
     DeviceState* d;
     if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
     FixedStepArgs a{d->par, T, p, Y, (long)ncell, h, ynew, errnorm, rtol, atol, ok};
-    return launch_1d(d->f_fixed, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_fixed_step");
+    return launch_1d(d->f_fixed, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_fixed_step",
+                     d->stage_lds(64));
 }
 
 int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const double* p, double* Y,

@@ -63,9 +63,55 @@ struct Emitter {
 
     explicit Emitter(const MechanismData& mm) : m(mm), ns(mm.ns()), nr(mm.nr()) {}
 
+    // NASA-7 coefficient table, per species and range (0: T < T_mid, 1: T >= T_mid):
+    //  [0..4]  cp/R  = c0 + T(c1 + T(c2 + T(c3 + T c4)))          (a1..a5)
+    //  [5..8]  H/RT  = c0 + T(c5 + T(c6 + T(c7 + T c8))) + c9/T    (a2/2, a3/3, a4/4, a5/5)
+    //  [9]     a6
+    //  [10..13] G = S/R - H/RT = c0 lnT + T(c10 + T(c11 + T(c12 + T c13))) + c14 - c9/T
+    //           (a2/2, a3/6, a4/12, a5/20), [14] = a7 - a1
+    //  [15..18] d(cp/R)/dT = c15 + T(c16 + T(c17 + T c18))            (a2, 2a3, 3a4, 4a5)
+    void thermo_table()
+    {
+        // constant-address-space view: loads through it are scalar (uniform)
+        o << "typedef const __attribute__((address_space(4))) double cdbl;\n"
+             "// a zero the compiler cannot see through, known to be wave-uniform\n"
+             "__device__ __forceinline__ int opaque_zero()\n{\n"
+             "  int z;\n  asm volatile(\"s_mov_b32 %0, 0\" : \"=s\"(z));\n"
+             "  return __builtin_amdgcn_readfirstlane(z);\n}\n";
+        o << "__constant__ double THERMO[NS][2][20] = {\n";
+        for (int k = 0; k < ns; ++k) {
+            o << "  {";
+            for (int half = 0; half < 2; ++half) {
+                const double* a = half == 0 ? m.species[k].lo : m.species[k].hi;
+                const double c[20] = {a[0], a[1], a[2], a[3], a[4], a[1] / 2, a[2] / 3, a[3] / 4, a[4] / 5,
+                                      a[5], a[1] / 2, a[2] / 6, a[3] / 12, a[4] / 20, a[6] - a[0],
+                                      a[1], 2 * a[2], 3 * a[3], 4 * a[4], 0.0};
+                o << "{";
+                for (int i = 0; i < 20; ++i) o << lit(c[i]) << (i < 19 ? ", " : "");
+                o << "}" << (half == 0 ? ", " : "");
+            }
+            o << "}" << (k + 1 < ns ? ",\n" : "\n");
+        }
+        o << "};\n\n";
+    }
+
+    void thermo_one(const std::string& base, const std::string& sfx, bool with_dcp)
+    {
+        o << "        { cdbl* c = " << base << ";\n"
+             "          cpR" << sfx << " = c[0] + T*(c[1] + T*(c[2] + T*(c[3] + T*c[4])));\n"
+             "          HRT" << sfx << " = c[0] + T*(c[5] + T*(c[6] + T*(c[7] + T*c[8]))) + c[9]*iT;\n"
+             "          G" << sfx << " = c[0]*lnT + T*(c[10] + T*(c[11] + T*(c[12] + T*c[13]))) + (c[14] - c[9]*iT);\n";
+        if (with_dcp)
+            o << "          dcpR" << sfx << " = c[15] + T*(c[16] + T*(c[17] + T*c[18]));\n";
+        o << "        }\n";
+    }
+
     void thermo(bool with_dcp)
     {
-        // group species by T_mid: one branch per group
+        // Group species by T_mid.  When every lane of the wave is on the same
+        // side of T_mid the range index is wave-uniform and the coefficients
+        // come in by scalar loads; a wave straddling T_mid evaluates both
+        // ranges and selects per lane.
         std::vector<double> tmids;
         for (auto& s : m.species) {
             bool seen = false;
@@ -73,34 +119,48 @@ struct Emitter {
             if (!seen) tmids.push_back(s.tmid);
         }
         for (double tm : tmids) {
-            for (int half = 0; half < 2; ++half) {
-                o << (half == 0 ? "  if (T < " + lit(tm) + ") {\n" : "  } else {\n");
-                for (int k = 0; k < ns; ++k) {
-                    const auto& s = m.species[k];
-                    if (s.tmid != tm) continue;
-                    const double* a = half == 0 ? s.lo : s.hi;
-                    o << "    cpR[" << k << "] = " << lit(a[0]) << " + T*(" << lit(a[1]) << " + T*("
-                      << lit(a[2]) << " + T*(" << lit(a[3]) << " + T*" << lit(a[4]) << ")));\n";
-                    o << "    HRT[" << k << "] = " << lit(a[0]) << " + T*(" << lit(a[1] / 2) << " + T*("
-                      << lit(a[2] / 3) << " + T*(" << lit(a[3] / 4) << " + T*" << lit(a[4] / 5)
-                      << "))) + " << lit(a[5]) << "*iT;\n";
-                    // G = S/R - H/RT
-                    o << "    G[" << k << "] = " << lit(a[0]) << "*(lnT - 1.0) + T*(" << lit(a[1] / 2)
-                      << " + T*(" << lit(a[2] / 6) << " + T*(" << lit(a[3] / 12) << " + T*"
-                      << lit(a[4] / 20) << "))) + (" << lit(a[6]) << " - " << lit(a[5]) << "*iT);\n";
-                    if (with_dcp)
-                        o << "    dcpR[" << k << "] = " << lit(a[1]) << " + T*(" << lit(2 * a[2])
-                          << " + T*(" << lit(3 * a[3]) << " + T*" << lit(4 * a[4]) << "));\n";
-                }
+            o << "  {\n    const bool below = T < " << lit(tm) << ";\n"
+                 "    const bool all_lo = __all(below), all_hi = __all(!below);\n"
+                 "    if (all_lo || all_hi) {\n"
+                 "      const int r = all_lo ? 0 : 20;\n";
+            for (int k = 0; k < ns; ++k) {
+                if (m.species[k].tmid != tm) continue;
+                const std::string idx = "[" + std::to_string(k) + "]";
+                o << "      { cdbl* c = TH + " << k * 40 << " + r;\n"
+                     "        cpR" << idx << " = c[0] + T*(c[1] + T*(c[2] + T*(c[3] + T*c[4])));\n"
+                     "        HRT" << idx << " = c[0] + T*(c[5] + T*(c[6] + T*(c[7] + T*c[8]))) + c[9]*iT;\n"
+                     "        G" << idx << " = c[0]*lnT + T*(c[10] + T*(c[11] + T*(c[12] + T*c[13]))) + (c[14] - c[9]*iT);\n";
+                if (with_dcp) o << "        dcpR" << idx << " = c[15] + T*(c[16] + T*(c[17] + T*c[18]));\n";
+                o << "      }\n";
             }
-            o << "  }\n";
+            o << "    } else {\n";
+            for (int k = 0; k < ns; ++k) {
+                if (m.species[k].tmid != tm) continue;
+                const std::string idx = "[" + std::to_string(k) + "]";
+                o << "      { double cpR_l, HRT_l, G_l, dcpR_l, cpR_h, HRT_h, G_h, dcpR_h;\n";
+                thermo_one("TH + " + std::to_string(k * 40), "_l", with_dcp);
+                thermo_one("TH + " + std::to_string(k * 40 + 20), "_h", with_dcp);
+                o << "        cpR" << idx << " = below ? cpR_l : cpR_h;\n"
+                     "        HRT" << idx << " = below ? HRT_l : HRT_h;\n"
+                     "        G" << idx << " = below ? G_l : G_h;\n";
+                if (with_dcp) o << "        dcpR" << idx << " = below ? dcpR_l : dcpR_h;\n";
+                o << "      }\n";
+            }
+            o << "    }\n  }\n";
         }
     }
 
     // state common to rhs and rhs_jac
     void prologue(bool jac)
     {
-        o << "  const double T = y[0];\n"
+        // The table and parameter addresses are offset by an opaque zero so the
+        // scalar loads of the constants stay inside this evaluation instead of
+        // being hoisted out of the substep loop (where ~300 live constants
+        // would spill).
+        o << "  const int z = opaque_zero();\n"
+             "  cdbl* TH = (cdbl*)&THERMO[0][0][0] + z;\n"
+             "  cdbl* P = (cdbl*)par + z;\n"
+             "  const double T = y[0];\n"
              "  const double lnT = log(T);\n"
              "  const double iT = 1.0 / T;\n"
              "  double cpR[NS], HRT[NS], G[NS];\n";
@@ -109,8 +169,10 @@ struct Emitter {
         o << "  double sig = 0.0;\n";
         for (int k = 0; k < ns; ++k)
             o << "  sig = fma(y[" << 1 + k << "], " << lit(1.0 / m.species[k].W) << ", sig);\n";
+        // rho = p / (R T sig); 1/rho = R T sig / p with 1/p given
         o << "  const double Wbar = 1.0 / sig;\n"
              "  const double rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
+             "  const double irho = " << lit(kRu) << " * T * sig * ip;\n"
              "  const double ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
              "  double C[NS];\n";
         for (int k = 0; k < ns; ++k)
@@ -132,7 +194,7 @@ struct Emitter {
     {
         const auto& r = m.reactions[j];
         o << "  { // reaction " << j << "\n";
-        o << "    const double lnk = par[" << j << "] + par[" << nr + j << "]*lnT - par[" << 2 * nr + j
+        o << "    const double lnk = P[" << j << "] + P[" << nr + j << "]*lnT - P[" << 2 * nr + j
           << "]*iT;\n";
         // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
         std::string lnkc;
@@ -208,7 +270,7 @@ struct Emitter {
             for (auto& t : r.prod) sh += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
             for (auto& t : r.reac) sh += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
             o << "    const double dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
-            o << "    const double dlnkinf = (par[" << nr + j << "] + par[" << 2 * nr + j << "]*iT) * iT;\n";
+            o << "    const double dlnkinf = (P[" << nr + j << "] + P[" << 2 * nr + j << "]*iT) * iT;\n";
             if (!falloff) {
                 o << "    const double dlnkf = dlnkinf;\n";
             } else {
@@ -252,10 +314,11 @@ struct Emitter {
 
     void rhs_tail()
     {
-        o << "  const double rcpinv = 1.0 / (rho * cp);\n";
+        // 1/(rho cp) = T sig / (p cpm)
+        o << "  const double icpm = 1.0 / cpm;\n"
+             "  const double rcpinv = T * sig * ip * icpm;\n";
         o << "  double hw = 0.0;\n";
         for (int k = 0; k < ns; ++k) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
-        o << "  const double irho = 1.0 / rho;\n";
         for (int k = 0; k < ns; ++k)
             o << "  f[" << 1 + k << "] = " << lit(m.species[k].W) << " * irho * wd[" << k << "];\n";
         o << "  f[0] = -" << lit(kRu) << " * T * hw * rcpinv;\n";
@@ -299,7 +362,7 @@ struct Emitter {
               << "][0], HwT); cpw = fma(cpR[" << k << "], wd[" << k << "], cpw);\n";
         o << "  const double fT = f[0];\n"
              "  const double RT = " << lit(kRu) << " * T;\n"
-             "  const double icp = 1.0 / cp;\n";
+             "  const double icp = icpm * " << lit(1.0 / kRu) << ";\n";
         for (int mm = 0; mm < ns; ++mm) {
             o << "  { double HJ = 0.0";
             for (int k = 0; k < ns; ++k) o << " + HRT[" << k << "]*J[" << 1 + k << "][" << 1 + mm << "]";
@@ -327,7 +390,8 @@ struct Emitter {
           << "constexpr int NR = " << nr << ";\n"
           << "constexpr int N = NS + 1;\n\n";
         // source terms only
-        o << "__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, "
+        thermo_table();
+        o << "__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, double ip, "
              "const double (&y)[N], double (&f)[N])\n{\n";
         prologue(false);
         for (int j = 0; j < nr; ++j) reaction(j, false);
@@ -335,7 +399,7 @@ struct Emitter {
         rhs_tail();
         o << "}\n\n";
         // source terms and Jacobian
-        o << "__device__ __forceinline__ void rhs_jac(const double* __restrict__ par, double p, "
+        o << "__device__ __forceinline__ void rhs_jac(const double* __restrict__ par, double p, double ip, "
              "const double (&y)[N], double (&f)[N], double (&J)[N][N])\n{\n";
         o << "#pragma unroll\n  for (int i = 0; i < N; ++i)\n#pragma unroll\n    for (int j = 0; j < N; ++j) J[i][j] = 0.0;\n";
         prologue(true);

@@ -51,11 +51,14 @@ struct StepArgs {
 
 // ---- dense LU with partial pivoting, one matrix per lane ----
 // Row interchanges are made with selects (the pivot row differs per lane), on
-// the trailing columns only; piv[k] records the row swapped into k at step k
-// (LINPACK order), and the solve replays the swaps step by step.
-__device__ __forceinline__ bool lu_factor(double (&A)[N][N], int (&piv)[N])
+// the trailing columns only, and skipped when no lane of the wave needs one;
+// piv[k] records the row swapped into k at step k (LINPACK order) and bit k of
+// the returned wave-uniform mask says whether any lane swapped at step k.  The
+// diagonal of U is stored as its reciprocal.
+__device__ __forceinline__ unsigned lu_factor(double (&A)[N][N], int (&piv)[N], bool& ok)
 {
-    bool ok = true;
+    unsigned swaps = 0u;
+    ok = true;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         double amax = fabs(A[k][k]);
@@ -69,17 +72,21 @@ __device__ __forceinline__ bool lu_factor(double (&A)[N][N], int (&piv)[N])
         }
         piv[k] = p;
         ok = ok && (amax > 0.0);
+        if (__any(p != k)) {
+            swaps |= 1u << k;
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
-            const bool s = (p == i);
+            for (int i = k + 1; i < N; ++i) {
+                const bool s = (p == i);
 #pragma unroll
-            for (int j = k; j < N; ++j) {
-                const double akj = A[k][j], aij = A[i][j];
-                A[k][j] = s ? aij : akj;
-                A[i][j] = s ? akj : aij;
+                for (int j = k; j < N; ++j) {
+                    const double akj = A[k][j], aij = A[i][j];
+                    A[k][j] = s ? aij : akj;
+                    A[i][j] = s ? akj : aij;
+                }
             }
         }
         const double rp = 1.0 / A[k][k];
+        A[k][k] = rp;
 #pragma unroll
         for (int i = k + 1; i < N; ++i) {
             const double l = A[i][k] * rp;
@@ -88,20 +95,23 @@ __device__ __forceinline__ bool lu_factor(double (&A)[N][N], int (&piv)[N])
             for (int j = k + 1; j < N; ++j) A[i][j] = fma(-l, A[k][j], A[i][j]);
         }
     }
-    return ok;
+    return swaps;
 }
 
-__device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], double (&b)[N])
+__device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
+                                         double (&b)[N])
 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const int p = piv[k];
+        if (swaps & (1u << k)) {
+            const int p = piv[k];
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
-            const bool s = (p == i);
-            const double bk = b[k], bi = b[i];
-            b[k] = s ? bi : bk;
-            b[i] = s ? bk : bi;
+            for (int i = k + 1; i < N; ++i) {
+                const bool s = (p == i);
+                const double bk = b[k], bi = b[i];
+                b[k] = s ? bi : bk;
+                b[i] = s ? bk : bi;
+            }
         }
 #pragma unroll
         for (int i = k + 1; i < N; ++i) b[i] = fma(-A[i][k], b[k], b[i]);
@@ -111,7 +121,7 @@ __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&pi
         double v = b[i];
 #pragma unroll
         for (int j = i + 1; j < N; ++j) v = fma(-A[i][j], b[j], v);
-        b[i] = v / A[i][i];
+        b[i] = v * A[i][i];
     }
 }
 
@@ -119,12 +129,15 @@ __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x);
 
 // One RODAS4 step from y with step h.  Returns false if the step matrix is
 // singular or anything is not finite; otherwise ynew and the RMS error norm.
-__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p,
+// The stage vectors u_1..u_5 live in LDS (ul[(s*N + k) * ls], one column per
+// lane); the matrix factors, y and the current stage stay in registers.
+__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip,
                                          const double (&y)[N], double h, double rtol,
-                                         double atol, double (&ynew)[N], double& errn)
+                                         double atol, double (&ynew)[N], double& errn,
+                                         double* __restrict__ ul, int ls)
 {
     double M[N][N], f[N];
-    mech::rhs_jac(par, p, y, f, M);
+    mech::rhs_jac(par, p, ip, y, f, M);
     const double ghinv = 1.0 / (h * Rodas4::gamma);
     const double hinv = 1.0 / h;
 #pragma unroll
@@ -134,43 +147,47 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
         M[i][i] += ghinv;
     }
     int piv[N];
-    bool ok = lu_factor(M, piv);
+    bool ok;
+    const unsigned swaps = lu_factor(M, piv, ok);
 
-    double u[Rodas4::S][N];
+    lu_solve(M, piv, swaps, f);
 #pragma unroll
-    for (int k = 0; k < N; ++k) u[0][k] = f[k];
-    lu_solve(M, piv, u[0]);
+    for (int k = 0; k < N; ++k) ul[k * ls] = f[k];
+    double u[N];
 #pragma unroll
     for (int s = 1; s < Rodas4::S; ++s) {
-        double Ys[N];
+        double Ys[N], acc[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            double v = y[k];
+            double v = y[k], w = 0.0;
 #pragma unroll
-            for (int j = 0; j < s; ++j) v = fma(RA[s][j], u[j][k], v);
+            for (int j = 0; j < s; ++j) {
+                const double uj = ul[(j * N + k) * ls];
+                v = fma(RA[s][j], uj, v);
+                w = fma(RC[s][j], uj, w);
+            }
             Ys[k] = v;
+            acc[k] = w;
         }
         if (s == Rodas4::S - 1) {
 #pragma unroll
             for (int k = 0; k < N; ++k) ynew[k] = Ys[k];     // stiffly accurate: y_new = Y_6 + u_6
         }
-        double fs[N];
-        mech::rhs(par, p, Ys, fs);
+        mech::rhs(par, p, ip, Ys, u);
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double v = fs[k];
+        for (int k = 0; k < N; ++k) u[k] = fma(acc[k], hinv, u[k]);
+        lu_solve(M, piv, swaps, u);
+        if (s < Rodas4::S - 1) {
 #pragma unroll
-            for (int j = 0; j < s; ++j) v = fma(RC[s][j] * hinv, u[j][k], v);
-            u[s][k] = v;
+            for (int k = 0; k < N; ++k) ul[(s * N + k) * ls] = u[k];
         }
-        lu_solve(M, piv, u[s]);
     }
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        ynew[k] += u[Rodas4::S - 1][k];
+        ynew[k] += u[k];
         const double sc = atol + rtol * fmax(fabs(y[k]), fabs(ynew[k]));
-        const double e = u[Rodas4::S - 1][k] / sc;
+        const double e = u[k] / sc;
         acc = fma(e, e, acc);
         ok = ok && finite(ynew[k]);
     }
@@ -181,7 +198,7 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
 // Per-lane integration state.
 struct Cell {
     double y[N];
-    double p, t, h;
+    double p, ip, t, h;
     int nacc, nrej, status;
     bool rej_last, done;
 };
@@ -193,6 +210,7 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
 #pragma unroll
     for (int k = 0; k < NS; ++k) c.y[1 + k] = Y[k * stride];
     c.p = p;
+    c.ip = 1.0 / p;
     c.t = 0.0;
     c.h = h0;
     c.nacc = 0;
@@ -209,7 +227,8 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
 // accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
 // a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)
 // or 0.2; the final step is truncated to land on dt.
-__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a)
+__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
+                                             double* __restrict__ ul, int ls)
 {
     if (c.done) return;
     if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return; }
@@ -218,7 +237,7 @@ __device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__
     double h = c.h;
     if (h >= a.dt - c.t) { h = a.dt - c.t; last = true; }
     double ynew[N], en;
-    const bool ok = ros_step(par, c.p, c.y, h, a.rtol, a.atol, ynew, en);
+    const bool ok = ros_step(par, c.p, c.ip, c.y, h, a.rtol, a.atol, ynew, en, ul, ls);
     if (ok && en <= 1.0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) c.y[k] = ynew[k];
@@ -271,9 +290,10 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateAr
     using namespace chem;
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
+    extern __shared__ double lds[];
     Cell c;
     cell_begin(c, a.T[cell], a.p[cell], a.Y + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
-    while (!c.done) cell_attempt(c, a.par, a.step);
+    while (!c.done) cell_attempt(c, a.par, a.step, lds + threadIdx.x, blockDim.x);
     cell_store(c, a.T, a.Y, cell, a.status, a.nacc, a.nrej);
 }
 
@@ -297,15 +317,16 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_eval(EvalArgs a)
     y[0] = a.T[cell];
 #pragma unroll
     for (int k = 0; k < NS; ++k) y[1 + k] = a.Y[cell * NS + k];
+    const double p = a.p[cell];
     if (a.J) {
         double J[N][N];
-        mech::rhs_jac(a.par, a.p[cell], y, f, J);
+        mech::rhs_jac(a.par, p, 1.0 / p, y, f, J);
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
             for (int j = 0; j < N; ++j) a.J[(cell * N + i) * N + j] = J[i][j];
     } else {
-        mech::rhs(a.par, a.p[cell], y, f);
+        mech::rhs(a.par, p, 1.0 / p, y, f);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) a.f[cell * N + i] = f[i];
@@ -330,11 +351,14 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArg
     using namespace chem;
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
+    extern __shared__ double lds[];
     double y[N], yn[N], en;
     y[0] = a.T[cell];
 #pragma unroll
     for (int k = 0; k < NS; ++k) y[1 + k] = a.Y[cell * NS + k];
-    const bool ok = ros_step(a.par, a.p[cell], y, a.h, a.rtol, a.atol, yn, en);
+    const double p = a.p[cell];
+    const bool ok = ros_step(a.par, p, 1.0 / p, y, a.h, a.rtol, a.atol, yn, en, lds + threadIdx.x,
+                             blockDim.x);
 #pragma unroll
     for (int k = 0; k < N; ++k) a.ynew[cell * N + k] = yn[k];
     a.err[cell] = en;
@@ -426,6 +450,7 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
                                                 const double* __restrict__ par)
 {
     using namespace chem;
+    extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
     const long total = blk->total;
     const long qchunk = blk->qchunk;
@@ -485,7 +510,7 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
             continue;
         }
         if (have) {
-            cell_attempt(c, par, step);
+            cell_attempt(c, par, step, lds + threadIdx.x, blockDim.x);
             if (c.done) {
                 const FieldDesc& fd = blk->fields[fidx];
                 cell_store(c, fd.T, fd.Y, local, fd.status, fd.nacc, fd.nrej);

@@ -51,13 +51,13 @@ int64_t size_bucket(int64_t total)
 }  // namespace
 
 int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,
-              const char* what)
+              const char* what, unsigned shmem)
 {
     void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
                    HIP_LAUNCH_PARAM_END};
     const int64_t grid = (n + block - 1) / block;
     if (grid > 0x7fffffff) return set_error(CHEM_E_INVAL, "too many cells for one launch");
-    HIPCHECK(hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, block, 1, 1, 0, stream, nullptr, cfg), what);
+    HIPCHECK(hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, block, 1, 1, shmem, stream, nullptr, cfg), what);
     return 0;
 }
 
@@ -75,6 +75,8 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
             return set_error(CHEM_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName +
                                                      "; this library is built for gfx950");
         d.num_cu = prop.multiProcessorCount;
+        d.lds_per_block = prop.sharedMemPerBlock;
+        d.n = m->data.ns() + 1;
         HIPCHECK(hipModuleLoadData(&d.module, m->code.data()), "hipModuleLoadData");
         int rc = 0;
         rc = rc ? rc : load_function(d.module, "chem_plain", &d.f_plain);
@@ -178,7 +180,8 @@ int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, doub
     int32_t* nr = nrej ? nrej : d->cells_i32 + 2 * ncell;
     IntegrateArgs a{d->par, T, p, Y, (long)ncell, o.h0, st, na, nr, step_args(dt, rtol, atol, o)};
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
-    if (int rc = launch_1d(d->f_plain, ncell, 64, &a, sizeof a, stream, "chem_plain")) return rc;
+    if (int rc = launch_1d(d->f_plain, ncell, 64, &a, sizeof a, stream, "chem_plain", d->stage_lds(64)))
+        return rc;
     if (!stats) return 0;
     HIPCHECK(hipEventRecord(d->ev1, stream), "event");
     HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
@@ -240,8 +243,8 @@ int launch_graph(DeviceState& d, const LaunchConfig& c, hipStream_t stream)
         size_t ps = sizeof pa;
         void* pcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &pa, HIP_LAUNCH_PARAM_BUFFER_SIZE, &ps, HIP_LAUNCH_PARAM_END};
         if (e == hipSuccess)
-            e = hipModuleLaunchKernel(d.f_persistent, grid_of(d, c), 1, 1, c.block, 1, 1, 0, d.capture_stream,
-                                      nullptr, pcfg);
+            e = hipModuleLaunchKernel(d.f_persistent, grid_of(d, c), 1, 1, c.block, 1, 1, d.stage_lds(c.block),
+                                      d.capture_stream, nullptr, pcfg);
         hipError_t e2 = hipStreamEndCapture(d.capture_stream, &g);
         if (e != hipSuccess) return hip_error(e, "capture persistent launch");
         if (e2 != hipSuccess) return hip_error(e2, "end capture");
@@ -321,9 +324,9 @@ int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fi
     if (int rc = launch_1d(d.f_gather, count, 256, &ga, sizeof ga, stream, "chem_gather_sample")) return rc;
 
     std::vector<LaunchConfig> cands;
-    for (int block : {64, 256})
+    for (int block : {64, 128, 256})
         for (int refill : {4, 16, 32})
-            cands.push_back(LaunchConfig{block, 1, refill});
+            if (d.stage_lds(block) <= d.lds_per_block) cands.push_back(LaunchConfig{block, 1, refill});
     if (o.block) for (auto& c : cands) c.block = o.block;
     if (o.refill) for (auto& c : cands) c.refill = o.refill;
     float best_ms = 1e30f;
@@ -375,6 +378,8 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
         return rc;
     }
     if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
+    if (d->stage_lds(c.block) > d->lds_per_block)
+        return set_error(CHEM_E_INVAL, "block too large for the stage vectors in LDS");
     if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s), stream)) return rc;
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     if (int rc = launch_graph(*d, c, stream)) return rc;

@@ -132,6 +132,10 @@ struct DeviceState {
     std::map<LaunchConfig, hipGraphExec_t> graphs;
     std::map<int64_t, LaunchConfig> tuned;  // by log2 bucket of the total cell count
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    size_t lds_per_block = 65536;
+    int n = 0;                           // state size ns + 1
+    // LDS for the RODAS4 stage vectors u_1..u_5 of every lane of a workgroup
+    unsigned stage_lds(int block) const { return (unsigned)(block * 5 * n * sizeof(double)); }
 };
 
 }  // namespace chemmi
@@ -158,7 +162,7 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out);
 void release_device_state(chem_mechanism* m);
 
 int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,
-              const char* what);
+              const char* what, unsigned shmem = 0);
 
 int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
               double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
