@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--workload", default="rde1m")
     ap.add_argument("--cpu-sample", type=float, default=0.05)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="persistent,plain")
+    ap.add_argument("--forms", default="persistent,persistent_history,persistent_natural,plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (cells are "
@@ -94,17 +94,32 @@ def main():
     Tw, Yw = T0.clone(), Y0.clone()
     stream = torch.cuda.current_stream()
     fper = flops_per_substep(mech.ns, mech.nr)
-    forms = {"persistent": chem.FORM_PERSISTENT, "plain": chem.FORM_PLAIN}
+    # persistent: cells started most-expensive-first, cost predicted from the state;
+    # persistent_history: cost = each cell's substep count in the previous call on
+    # the same input (an upper bound for history-based ordering);
+    # persistent_natural: index order; plain: one launch, one cell per lane.
+    forms = {"persistent": (chem.FORM_PERSISTENT, {}),
+             "persistent_history": (chem.FORM_PERSISTENT, {"history": True}),
+             "persistent_natural": (chem.FORM_PERSISTENT, {"order": chem.ORDER_NATURAL}),
+             "plain": (chem.FORM_PLAIN, {})}
+    _, _, _, _, na0, nr0 = chem.integrate(mech, T0, pg, Y0, w["dt"], w["rtol"], w["atol"],
+                                          form=chem.FORM_PLAIN, return_counts=True)
+    prev_cost = (na0 + nr0).contiguous()
 
     results = {}
     for name in args.forms.split(","):
-        form = forms[name]
+        form, extra = forms[name]
+        kw = {}
+        if extra.get("history"):
+            kw["cost"] = prev_cost
+        if "order" in extra:
+            kw["order"] = extra["order"]
 
         def step(stats=False):
             Tw.copy_(T0)
             Yw.copy_(Y0)
             return chem.integrate(mech, Tw, pg, Yw, w["dt"], w["rtol"], w["atol"], form=form,
-                                  inplace=True, stats=stats)[2]
+                                  inplace=True, stats=stats, **kw)[2]
 
         st = step(stats=True)                      # includes the autotune on first use
         for _ in range(args.warmup):
@@ -118,7 +133,7 @@ def main():
             Yw.copy_(Y0)
             ev[i][0].record(stream)
             chem.integrate(mech, Tw, pg, Yw, w["dt"], w["rtol"], w["atol"], form=form,
-                           inplace=True, stats=False)
+                           inplace=True, stats=False, **kw)
             ev[i][1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0

@@ -72,6 +72,12 @@ enum chem_form {
     CHEM_FORM_PERSISTENT = 2    /* persistent work-stealing launch in a HIP graph */
 };
 
+/* Order in which the persistent form starts cells. */
+enum chem_order {
+    CHEM_ORDER_COST = 1,        /* default: most expensive first (caller's cost, else predicted) */
+    CHEM_ORDER_NATURAL = 2      /* index order */
+};
+
 typedef struct {
     int form;                   /* enum chem_form */
     int max_substeps;           /* attempts per cell; <= 0 means 100000 */
@@ -81,6 +87,11 @@ typedef struct {
     int block;                  /* persistent: lanes per workgroup (64..256); 0 = tuned */
     int waves_per_simd;         /* persistent: resident waves per SIMD (1..2); 0 = tuned */
     int refill;                 /* persistent: idle lanes that trigger a refill; 0 = tuned */
+    int order;                  /* persistent: enum chem_order; 0 = CHEM_ORDER_COST */
+    const int32_t *const *cost; /* nullable host array [nfield] of nullable device int32 [ncell]
+                                   per-cell cost hints (e.g. nacc + nrej of the previous call);
+                                   fields without one get a cost predicted from their state:
+                                   the RMS over y of f(y) dt / (atol + rtol |y|) */
 } chem_options;
 
 typedef struct {

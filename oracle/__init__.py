@@ -17,6 +17,7 @@ LIB = HERE / "liboracle.so"
 SOURCES = [HERE / "oracle.c", HERE / "chem_generic.inc", HERE / "oracle.h"]
 
 RODAS4 = 0
+ROS4 = 1
 CELL_OK, CELL_MAXSTEPS, CELL_HMIN, CELL_NONFINITE, CELL_BADINPUT = range(5)
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")

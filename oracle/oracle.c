@@ -132,10 +132,35 @@ static void tableau_rodas4(omtab *t)
     t->e[5] = 1.0;
 }
 
+/* ---------------- ROS4 ----------------
+ * Hairer & Wanner, Solving ODEs II, Sec. IV.7 (Table 7.2, the L-stable
+ * parameter set with gamma = 0.57282 of Shampine's 4-stage order-4(3)
+ * family), transformed u-form.  Stage 4 has the same argument as stage 3,
+ * so a method written for it needs three source evaluations per step; the
+ * oracle simply evaluates it again. */
+static void tableau_ros4(omtab *t)
+{
+    memset(t, 0, sizeof *t);
+    t->s = 4;
+    t->gamma = 0.57282;
+    t->a[1][0] = 2.0;
+    t->a[2][0] = 1.867943637803922;   t->a[2][1] = 0.2344449711399156;
+    t->a[3][0] = 1.867943637803922;   t->a[3][1] = 0.2344449711399156;
+    t->c[1][0] = -7.13761503641231;
+    t->c[2][0] = 2.580708087951457;   t->c[2][1] = 0.6515950076447975;
+    t->c[3][0] = -2.137148994382534;  t->c[3][1] = -0.3214669691237626;
+    t->c[3][2] = -0.6949742501781779;
+    t->m[0] = 2.255570073418735;      t->m[1] = 0.2870493262186792;
+    t->m[2] = 0.435317943184018;      t->m[3] = 1.093502252409163;
+    t->e[0] = -0.2815431932141155;    t->e[1] = -0.0727619912493892;
+    t->e[2] = -0.1082196201495311;    t->e[3] = -1.093502252409163;
+}
+
 static int get_tableau(int method, omtab *t)
 {
-    if (method != OM_RODAS4) return -1;
-    tableau_rodas4(t);
+    if (method == OM_RODAS4) tableau_rodas4(t);
+    else if (method == OM_ROS4) tableau_ros4(t);
+    else return -1;
     return 0;
 }
 

@@ -22,10 +22,10 @@ typedef struct omech omech;
 enum { OM_OK = 0, OM_E_IO = -1, OM_E_PARSE = -2, OM_E_INVALID = -3, OM_E_SIZE = -4 };
 enum { OM_CELL_OK = 0, OM_CELL_MAXSTEPS = 1, OM_CELL_HMIN = 2, OM_CELL_NONFINITE = 3,
        OM_CELL_BADINPUT = 4 };
-enum { OM_RODAS4 = 0 };
+enum { OM_RODAS4 = 0, OM_ROS4 = 1 };
 
 typedef struct {
-    int method;          /* OM_RODAS4 */
+    int method;          /* OM_RODAS4 or OM_ROS4 */
     int max_substeps;    /* attempts (accepted + rejected) per cell; default 100000 */
     double hmin_rel;     /* fail when h < hmin_rel * dt; default 1e-20 */
 } om_opts;

@@ -13,11 +13,11 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN
+from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN, ORDER_COST, ORDER_NATURAL
 
 __all__ = ["Mechanism", "integrate", "integrate_batched", "integrate_adjoint", "eval_source",
            "step_fixed", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
-           "FORM_PERSISTENT", "version"]
+           "FORM_PERSISTENT", "ORDER_COST", "ORDER_NATURAL", "version"]
 
 
 def _torch():
@@ -83,9 +83,16 @@ class Mechanism:
 
 
 def _options(form=FORM_AUTO, max_substeps=0, hmin_rel=0.0, h0=None, checkpoint_every=0, block=0,
-             waves_per_simd=0, refill=0):
-    return _lib.Options(form, max_substeps, hmin_rel, None if h0 is None else h0.data_ptr(),
-                        checkpoint_every, block, waves_per_simd, refill)
+             waves_per_simd=0, refill=0, order=0, cost=None):
+    """cost: None, or a list with one int32 GPU tensor (or None) per field."""
+    carr = None
+    if cost is not None:
+        carr = (C.c_void_p * max(len(cost), 1))(*[None if c is None else c.data_ptr() for c in cost])
+    o = _lib.Options(form, max_substeps, hmin_rel, None if h0 is None else h0.data_ptr(),
+                     checkpoint_every, block, waves_per_simd, refill, order,
+                     C.cast(carr, C.POINTER(C.c_void_p)) if carr is not None else None)
+    o._keep = carr
+    return o
 
 
 def integrate(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stats=True,
@@ -102,6 +109,8 @@ def integrate(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stat
     if return_counts:
         st, nacc, nrej = (torch.empty(n, dtype=torch.int32, device=T.device) for _ in range(3))
     s = _lib.Stats() if stats else None
+    if opts.get("cost") is not None and not isinstance(opts["cost"], (list, tuple)):
+        opts["cost"] = [opts["cost"]]
     o = _options(form=form, **opts)
     rc = _lib.lib().chem_integrate(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt), float(rtol),
                                    float(atol), C.byref(o), C.byref(s) if s is not None else None,

@@ -12,6 +12,7 @@ CHEM_OK = 0
 ERRORS = {-1: "CHEM_E_INVAL", -2: "CHEM_E_PARSE", -3: "CHEM_E_MECH_INVALID", -4: "CHEM_E_HIP",
           -5: "CHEM_E_NOMEM", -6: "CHEM_E_CELL_FAILED", -7: "CHEM_E_COMPILE", -8: "CHEM_E_UNSUPPORTED"}
 FORM_AUTO, FORM_PLAIN, FORM_PERSISTENT = 0, 1, 2
+ORDER_COST, ORDER_NATURAL = 1, 2
 
 EXPORTS = ["chem_load_mechanism", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
            "chem_set_params", "chem_eval_source", "chem_step_fixed", "chem_integrate",
@@ -21,7 +22,8 @@ EXPORTS = ["chem_load_mechanism", "chem_free_mechanism", "chem_mechanism_info", 
 class Options(C.Structure):
     _fields_ = [("form", C.c_int), ("max_substeps", C.c_int), ("hmin_rel", C.c_double),
                 ("h0", C.c_void_p), ("checkpoint_every", C.c_int), ("block", C.c_int),
-                ("waves_per_simd", C.c_int), ("refill", C.c_int)]
+                ("waves_per_simd", C.c_int), ("refill", C.c_int), ("order", C.c_int),
+                ("cost", C.POINTER(C.c_void_p))]
 
 
 class Stats(C.Structure):

@@ -23,11 +23,12 @@ HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "codeg
 
 
 def embed_device_source():
-    src = (CSRC / "device" / "integrator.hip").read_text()
     delim = "CHEMDEV"
-    assert f"){delim}\"" not in src
-    out = (f"// generated from device/integrator.hip by build.py; do not edit\n"
-           f"static const char kIntegratorSource[] = R\"{delim}(\n{src}){delim}\";\n")
+    out = "// generated from device/*.hip by build.py; do not edit\n"
+    for var, name in (("kMathSource", "math.hip"), ("kIntegratorSource", "integrator.hip")):
+        src = (CSRC / "device" / name).read_text()
+        assert f"){delim}\"" not in src
+        out += f"static const char {var}[] = R\"{delim}(\n{src}){delim}\";\n"
     target = CSRC / "_device_source.inc"
     if not target.exists() or target.read_text() != out:
         target.write_text(out)

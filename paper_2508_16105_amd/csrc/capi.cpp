@@ -81,6 +81,8 @@ Options resolve_options(const chem_options* o)
         r.block = o->block;
         r.waves_per_simd = o->waves_per_simd;
         r.refill = o->refill;
+        if (o->order) r.order = o->order;
+        r.cost = o->cost;
     }
     return r;
 }
@@ -210,7 +212,9 @@ int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const dou
     if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
     if (o.form == CHEM_FORM_PERSISTENT) {
-        FieldView fv{T, p, Y, ncell, cell_status, nacc, nrej, o.h0};
+        const int32_t* cost = o.cost ? o.cost[0] : nullptr;
+        if (cost && !is_device_ptr(cost)) return set_error(CHEM_E_INVAL, "cost[0] is not a device pointer");
+        FieldView fv{T, p, Y, ncell, cell_status, nacc, nrej, o.h0, cost};
         return run_persistent(m, &fv, 1, dt, rtol, atol, o, stats, (hipStream_t)stream);
     }
     return run_plain(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, nacc, nrej,
@@ -233,10 +237,19 @@ int chem_integrate_batched(const chem_mechanism* mc, int nfield, double* const* 
         if (ncell[f] < 0) return set_error(CHEM_E_INVAL, "negative field size");
         if (ncell[f] == 0) continue;
         if (int rc = check_device_ptrs({{T[f], "T[f]"}, {p[f], "p[f]"}, {Y[f], "Y[f]"}})) return rc;
-        fields.push_back(FieldView{T[f], p[f], Y[f], ncell[f], nullptr, nullptr, nullptr, nullptr});
+        fields.push_back(FieldView{T[f], p[f], Y[f], ncell[f], nullptr, nullptr, nullptr, nullptr, nullptr});
     }
     if (fields.empty()) return CHEM_OK;
     Options o = resolve_options(opt);
+    if (o.cost) {
+        int i = 0;
+        for (int f = 0; f < nfield; ++f) {
+            if (ncell[f] == 0) continue;
+            if (o.cost[f] && !is_device_ptr(o.cost[f]))
+                return set_error(CHEM_E_INVAL, "cost[f] is not a device pointer");
+            fields[i++].cost = o.cost[f];
+        }
+    }
     if (o.h0) return set_error(CHEM_E_INVAL, "h0 is per field; not supported by the batched call");
     std::lock_guard<std::mutex> lk(m->mu);
     if (o.form == CHEM_FORM_PLAIN) {

@@ -73,11 +73,20 @@ struct Emitter {
     void thermo_table()
     {
         // constant-address-space view: loads through it are scalar (uniform)
+        o << "__constant__ double EXP2_J64[64] = {";
+        for (int j = 0; j < 64; ++j)
+            o << lit((double)std::exp2((long double)j / 64.0L)) << (j < 63 ? ", " : "};\n");
         o << "typedef const __attribute__((address_space(4))) double cdbl;\n"
              "// a zero the compiler cannot see through, known to be wave-uniform\n"
              "__device__ __forceinline__ int opaque_zero()\n{\n"
              "  int z;\n  asm volatile(\"s_mov_b32 %0, 0\" : \"=s\"(z));\n"
              "  return __builtin_amdgcn_readfirstlane(z);\n}\n";
+        o << "// molar masses: W_k, 1/W_k, R/W_k\n__constant__ double MWTAB[3 * NS] = {";
+        for (int t = 0; t < 3; ++t)
+            for (int k = 0; k < ns; ++k) {
+                const double W = m.species[k].W;
+                o << lit(t == 0 ? W : (t == 1 ? 1.0 / W : kRu / W)) << ((t == 2 && k == ns - 1) ? "};\n" : ", ");
+            }
         o << "__constant__ double THERMO[NS][2][20] = {\n";
         for (int k = 0; k < ns; ++k) {
             o << "  {";
@@ -95,14 +104,27 @@ struct Emitter {
         o << "};\n\n";
     }
 
+    // The NASA-7 polynomials at T from the table row c, as power sums over
+    // T, T^2, T^3, T^4 (computed once per evaluation) so every step is a
+    // multiply-accumulate with the scalar coefficient as a multiplicand (one
+    // instruction; a scalar addend would cost two extra moves).
+    void poly_body(const std::string& sfx, bool with_dcp)
+    {
+        o << "        { double a = T4 * c[4]; a = fma(T3, c[3], a); a = fma(T2, c[2], a); a = fma(T, c[1], a);\n"
+             "          cpR" << sfx << " = a + c[0]; }\n"
+             "        { double a = T4 * c[8]; a = fma(T3, c[7], a); a = fma(T2, c[6], a); a = fma(T, c[5], a);\n"
+             "          a = fma(iT, c[9], a); HRT" << sfx << " = a + c[0]; }\n"
+             "        { double a = T4 * c[13]; a = fma(T3, c[12], a); a = fma(T2, c[11], a); a = fma(T, c[10], a);\n"
+             "          a = fma(lnT, c[0], a); a = fma(-iT, c[9], a); G" << sfx << " = a + c[14]; }\n";
+        if (with_dcp)
+            o << "        { double a = T3 * c[18]; a = fma(T2, c[17], a); a = fma(T, c[16], a); dcpR" << sfx
+              << " = a + c[15]; }\n";
+    }
+
     void thermo_one(const std::string& base, const std::string& sfx, bool with_dcp)
     {
-        o << "        { cdbl* c = " << base << ";\n"
-             "          cpR" << sfx << " = c[0] + T*(c[1] + T*(c[2] + T*(c[3] + T*c[4])));\n"
-             "          HRT" << sfx << " = c[0] + T*(c[5] + T*(c[6] + T*(c[7] + T*c[8]))) + c[9]*iT;\n"
-             "          G" << sfx << " = c[0]*lnT + T*(c[10] + T*(c[11] + T*(c[12] + T*c[13]))) + (c[14] - c[9]*iT);\n";
-        if (with_dcp)
-            o << "          dcpR" << sfx << " = c[15] + T*(c[16] + T*(c[17] + T*c[18]));\n";
+        o << "        { cdbl* c = " << base << ";\n";
+        poly_body(sfx, with_dcp);
         o << "        }\n";
     }
 
@@ -126,11 +148,8 @@ struct Emitter {
             for (int k = 0; k < ns; ++k) {
                 if (m.species[k].tmid != tm) continue;
                 const std::string idx = "[" + std::to_string(k) + "]";
-                o << "      { cdbl* c = TH + " << k * 40 << " + r;\n"
-                     "        cpR" << idx << " = c[0] + T*(c[1] + T*(c[2] + T*(c[3] + T*c[4])));\n"
-                     "        HRT" << idx << " = c[0] + T*(c[5] + T*(c[6] + T*(c[7] + T*c[8]))) + c[9]*iT;\n"
-                     "        G" << idx << " = c[0]*lnT + T*(c[10] + T*(c[11] + T*(c[12] + T*c[13]))) + (c[14] - c[9]*iT);\n";
-                if (with_dcp) o << "        dcpR" << idx << " = c[15] + T*(c[16] + T*(c[17] + T*c[18]));\n";
+                o << "      { cdbl* c = TH + " << k * 40 << " + r;\n";
+                poly_body(idx, with_dcp);
                 o << "      }\n";
             }
             o << "    } else {\n";
@@ -160,15 +179,17 @@ struct Emitter {
         o << "  const int z = opaque_zero();\n"
              "  cdbl* TH = (cdbl*)&THERMO[0][0][0] + z;\n"
              "  cdbl* P = (cdbl*)par + z;\n"
+             "  cdbl* MW = (cdbl*)&MWTAB[0] + z;\n"
              "  const double T = y[0];\n"
              "  const double lnT = log(T);\n"
              "  const double iT = 1.0 / T;\n"
+             "  const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;\n"
              "  double cpR[NS], HRT[NS], G[NS];\n";
         if (jac) o << "  double dcpR[NS];\n";
         thermo(jac);
         o << "  double sig = 0.0;\n";
         for (int k = 0; k < ns; ++k)
-            o << "  sig = fma(y[" << 1 + k << "], " << lit(1.0 / m.species[k].W) << ", sig);\n";
+            o << "  sig = fma(y[" << 1 + k << "], MW[" << ns + k << "], sig);\n";
         // rho = p / (R T sig); 1/rho = R T sig / p with 1/p given
         o << "  const double Wbar = 1.0 / sig;\n"
              "  const double rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
@@ -176,7 +197,7 @@ struct Emitter {
              "  const double ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
              "  double C[NS];\n";
         for (int k = 0; k < ns; ++k)
-            o << "  C[" << k << "] = rho * (y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W) << ");\n";
+            o << "  C[" << k << "] = rho * (y[" << 1 + k << "] * MW[" << ns + k << "]);\n";
         o << "  const double lnPRT = " << lit(std::log(kPatm / kRu)) << " - lnT;\n"
              "  double wd[NS];\n"
              "#pragma unroll\n  for (int k = 0; k < NS; ++k) wd[k] = 0.0;\n";
@@ -194,8 +215,10 @@ struct Emitter {
     {
         const auto& r = m.reactions[j];
         o << "  { // reaction " << j << "\n";
-        o << "    const double lnk = P[" << j << "] + P[" << nr + j << "]*lnT - P[" << 2 * nr + j
-          << "]*iT;\n";
+        // ln k = ln A + b ln T - (Ea/R) / T, one scalar operand per instruction
+        o << "    double lnk = lnT * P[" << nr + j << "];\n"
+             "    lnk = fma(-iT, P[" << 2 * nr + j << "], lnk);\n"
+             "    lnk = lnk + P[" << j << "];\n";
         // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
         std::string lnkc;
         for (auto& t : r.prod) lnkc += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
@@ -205,14 +228,14 @@ struct Emitter {
         const bool falloff = r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe;
         if (r.kind != RxnKind::Elementary) o << "    const double Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
-            o << "    const double kf = exp(lnk);\n"
-                 "    const double kr = exp(lnk - lnKc);\n";
+            o << "    const double kf = chem_math::exp_tang(lnk);\n"
+                 "    const double kr = chem_math::exp_tang(lnk - lnKc);\n";
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
-            o << "    const double kinf = exp(lnk);\n"
+            o << "    const double kinf = chem_math::exp_tang(lnk);\n"
                  "    const double lnr0 = " << lit(r.lnA0) << " + " << lit(r.b0) << "*lnT - "
               << lit(r.EaR0) << "*iT - lnk;\n"
-                 "    const double r0 = exp(lnr0);\n"
+                 "    const double r0 = chem_math::exp_tang(lnr0);\n"
                  "    const double Pr = r0 * Mc;\n"
                  "    const bool floored = !(Pr >= 1e-300);\n"
                  "    const double logPr = floored ? -300.0 : log10(Pr);\n";
@@ -249,7 +272,7 @@ struct Emitter {
             }
             o << "    const double ipr1 = 1.0 / (1.0 + Pr);\n"
                  "    const double kf = kinf * Pr * ipr1 * Fb;\n"
-                 "    const double iKc = exp(-lnKc);\n"
+                 "    const double iKc = chem_math::exp_tang(-lnKc);\n"
                  "    const double kr = kf * iKc;\n";
         }
         o << "    const double pf = " << side_product(r.reac) << ";\n"
@@ -320,7 +343,7 @@ struct Emitter {
         o << "  double hw = 0.0;\n";
         for (int k = 0; k < ns; ++k) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
         for (int k = 0; k < ns; ++k)
-            o << "  f[" << 1 + k << "] = " << lit(m.species[k].W) << " * irho * wd[" << k << "];\n";
+            o << "  f[" << 1 + k << "] = MW[" << k << "] * (irho * wd[" << k << "]);\n";
         o << "  f[0] = -" << lit(kRu) << " * T * hw * rcpinv;\n";
     }
 
@@ -328,13 +351,12 @@ struct Emitter {
     {
         o << "  double cpm = 0.0;\n";
         for (int k = 0; k < ns; ++k)
-            o << "  cpm = fma(cpR[" << k << "], y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W) << ", cpm);\n";
+            o << "  cpm = fma(cpR[" << k << "], y[" << 1 + k << "] * MW[" << ns + k << "], cpm);\n";
         o << "  const double cp = " << lit(kRu) << " * cpm;\n";
         if (jac) {
             o << "  double dcpm = 0.0;\n";
             for (int k = 0; k < ns; ++k)
-                o << "  dcpm = fma(dcpR[" << k << "], y[" << 1 + k << "] * " << lit(1.0 / m.species[k].W)
-                  << ", dcpm);\n";
+                o << "  dcpm = fma(dcpR[" << k << "], y[" << 1 + k << "] * MW[" << ns + k << "], dcpm);\n";
             o << "  const double dcp = " << lit(kRu) << " * dcpm;\n";
         }
     }
@@ -366,19 +388,20 @@ struct Emitter {
         for (int mm = 0; mm < ns; ++mm) {
             o << "  { double HJ = 0.0";
             for (int k = 0; k < ns; ++k) o << " + HRT[" << k << "]*J[" << 1 + k << "][" << 1 + mm << "]";
-            o << ";\n    J[0][" << 1 + mm << "] = -RT * (rho*HJ - Wbar*HS) * " << lit(1.0 / m.species[mm].W)
-              << " * rcpinv - fT * (cpR[" << mm << "] * " << lit(kRu / m.species[mm].W) << " * icp - Wbar * "
-              << lit(1.0 / m.species[mm].W) << "); }\n";
+            o << ";\n    double t = fma(rho, HJ, -Wbar*HS) * (-RT * rcpinv);\n"
+                 "    double u = fma(cpR[" << mm << "], icp * " << lit(kRu) << ", -Wbar);\n"
+                 "    J[0][" << 1 + mm << "] = fma(-fT, u, t) * MW[" << ns + mm << "]; }\n";
         }
         o << "  J[0][0] = -" << lit(kRu) << " * (cpw + T*HwT - HS) * rcpinv - fT * (dcp * icp - iT);\n";
         for (int k = 0; k < ns; ++k) {
-            const double Wk = m.species[k].W;
-            o << "  { const double g = f[" << 1 + k << "] - " << lit(Wk) << " * Sk[" << k << "] * irho;\n";
+            // J_km = (1/W_m)(W_k Jc_km + Wbar g_k), g_k = f_k - W_k S_k / rho
+            o << "  { const double g = fma(-MW[" << k << "], Sk[" << k << "] * irho, f[" << 1 + k << "]);\n"
+                 "    const double wg = Wbar * g;\n";
             for (int mm = 0; mm < ns; ++mm)
-                o << "    J[" << 1 + k << "][" << 1 + mm << "] = " << lit(Wk / m.species[mm].W) << " * J["
-                  << 1 + k << "][" << 1 + mm << "] + Wbar * " << lit(1.0 / m.species[mm].W) << " * g;\n";
-            o << "    J[" << 1 + k << "][0] = " << lit(Wk) << " * irho * (J[" << 1 + k << "][0] - Sk[" << k
-              << "] * iT) + f[" << 1 + k << "] * iT; }\n";
+                o << "    J[" << 1 + k << "][" << 1 + mm << "] = fma(J[" << 1 + k << "][" << 1 + mm << "], MW[" << k
+                  << "], wg) * MW[" << ns + mm << "];\n";
+            o << "    J[" << 1 + k << "][0] = fma(MW[" << k << "] * irho, J[" << 1 + k << "][0] - Sk[" << k
+              << "] * iT, f[" << 1 + k << "] * iT); }\n";
         }
     }
 

@@ -288,6 +288,7 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
 extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateArgs a)
 {
     using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     extern __shared__ double lds[];
@@ -311,6 +312,7 @@ struct EvalArgs {
 extern "C" __global__ void __launch_bounds__(64, 1) chem_eval(EvalArgs a)
 {
     using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     double y[N], f[N];
@@ -349,6 +351,7 @@ struct FixedStepArgs {
 extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArgs a)
 {
     using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     extern __shared__ double lds[];
@@ -411,11 +414,19 @@ extern "C" __global__ void __launch_bounds__(256) chem_reduce_stats(const int* _
 }
 
 // ---- persistent form ----
-// Cells of all fields form one global index space [0, total), split into nq
-// contiguous queues (one per XCD).  Each wave pulls cells from the queue of
-// its XCD (workgroups are dealt to the XCDs round-robin), moves on to the
-// next queue when its own is empty, and refills idle lanes at substep
-// boundaries, so a lane never waits for the slowest cell of its wave.
+// Cells of all fields form one global index space [0, total).  Optionally the
+// cells are first ordered by predicted cost, most expensive first (a counting
+// sort over 256 cost buckets): the cost of a cell is either given by the
+// caller (e.g. its substep count in the previous call, the measured load the
+// paper balances on) or predicted from its state by one source-term
+// evaluation (the RMS of f dt / (atol + rtol |y|)).  Positions are dealt to
+// nq queues (one per XCD) interleaved, so every queue sees the same cost mix.
+// Each wave pulls cells from the queue of its XCD (workgroups are dealt to
+// the XCDs round-robin), moves on to the next queue when its own is empty,
+// and refills idle lanes at substep boundaries, so a lane never waits for the
+// slowest cell of its wave.
+constexpr int kCostBuckets = 256;
+
 struct FieldDesc {
     double* T;
     const double* p;
@@ -423,40 +434,136 @@ struct FieldDesc {
     int* status;
     int* nacc;
     int* nrej;
+    const int* cost;          // nullable: per-cell cost hint
     long ncell;
     long start;               // first global index of this field
 };
 
 struct PersistBlock {
     long total;
-    long qchunk;              // cells per queue
     int nfield;
     int nq;
-    int refill;               // idle lanes that trigger a refill
-    int pad;
+    int refill;
+    int order;                // 1: cost-ordered
     chem::StepArgs step;
+    unsigned char* bucket;    // [total] cost bucket per cell
+    int* perm;                // [total] cells by descending cost
+    unsigned* hist;           // [kCostBuckets]
+    unsigned* cursor;         // [kCostBuckets]
     FieldDesc fields[1];      // nfield entries
 };
 
-extern "C" __global__ void chem_reset_heads(unsigned long long* heads, int nq)
+__device__ __forceinline__ int field_of(const PersistBlock* __restrict__ blk, long g)
 {
-    const int i = threadIdx.x;
-    if (i < nq) heads[i] = 0ull;
+    int f = 0;
+    while (f + 1 < blk->nfield && blk->fields[f + 1].start <= g) ++f;
+    return f;
 }
 
-template <int WAVES_PER_SIMD>
+extern "C" __global__ void chem_reset_heads(const PersistBlock* __restrict__ blk, unsigned long long* heads)
+{
+    const int i = threadIdx.x;
+    if (i < 64) heads[i] = 0ull;
+    for (int b = i; b < kCostBuckets; b += blockDim.x) blk->hist[b] = 0u;
+}
+
+extern "C" __global__ void __launch_bounds__(256) chem_order_key(const PersistBlock* __restrict__ blk,
+                                                                const double* __restrict__ par)
+{
+    using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    __shared__ unsigned h[kCostBuckets];
+    for (int b = threadIdx.x; b < kCostBuckets; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    if (blk->order) {
+        const StepArgs st = blk->step;
+        for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < blk->total;
+             g += (long)gridDim.x * blockDim.x) {
+            const FieldDesc& fd = blk->fields[field_of(blk, g)];
+            const long l = g - fd.start;
+            double key;
+            if (fd.cost) {
+                key = 12.0 * log2(1.0 + (double)max(fd.cost[l], 0));
+            } else {
+                double y[N], f[N];
+                y[0] = fd.T[l];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) y[1 + k] = fd.Y[l * NS + k];
+                const double p = fd.p[l];
+                mech::rhs(par, p, 1.0 / p, y, f);
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double e = f[k] * st.dt / (st.atol + st.rtol * fabs(y[k]));
+                    s = fma(e, e, s);
+                }
+                key = 4.0 * log2(1.0 + sqrt(s * (1.0 / N)));
+            }
+            const int b = (key >= 0.0) ? (key < kCostBuckets - 1 ? (int)key : kCostBuckets - 1)
+                                       : kCostBuckets - 1;    // NaN: schedule early
+            blk->bucket[g] = (unsigned char)b;
+            atomicAdd(&h[b], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kCostBuckets; b += blockDim.x)
+        if (h[b]) atomicAdd(&blk->hist[b], h[b]);
+}
+
+// start positions of the buckets, most expensive bucket first
+extern "C" __global__ void __launch_bounds__(kCostBuckets) chem_order_scan(const PersistBlock* __restrict__ blk)
+{
+    __shared__ unsigned s[kCostBuckets];
+    const int t = threadIdx.x;
+    s[t] = blk->hist[kCostBuckets - 1 - t];
+    __syncthreads();
+    for (int off = 1; off < kCostBuckets; off <<= 1) {
+        const unsigned v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    const int b = kCostBuckets - 1 - t;
+    blk->cursor[b] = s[t] - blk->hist[b];         // exclusive
+}
+
+// Cells to their positions: within each chunk of blockDim cells, ranks come
+// from LDS atomics and one global atomic per bucket reserves the chunk's
+// share (the cheap cells of a field mostly share one bucket, so per-cell
+// global atomics would serialise on it).
+extern "C" __global__ void __launch_bounds__(256) chem_order_scatter(const PersistBlock* __restrict__ blk)
+{
+    if (!blk->order) return;
+    __shared__ unsigned cnt[kCostBuckets], off[kCostBuckets];
+    const long total = blk->total;
+    for (long base = (long)blockIdx.x * blockDim.x; base < total; base += (long)gridDim.x * blockDim.x) {
+        for (int b = threadIdx.x; b < kCostBuckets; b += blockDim.x) cnt[b] = 0u;
+        __syncthreads();
+        const long g = base + threadIdx.x;
+        const int b = g < total ? (int)blk->bucket[g] : -1;
+        const unsigned r = b >= 0 ? atomicAdd(&cnt[b], 1u) : 0u;
+        __syncthreads();
+        for (int k = threadIdx.x; k < kCostBuckets; k += blockDim.x)
+            if (cnt[k]) off[k] = atomicAdd(&blk->cursor[k], cnt[k]);
+        __syncthreads();
+        if (b >= 0) blk->perm[off[b] + r] = (int)g;
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__ blk,
                                                 unsigned long long* __restrict__ heads,
                                                 const double* __restrict__ par)
 {
     using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
     const long total = blk->total;
-    const long qchunk = blk->qchunk;
     const int nq = blk->nq;
-    const int nfield = blk->nfield;
     const int refill = blk->refill;
+    const bool ordered = blk->order != 0;
+    const int* __restrict__ perm = blk->perm;
     const StepArgs step = blk->step;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -482,12 +589,14 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
                 unsigned long long old = 0;
                 if (lane == leader) old = atomicAdd(&heads[q], (unsigned long long)need);
                 old = __shfl(old, leader);
-                const long qbeg = (long)q * qchunk;
-                const long qsize = (total - qbeg < qchunk) ? total - qbeg : qchunk;
+                // queue q holds positions q, q + nq, q + 2 nq, ... below total
+                const long qsize = (total - q + nq - 1) / nq;
                 const long avail = qsize - (long)old;
                 const int got = avail <= 0 ? 0 : (avail < (long)need ? (int)avail : need);
-                if (!have && rank >= assigned && rank < assigned + got)
-                    my_g = qbeg + (long)old + (rank - assigned);
+                if (!have && rank >= assigned && rank < assigned + got) {
+                    const long pos = ((long)old + (rank - assigned)) * nq + q;
+                    my_g = ordered ? (long)perm[pos] : pos;
+                }
                 assigned += got;
                 if (got < need) {
                     q = (q + 1 == nq) ? 0 : q + 1;
@@ -496,10 +605,8 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
                 need -= got;
             }
             if (my_g >= 0) {
-                int f = 0;
-                while (f + 1 < nfield && blk->fields[f + 1].start <= my_g) ++f;
-                fidx = f;
-                const FieldDesc& fd = blk->fields[f];
+                fidx = field_of(blk, my_g);
+                const FieldDesc& fd = blk->fields[fidx];
                 local = my_g - fd.start;
                 cell_begin(c, fd.T[local], fd.p[local], fd.Y + local * NS, 1, step.dt);
                 have = true;
@@ -524,7 +631,7 @@ extern "C" __global__ void __launch_bounds__(256, 1)
 chem_persistent(const PersistBlock* __restrict__ blk, unsigned long long* __restrict__ heads,
                 const double* __restrict__ par)
 {
-    persistent_body<1>(blk, heads, par);
+    persistent_body(blk, heads, par);
 }
 
 // gather every stride-th cell of the global index space into contiguous
@@ -538,9 +645,7 @@ extern "C" __global__ void __launch_bounds__(256) chem_gather_sample(const Persi
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const long g = i * stride;
-    int f = 0;
-    while (f + 1 < blk->nfield && blk->fields[f + 1].start <= g) ++f;
-    const FieldDesc& fd = blk->fields[f];
+    const FieldDesc& fd = blk->fields[field_of(blk, g)];
     const long l = g - fd.start;
     T[i] = fd.T[l];
     p[i] = fd.p[l];

@@ -1,0 +1,49 @@
+// math.hip -- device math used by the generated source terms.
+//
+// exp(x) by Tang's table-driven method (P. T. P. Tang, "Table-driven
+// implementation of the exponential function in IEEE floating-point
+// arithmetic", ACM TOMS 15(2), 1989), with 64 table entries:
+//     x = (64 m + j) ln2/64 + r,  |r| <= ln2/128,
+//     exp(x) = 2^m * 2^(j/64) * exp(r),
+// exp(r) - 1 from its degree-5 Taylor polynomial (truncation below 4e-17 on
+// that interval), 2^(j/64) from a table held in LDS.  The reduction
+// r = x - n ln2/64 uses a two-part ln2/64 through fused multiply-adds.  No
+// special-case branches: NaN propagates, arguments beyond the double range
+// give 0 or inf through ldexp, +-inf give NaN (a failed step for the caller).
+// The table values (2^(j/64) rounded to double) come with the generated code
+// as EXP2_J64.
+
+namespace chem_math {
+
+__shared__ double exp2_j64[64];
+
+// Copy the table into LDS.  Every thread of the workgroup must call this
+// (it contains a barrier) before the first exp_tang.
+__device__ __forceinline__ void exp_table_init(const double* __restrict__ src)
+{
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) exp2_j64[i] = src[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double exp_tang(double x)
+{
+    constexpr double kInvL = 92.33248261689366;            // 64 / ln 2
+    constexpr double kL1 = 0.010830424696249145;           // ln2/64, leading part
+    constexpr double kL2 = 3.623510646634843e-19;          // ln2/64 - kL1
+    const double nd = __builtin_rint(x * kInvL);
+    const int n = (int)nd;
+    double r = fma(-nd, kL1, x);
+    r = fma(-nd, kL2, r);
+    // p = exp(r) - 1; scalar constants enter as multiplicands or through a
+    // separate add (an FMA with a scalar addend costs two extra moves)
+    double q = r * (1.0 / 120.0);
+    q = q + (1.0 / 24.0);
+    q = q * r;
+    q = q + (1.0 / 6.0);
+    q = fma(r, q, 0.5);
+    const double p = fma(r * r, q, r);
+    const double s = exp2_j64[n & 63];
+    return ldexp(fma(s, p, s), n >> 6);
+}
+
+}  // namespace chem_math

@@ -16,11 +16,11 @@
 
 namespace chemmi {
 
-#include "_device_source.inc"   // kIntegratorSource: csrc/device/integrator.hip
+#include "_device_source.inc"   // kMathSource, kIntegratorSource: csrc/device/*.hip
 
 std::string device_source(const std::string& mechanism_code)
 {
-    return mechanism_code + "\n" + std::string(kIntegratorSource);
+    return std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kIntegratorSource);
 }
 
 const std::vector<std::string>& compile_options()

@@ -87,10 +87,14 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_persistent", &d.f_persistent);
         rc = rc ? rc : load_function(d.module, "chem_reset_heads", &d.f_reset);
         rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
+        rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
+        rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
+        rc = rc ? rc : load_function(d.module, "chem_order_scatter", &d.f_oscatter);
         if (rc) return rc;
         HIPCHECK(hipMalloc((void**)&d.par, sizeof(double) * std::max<size_t>(m->params.size(), 1)), "hipMalloc par");
         HIPCHECK(hipMalloc((void**)&d.stats, sizeof(unsigned long long) * 4), "hipMalloc stats");
         HIPCHECK(hipMalloc((void**)&d.heads, sizeof(unsigned long long) * 64), "hipMalloc heads");
+        HIPCHECK(hipMalloc((void**)&d.hist, sizeof(unsigned) * 2 * kCostBuckets), "hipMalloc hist");
         HIPCHECK(hipEventCreate(&d.ev0), "hipEventCreate");
         HIPCHECK(hipEventCreate(&d.ev1), "hipEventCreate");
         d.par_version = 0;
@@ -117,7 +121,7 @@ void release_device_state(chem_mechanism* m)
         for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
         if (d.capture_stream) (void)hipStreamDestroy(d.capture_stream);
         for (void* p : {(void*)d.par, (void*)d.stats, (void*)d.heads, (void*)d.block_buf,
-                        (void*)d.cells_i32, (void*)d.sample})
+                        (void*)d.cells_i32, (void*)d.sample, (void*)d.bucket, (void*)d.perm, (void*)d.hist})
             if (p) (void)hipFree(p);
         if (d.ev0) (void)hipEventDestroy(d.ev0);
         if (d.ev1) (void)hipEventDestroy(d.ev1);
@@ -225,9 +229,9 @@ int grid_of(const DeviceState& d, const LaunchConfig& c)
     return std::max(1, waves * 64 / c.block);
 }
 
-// Launch [reset queue heads -> persistent kernel] as a graph built once per
-// launch shape (the kernels read everything call-specific from the field
-// table, whose device address is fixed).
+// Launch [reset -> cost keys -> bucket offsets -> permutation -> persistent
+// kernel] as a graph built once per launch shape (the kernels read everything
+// call-specific from the field table, whose device address is fixed).
 int launch_graph(DeviceState& d, const LaunchConfig& c, hipStream_t stream)
 {
     auto it = d.graphs.find(c);
@@ -235,16 +239,23 @@ int launch_graph(DeviceState& d, const LaunchConfig& c, hipStream_t stream)
         if (!d.capture_stream) HIPCHECK(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "stream");
         hipGraph_t g;
         HIPCHECK(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-        struct { unsigned long long* h; int n; } ra{d.heads, 64};
-        size_t rs = sizeof ra;
-        void* rcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &ra, HIP_LAUNCH_PARAM_BUFFER_SIZE, &rs, HIP_LAUNCH_PARAM_END};
-        hipError_t e = hipModuleLaunchKernel(d.f_reset, 1, 1, 1, 64, 1, 1, 0, d.capture_stream, nullptr, rcfg);
+        struct { const char* blk; unsigned long long* h; } ra{d.block_buf, d.heads};
+        struct { const char* blk; const double* par; } ka{d.block_buf, d.par};
+        struct { const char* blk; } sa{d.block_buf};
         struct { const char* blk; unsigned long long* heads; const double* par; } pa{d.block_buf, d.heads, d.par};
-        size_t ps = sizeof pa;
-        void* pcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &pa, HIP_LAUNCH_PARAM_BUFFER_SIZE, &ps, HIP_LAUNCH_PARAM_END};
+        auto launch = [&](hipFunction_t f, unsigned grid, unsigned block, unsigned shmem, void* args,
+                          size_t size) {
+            void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
+                           HIP_LAUNCH_PARAM_END};
+            return hipModuleLaunchKernel(f, grid, 1, 1, block, 1, 1, shmem, d.capture_stream, nullptr, cfg);
+        };
+        const unsigned sweep = (unsigned)d.num_cu * 4;   // grid-stride sweeps over all cells
+        hipError_t e = launch(d.f_reset, 1, 256, 0, &ra, sizeof ra);
+        if (e == hipSuccess) e = launch(d.f_okey, sweep, 256, 0, &ka, sizeof ka);
+        if (e == hipSuccess) e = launch(d.f_oscan, 1, kCostBuckets, 0, &sa, sizeof sa);
+        if (e == hipSuccess) e = launch(d.f_oscatter, sweep, 256, 0, &sa, sizeof sa);
         if (e == hipSuccess)
-            e = hipModuleLaunchKernel(d.f_persistent, grid_of(d, c), 1, 1, c.block, 1, 1, d.stage_lds(c.block),
-                                      d.capture_stream, nullptr, pcfg);
+            e = launch(d.f_persistent, grid_of(d, c), c.block, d.stage_lds(c.block), &pa, sizeof pa);
         hipError_t e2 = hipStreamEndCapture(d.capture_stream, &g);
         if (e != hipSuccess) return hip_error(e, "capture persistent launch");
         if (e2 != hipSuccess) return hip_error(e2, "end capture");
@@ -263,7 +274,10 @@ int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<Fie
 {
     total = 0;
     for (int f = 0; f < nfield; ++f) total += fv[f].ncell;
+    if (total >= (int64_t(1) << 31)) return set_error(CHEM_E_INVAL, "more than 2^31 - 1 cells in one launch");
     if (int rc = grow(&d.cells_i32, &d.cells_cap, 3 * (size_t)total, "workspace")) return rc;
+    if (int rc = grow(&d.bucket, &d.bucket_cap, (size_t)total, "workspace")) return rc;
+    if (int rc = grow(&d.perm, &d.perm_cap, (size_t)total, "workspace")) return rc;
     out.clear();
     int64_t start = 0;
     for (int f = 0; f < nfield; ++f) {
@@ -274,6 +288,7 @@ int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<Fie
         x.status = fv[f].status ? fv[f].status : d.cells_i32 + start;
         x.nacc = fv[f].nacc ? fv[f].nacc : d.cells_i32 + total + start;
         x.nrej = fv[f].nrej ? fv[f].nrej : d.cells_i32 + 2 * total + start;
+        x.cost = fv[f].cost;
         x.ncell = (long)fv[f].ncell;
         x.start = (long)start;
         out.push_back(x);
@@ -283,16 +298,19 @@ int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<Fie
 }
 
 PersistHeader header_for(const DeviceState& d, int64_t total, int nfield, const LaunchConfig& c,
-                         const StepArgs& s)
+                         const StepArgs& s, int order)
 {
-    (void)d;
     PersistHeader h{};
     h.total = (long)total;
     h.nq = 8;                                        // one queue per XCD
-    h.qchunk = (long)((total + h.nq - 1) / h.nq);
     h.nfield = nfield;
     h.refill = std::max(1, std::min(64, c.refill));
+    h.order = order == CHEM_ORDER_NATURAL ? 0 : 1;
     h.step = s;
+    h.bucket = d.bucket;
+    h.perm = d.perm;
+    h.hist = d.hist;
+    h.cursor = d.hist + kCostBuckets;
     return h;
 }
 
@@ -317,7 +335,7 @@ int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fi
     double* sp = sT + count;
     double* sY = sp + count;
     double* wT = d.sample + per;                      // working copy
-    PersistHeader h = header_for(d, total, (int)fields.size(), LaunchConfig{}, s);
+    PersistHeader h = header_for(d, total, (int)fields.size(), LaunchConfig{}, s, o.order);
     if (int rc = write_block(d, fields, h, stream)) return rc;
     struct { const char* blk; long stride; long count; double* T; double* p; double* Y; } ga{
         d.block_buf, (long)stride, (long)count, sT, sp, sY};
@@ -334,12 +352,12 @@ int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fi
     // count <= total, so the per-cell workspace (3 * total) already fits the sample
     std::vector<FieldDesc> sf(1);
     sf[0] = FieldDesc{wT, sp, wT + count, d.cells_i32, d.cells_i32 + count, d.cells_i32 + 2 * count,
-                      (long)count, 0};
+                      nullptr, (long)count, 0};
     for (const auto& c : cands) {
         HIPCHECK(hipMemcpyAsync(wT, sT, sizeof(double) * count, hipMemcpyDeviceToDevice, stream), "sample copy");
         HIPCHECK(hipMemcpyAsync(wT + count, sY, sizeof(double) * count * ns, hipMemcpyDeviceToDevice, stream),
                  "sample copy");
-        PersistHeader hs = header_for(d, count, 1, c, s);
+        PersistHeader hs = header_for(d, count, 1, c, s, o.order);
         if (int rc = write_block(d, sf, hs, stream)) return rc;
         HIPCHECK(hipEventRecord(d.ev0, stream), "event");
         if (int rc = launch_graph(d, c, stream)) return rc;
@@ -380,7 +398,7 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
     if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
     if (d->stage_lds(c.block) > d->lds_per_block)
         return set_error(CHEM_E_INVAL, "block too large for the stage vectors in LDS");
-    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s), stream)) return rc;
+    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, o.order), stream)) return rc;
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     if (int rc = launch_graph(*d, c, stream)) return rc;
     if (!stats) return 0;

@@ -65,18 +65,24 @@ struct FieldDesc {
     int* status;
     int* nacc;
     int* nrej;
+    const int* cost;
     long ncell;
     long start;
 };
 
+constexpr int kCostBuckets = 256;
+
 struct PersistHeader {
     long total;
-    long qchunk;
     int nfield;
     int nq;
     int refill;
-    int pad;
+    int order;
     StepArgs step;
+    unsigned char* bucket;
+    int* perm;
+    unsigned* hist;
+    unsigned* cursor;
 };
 
 struct Options {
@@ -88,6 +94,8 @@ struct Options {
     int block = 0;
     int waves_per_simd = 0;
     int refill = 0;
+    int order = CHEM_ORDER_COST;
+    const int32_t* const* cost = nullptr;
 };
 
 // One field of cells as the caller passed it.
@@ -100,6 +108,7 @@ struct FieldView {
     int32_t* nacc;
     int32_t* nrej;
     const double* h0;
+    const int32_t* cost;
 };
 
 struct LaunchConfig {
@@ -117,7 +126,8 @@ struct DeviceState {
     int num_cu = 256;
     hipModule_t module = nullptr;
     hipFunction_t f_plain = nullptr, f_eval = nullptr, f_fixed = nullptr, f_zero = nullptr,
-                  f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr;
+                  f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr,
+                  f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr;
     double* par = nullptr;               // 3 * nr device doubles
     uint64_t par_version = 0;
     unsigned long long* stats = nullptr; // 4 counters
@@ -128,6 +138,11 @@ struct DeviceState {
     size_t cells_cap = 0;
     double* sample = nullptr;            // autotune sample buffers
     size_t sample_cap = 0;
+    unsigned char* bucket = nullptr;     // cost ordering: bucket per cell
+    size_t bucket_cap = 0;
+    int* perm = nullptr;                 // cost ordering: cells by descending cost
+    size_t perm_cap = 0;
+    unsigned* hist = nullptr;            // [2 * kCostBuckets]: histogram, cursors
     hipStream_t capture_stream = nullptr;
     std::map<LaunchConfig, hipGraphExec_t> graphs;
     std::map<int64_t, LaunchConfig> tuned;  // by log2 bucket of the total cell count

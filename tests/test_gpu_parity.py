@@ -117,10 +117,12 @@ def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev):
     T, p, Y, reg = rde_field(mech_text("m9"), 256, 256, 101)
     Tp, Yp, sp, stp, nap, nrp = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL,
                                                return_counts=True)
-    for block, refill in ((64, 1), (256, 16), (128, 64)):
+    cost = (nap + nrp).contiguous()
+    for block, refill, extra in ((64, 1, {}), (256, 16, {"order": chem.ORDER_NATURAL}),
+                                 (128, 64, {"cost": cost}), (64, 8, {"cost": torch.zeros_like(cost)})):
         Tq, Yq, sq, stq, naq, nrq = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL,
                                                    ATOL, form=chem.FORM_PERSISTENT, block=block,
-                                                   refill=refill, return_counts=True)
+                                                   refill=refill, return_counts=True, **extra)
         assert torch.equal(Tp, Tq) and torch.equal(Yp, Yq)
         assert torch.equal(nap, naq) and torch.equal(nrp, nrq) and torch.equal(stp, stq)
         assert sq["accepted"] == sp["accepted"] and sq["cells"] == sp["cells"]
