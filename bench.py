@@ -23,6 +23,38 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12          # MI355X FP64 vector peak, FLOP/s
 RODAS4_STAGES = 6
+# The device code of a mechanism is generated from these files; HBM traffic
+# recorded under profiles/ applies only while their hash is unchanged.
+KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
+                  "paper_2508_16105_amd/csrc/device/math.hip",
+                  "paper_2508_16105_amd/csrc/codegen.cpp",
+                  "paper_2508_16105_amd/csrc/module.cpp"]
+TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
+
+
+def kernel_source_hash(mech_file: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES + [mech_file]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(mech_file: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE for the
+    current kernel sources, or None if the kernel changed since."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    want = kernel_source_hash(mech_file)
+    if f"kernel source hash: {want}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("| HBM bytes per launch |"):
+            return float(line.strip("| \n").split("|")[-1])
+    return None
 
 
 def flops_per_substep(ns: int, nr: int, s: int = RODAS4_STAGES) -> float:
@@ -70,7 +102,10 @@ def main():
     ap.add_argument("--workload", default="rde1m")
     ap.add_argument("--cpu-sample", type=float, default=0.05)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="persistent,persistent_history,persistent_natural,plain")
+    ap.add_argument("--forms", default="persistent,persistent_adjacent,persistent_history,"
+                                        "persistent_natural,plain")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 512 MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (cells are "
@@ -79,6 +114,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8}))
+        return
     import paper_2508_16105_amd as chem
     from workloads import WORKLOADS, mech_path, mech_text
     from workloads.states import rde_field
@@ -95,16 +139,24 @@ def main():
     stream = torch.cuda.current_stream()
     fper = flops_per_substep(mech.ns, mech.nr)
     # persistent: cells started most-expensive-first, cost predicted from the state;
-    # persistent_history: cost = each cell's substep count in the previous call on
-    # the same input (an upper bound for history-based ordering);
+    # persistent_adjacent: cost = each cell's substep count in the adjacent flow
+    # step of the same field (the field one dt later), as a time-stepping solver
+    # has it from its previous step;
+    # persistent_history: cost = substep counts of this very step (upper bound);
     # persistent_natural: index order; plain: one launch, one cell per lane.
     forms = {"persistent": (chem.FORM_PERSISTENT, {}),
+             "persistent_adjacent": (chem.FORM_PERSISTENT, {"adjacent": True}),
              "persistent_history": (chem.FORM_PERSISTENT, {"history": True}),
              "persistent_natural": (chem.FORM_PERSISTENT, {"order": chem.ORDER_NATURAL}),
              "plain": (chem.FORM_PLAIN, {})}
     _, _, _, _, na0, nr0 = chem.integrate(mech, T0, pg, Y0, w["dt"], w["rtol"], w["atol"],
                                           form=chem.FORM_PLAIN, return_counts=True)
     prev_cost = (na0 + nr0).contiguous()
+    T1, Y1, _ = chem.integrate(mech, T0, pg, Y0, w["dt"], w["rtol"], w["atol"], form=chem.FORM_PLAIN)
+    _, _, _, _, na1, nr1 = chem.integrate(mech, T1, pg, Y1, w["dt"], w["rtol"], w["atol"],
+                                          form=chem.FORM_PLAIN, return_counts=True)
+    adjacent_cost = (na1 + nr1).contiguous()
+    del T1, Y1
 
     results = {}
     for name in args.forms.split(","):
@@ -112,6 +164,8 @@ def main():
         kw = {}
         if extra.get("history"):
             kw["cost"] = prev_cost
+        if extra.get("adjacent"):
+            kw["cost"] = adjacent_cost
         if "order" in extra:
             kw["order"] = extra["order"]
 
@@ -166,7 +220,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": r["achieved_tflops"], "peak": PEAK_FP64_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": r["achieved_tflops"] / (PEAK_FP64_VALU / 1e12),
-                     "traffic": None,
+                     "traffic": recorded_traffic(os.path.relpath(mech_path(w["mech"]), ROOT))
+                     if head in ("persistent", "persistent_adjacent", "persistent_history") else None,
                      "kernel": "chem_persistent" if head == "persistent" else "chem_plain",
                      "kernel_ms": r["kernel_ms"],
                      "flops_per_substep": fper, "substeps_per_launch": r["substeps"]},
