@@ -166,15 +166,25 @@ int chem_integrate_batched(const chem_mechanism *m, int nfield, double *const *T
                            double dt, double rtol, double atol, const chem_options *opt,
                            chem_stats *stats, void *stream);
 
-/* Discrete adjoint of the frozen-step map y0 -> y(dt): the accepted step
-   sizes of the forward solve are held fixed and every RODAS4 step is
-   differentiated exactly.  Device inputs: T0, p, Y0 (the start state),
-   gT[ncell], gY[ncell * ns] (dL/dT_end, dL/dY_end).  Device outputs: gT0,
-   gY0 (dL/dT0, dL/dY0 per cell) and g_lnA, g_b, g_Ea [n_reactions]: dL with
-   respect to each reaction's ln A, b and Ea (J/mol), summed over cells in a
-   fixed order (deterministic).  T_end/Y_end (nullable device) receive the
-   forward result.  The forward solve stores its state every
-   opt->checkpoint_every accepted steps and recomputes in between. */
+/* Discrete adjoint of the frozen-step map y0 -> y(dt) of the chemistry step
+   above (the paper defines the step, eqs. (20)-(21), not its derivative; the
+   construction follows the Rosenbrock adjoints of Sandu, Daescu & Carmichael,
+   Atmos. Environ. 37 (2003)): the accepted step sizes of the forward solve are held fixed and every RODAS4
+   step is differentiated exactly, stage by stage (transposed LU solves, the
+   Jacobian at each stage point, and the derivative of the step matrix's
+   Jacobian along each stage vector).  Device inputs: T0, p, Y0 (the start
+   state), gT[ncell], gY[ncell * ns] (dL/dT_end, dL/dY_end).  Device outputs:
+   gT0, gY0 (dL/dT0, dL/dY0 per cell) and g_lnA, g_b, g_Ea [n_reactions]: dL
+   with respect to each reaction's ln A, b and Ea (J/mol) of the main rate,
+   summed over cells in a fixed order (bitwise reproducible).  T_end/Y_end
+   (device, both or neither) receive the forward result, bitwise equal to
+   chem_integrate's.  The call first runs a sizing pass, then stores each
+   cell's state every opt->checkpoint_every (1..16, default 4) accepted steps
+   and recomputes in between; it allocates its arena (8 bytes per accepted
+   step plus one state per checkpoint per cell, and 24 n_reactions bytes per
+   cell) for the call and synchronises the stream.  Returns
+   CHEM_E_CELL_FAILED if a cell failed (stats or not): such cells get NaN
+   gT0/gY0 and add nothing to the parameter gradients. */
 int chem_integrate_adjoint(const chem_mechanism *m, int64_t ncell, const double *T0,
                            const double *p, const double *Y0, double dt, double rtol,
                            double atol, const double *gT, const double *gY, double *gT0,

@@ -171,9 +171,10 @@ def step_fixed(mech: Mechanism, T, p, Y, h, rtol=1e-8, atol=1e-12, stream=None):
 
 
 def integrate_adjoint(mech: Mechanism, T0, p, Y0, dt, rtol, atol, gT, gY, *, stats=True,
-                      stream=None, checkpoint_every=0, **opts):
+                      stream=None, checkpoint_every=0, allow_failed=False, **opts):
     """Discrete adjoint of the frozen-step map.  Returns
-    (gT0, gY0, g_lnA, g_b, g_Ea, T_end, Y_end, stats)."""
+    (gT0, gY0, g_lnA, g_b, g_Ea, T_end, Y_end, stats).  Failed cells (with
+    allow_failed) get NaN gT0/gY0 and add nothing to the parameter gradients."""
     torch = _torch()
     n = T0.shape[0]
     for t, nm, sh in ((T0, "T0", (n,)), (p, "p", (n,)), (Y0, "Y0", (n, mech.ns)),
@@ -187,10 +188,11 @@ def integrate_adjoint(mech: Mechanism, T0, p, Y0, dt, rtol, atol, gT, gY, *, sta
     Ye = torch.empty((n, mech.ns), dtype=torch.float64, device=dev)
     s = _lib.Stats() if stats else None
     o = _options(checkpoint_every=checkpoint_every, **opts)
-    _lib.check(_lib.lib().chem_integrate_adjoint(
+    rc = _lib.lib().chem_integrate_adjoint(
         mech.h, n, _ptr(T0), _ptr(p), _ptr(Y0), float(dt), float(rtol), float(atol), _ptr(gT),
         _ptr(gY), _ptr(gT0), _ptr(gY0), _ptr(ga), _ptr(gb), _ptr(ge), _ptr(Te), _ptr(Ye),
-        C.byref(o), C.byref(s) if s is not None else None, _stream(stream)))
+        C.byref(o), C.byref(s) if s is not None else None, _stream(stream))
+    _lib.check(rc, allow=(-6,) if allow_failed else ())
     return gT0, gY0, ga, gb, ge, Te, Ye, (s.as_dict() if s is not None else None)
 
 

@@ -283,10 +283,37 @@ int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double
                            chem_stats* stats, void* stream)
 {
     g_last_error.clear();
-    (void)mc; (void)ncell; (void)T0; (void)p; (void)Y0; (void)dt; (void)rtol; (void)atol; (void)gT;
-    (void)gY; (void)gT0; (void)gY0; (void)g_lnA; (void)g_b; (void)g_Ea; (void)T_end; (void)Y_end;
-    (void)opt; (void)stats; (void)stream;
-    return set_error(CHEM_E_UNSUPPORTED, "adjoint not built yet");
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (int rc = check_device_ptrs({{g_lnA, "g_lnA"}, {g_b, "g_b"}, {g_Ea, "g_Ea"}})) return rc;
+    if (ncell > 0)
+        if (int rc = check_device_ptrs({{T0, "T0"}, {p, "p"}, {Y0, "Y0"}, {gT, "gT"}, {gY, "gY"},
+                                        {gT0, "gT0"}, {gY0, "gY0"}}))
+            return rc;
+    if ((T_end && !is_device_ptr(T_end)) || (Y_end && !is_device_ptr(Y_end)))
+        return set_error(CHEM_E_INVAL, "T_end/Y_end is not a device pointer");
+    if (!T_end != !Y_end) return set_error(CHEM_E_INVAL, "give both T_end and Y_end or neither");
+    Options o = resolve_options(opt);
+    if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    const int ns = m->data.ns();
+    double *Te = T_end, *Ye = Y_end;
+    void* own = nullptr;
+    if (!Te && ncell > 0) {
+        hipError_t e = hipMalloc(&own, sizeof(double) * (size_t)ncell * (ns + 1));
+        if (e != hipSuccess) return hip_error(e, "hipMalloc T_end/Y_end");
+        Te = (double*)own;
+        Ye = Te + ncell;
+    }
+    int rc = run_adjoint(m, ncell, T0, p, Y0, dt, rtol, atol, gT, gY, gT0, gY0, g_lnA, g_b, g_Ea, Te, Ye, o,
+                         stats, (hipStream_t)stream);
+    if (own) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipFree(own);
+    }
+    return rc;
 }
 
 }  // extern "C"

@@ -110,14 +110,14 @@ struct Emitter {
     // instruction; a scalar addend would cost two extra moves).
     void poly_body(const std::string& sfx, bool with_dcp)
     {
-        o << "        { double a = T4 * c[4]; a = fma(T3, c[3], a); a = fma(T2, c[2], a); a = fma(T, c[1], a);\n"
+        o << "        { S a = T4 * c[4]; a = fma(T3, c[3], a); a = fma(T2, c[2], a); a = fma(T, c[1], a);\n"
              "          cpR" << sfx << " = a + c[0]; }\n"
-             "        { double a = T4 * c[8]; a = fma(T3, c[7], a); a = fma(T2, c[6], a); a = fma(T, c[5], a);\n"
+             "        { S a = T4 * c[8]; a = fma(T3, c[7], a); a = fma(T2, c[6], a); a = fma(T, c[5], a);\n"
              "          a = fma(iT, c[9], a); HRT" << sfx << " = a + c[0]; }\n"
-             "        { double a = T4 * c[13]; a = fma(T3, c[12], a); a = fma(T2, c[11], a); a = fma(T, c[10], a);\n"
+             "        { S a = T4 * c[13]; a = fma(T3, c[12], a); a = fma(T2, c[11], a); a = fma(T, c[10], a);\n"
              "          a = fma(lnT, c[0], a); a = fma(-iT, c[9], a); G" << sfx << " = a + c[14]; }\n";
         if (with_dcp)
-            o << "        { double a = T3 * c[18]; a = fma(T2, c[17], a); a = fma(T, c[16], a); dcpR" << sfx
+            o << "        { S a = T3 * c[18]; a = fma(T2, c[17], a); a = fma(T, c[16], a); dcpR" << sfx
               << " = a + c[15]; }\n";
     }
 
@@ -156,7 +156,7 @@ struct Emitter {
             for (int k = 0; k < ns; ++k) {
                 if (m.species[k].tmid != tm) continue;
                 const std::string idx = "[" + std::to_string(k) + "]";
-                o << "      { double cpR_l, HRT_l, G_l, dcpR_l, cpR_h, HRT_h, G_h, dcpR_h;\n";
+                o << "      { S cpR_l, HRT_l, G_l, dcpR_l, cpR_h, HRT_h, G_h, dcpR_h;\n";
                 thermo_one("TH + " + std::to_string(k * 40), "_l", with_dcp);
                 thermo_one("TH + " + std::to_string(k * 40 + 20), "_h", with_dcp);
                 o << "        cpR" << idx << " = below ? cpR_l : cpR_h;\n"
@@ -180,26 +180,26 @@ struct Emitter {
              "  cdbl* TH = (cdbl*)&THERMO[0][0][0] + z;\n"
              "  cdbl* P = (cdbl*)par + z;\n"
              "  cdbl* MW = (cdbl*)&MWTAB[0] + z;\n"
-             "  const double T = y[0];\n"
-             "  const double lnT = log(T);\n"
-             "  const double iT = 1.0 / T;\n"
-             "  const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;\n"
-             "  double cpR[NS], HRT[NS], G[NS];\n";
-        if (jac) o << "  double dcpR[NS];\n";
+             "  const S T = y[0];\n"
+             "  const S lnT = log(T);\n"
+             "  const S iT = 1.0 / T;\n"
+             "  const S T2 = T * T, T3 = T2 * T, T4 = T2 * T2;\n"
+             "  S cpR[NS], HRT[NS], G[NS];\n";
+        if (jac) o << "  S dcpR[NS];\n";
         thermo(jac);
-        o << "  double sig = 0.0;\n";
+        o << "  S sig = 0.0;\n";
         for (int k = 0; k < ns; ++k)
             o << "  sig = fma(y[" << 1 + k << "], MW[" << ns + k << "], sig);\n";
         // rho = p / (R T sig); 1/rho = R T sig / p with 1/p given
-        o << "  const double Wbar = 1.0 / sig;\n"
-             "  const double rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
-             "  const double irho = " << lit(kRu) << " * T * sig * ip;\n"
-             "  const double ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
-             "  double C[NS];\n";
+        o << "  const S Wbar = 1.0 / sig;\n"
+             "  const S rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
+             "  const S irho = " << lit(kRu) << " * T * sig * ip;\n"
+             "  const S ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
+             "  S C[NS];\n";
         for (int k = 0; k < ns; ++k)
             o << "  C[" << k << "] = rho * (y[" << 1 + k << "] * MW[" << ns + k << "]);\n";
-        o << "  const double lnPRT = " << lit(std::log(kPatm / kRu)) << " - lnT;\n"
-             "  double wd[NS];\n"
+        o << "  const S lnPRT = " << lit(std::log(kPatm / kRu)) << " - lnT;\n"
+             "  S wd[NS];\n"
              "#pragma unroll\n  for (int k = 0; k < NS; ++k) wd[k] = 0.0;\n";
     }
 
@@ -211,12 +211,14 @@ struct Emitter {
         return s;
     }
 
-    void reaction(int j, bool jac)
+    // mode 0: source terms; 1: source terms and Jacobian; 2: parameter products
+    void reaction(int j, int mode)
     {
+        const bool jac = mode == 1, vjp = mode == 2;
         const auto& r = m.reactions[j];
         o << "  { // reaction " << j << "\n";
         // ln k = ln A + b ln T - (Ea/R) / T, one scalar operand per instruction
-        o << "    double lnk = lnT * P[" << nr + j << "];\n"
+        o << "    S lnk = lnT * P[" << nr + j << "];\n"
              "    lnk = fma(-iT, P[" << 2 * nr + j << "], lnk);\n"
              "    lnk = lnk + P[" << j << "];\n";
         // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
@@ -224,67 +226,85 @@ struct Emitter {
         for (auto& t : r.prod) lnkc += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
         for (auto& t : r.reac) lnkc += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
         if (r.dnu != 0) lnkc += " + " + lit(r.dnu) + "*lnPRT";
-        o << "    const double lnKc = 0.0" << lnkc << ";\n";
+        o << "    const S lnKc = 0.0" << lnkc << ";\n";
         const bool falloff = r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe;
-        if (r.kind != RxnKind::Elementary) o << "    const double Mc = " << third_body_sum(r) << ";\n";
+        if (r.kind != RxnKind::Elementary) o << "    const S Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
-            o << "    const double kf = chem_math::exp_tang(lnk);\n"
-                 "    const double kr = chem_math::exp_tang(lnk - lnKc);\n";
+            o << "    const S kf = chem_math::exp_tang(lnk);\n"
+                 "    const S kr = chem_math::exp_tang(lnk - lnKc);\n";
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
-            o << "    const double kinf = chem_math::exp_tang(lnk);\n"
-                 "    const double lnr0 = " << lit(r.lnA0) << " + " << lit(r.b0) << "*lnT - "
+            o << "    const S kinf = chem_math::exp_tang(lnk);\n"
+                 "    const S lnr0 = " << lit(r.lnA0) << " + " << lit(r.b0) << "*lnT - "
               << lit(r.EaR0) << "*iT - lnk;\n"
-                 "    const double r0 = chem_math::exp_tang(lnr0);\n"
-                 "    const double Pr = r0 * Mc;\n"
+                 "    const S r0 = chem_math::exp_tang(lnr0);\n"
+                 "    const S Pr = r0 * Mc;\n"
                  "    const bool floored = !(Pr >= 1e-300);\n"
-                 "    const double logPr = floored ? -300.0 : log10(Pr);\n";
+                 "    const S logPr = floored ? -300.0 : log10(Pr);\n";
             if (r.kind == RxnKind::Troe) {
-                o << "    const double e3 = exp(-T * " << lit(1.0 / r.T3) << ");\n"
-                     "    const double e1 = exp(-T * " << lit(1.0 / r.T1) << ");\n";
-                o << "    double Fc = " << lit(1.0 - r.alpha) << "*e3 + " << lit(r.alpha) << "*e1;\n";
-                if (jac)
-                    o << "    double dFc = " << lit(-(1.0 - r.alpha) / r.T3) << "*e3 + "
+                o << "    const S e3 = exp(-T * " << lit(1.0 / r.T3) << ");\n"
+                     "    const S e1 = exp(-T * " << lit(1.0 / r.T1) << ");\n";
+                o << "    S Fc = " << lit(1.0 - r.alpha) << "*e3 + " << lit(r.alpha) << "*e1;\n";
+                if (jac || vjp)
+                    o << "    S dFc = " << lit(-(1.0 - r.alpha) / r.T3) << "*e3 + "
                       << lit(-r.alpha / r.T1) << "*e1;\n";
                 if (r.has_T2) {
-                    o << "    const double e2 = exp(" << lit(-r.T2) << " * iT);\n"
+                    o << "    const S e2 = exp(" << lit(-r.T2) << " * iT);\n"
                          "    Fc += e2;\n";
-                    if (jac) o << "    dFc += " << lit(r.T2) << "*iT*iT*e2;\n";
+                    if (jac || vjp) o << "    dFc += " << lit(r.T2) << "*iT*iT*e2;\n";
                 }
-                o << "    const double logFc = log10(Fc);\n"
-                     "    const double tc = -0.4 - 0.67*logFc;\n"
-                     "    const double tn = 0.75 - 1.27*logFc;\n"
-                     "    const double tu = logPr + tc;\n"
-                     "    const double tden = tn - 0.14*tu;\n"
-                     "    const double tx = tu / tden;\n"
-                     "    const double opx2 = 1.0 + tx*tx;\n"
-                     "    const double logF = logFc / opx2;\n"
-                     "    const double Fb = exp(" << lit(std::log(10.0)) << " * logF);\n";
-                if (jac) {
-                    o << "    const double tg = -logFc * 2.0 * tx / (opx2*opx2);\n"
-                         "    const double dF_dPr = floored ? 0.0 : tg * tn / (tden*tden);\n"
-                         "    const double dF_dFc = 1.0/opx2 + tg * (-0.67*tn + 1.27*tu) / (tden*tden);\n"
-                         "    const double dlogFc_dT = dFc / (Fc * " << lit(std::log(10.0)) << ");\n";
+                o << "    const S logFc = log10(Fc);\n"
+                     "    const S tc = -0.4 - 0.67*logFc;\n"
+                     "    const S tn = 0.75 - 1.27*logFc;\n"
+                     "    const S tu = logPr + tc;\n"
+                     "    const S tden = tn - 0.14*tu;\n"
+                     "    const S tx = tu / tden;\n"
+                     "    const S opx2 = 1.0 + tx*tx;\n"
+                     "    const S logF = logFc / opx2;\n"
+                     "    const S Fb = exp(" << lit(std::log(10.0)) << " * logF);\n";
+                if (jac || vjp) {
+                    o << "    const S tg = -logFc * 2.0 * tx / (opx2*opx2);\n"
+                         "    const S dF_dPr = floored ? 0.0 : tg * tn / (tden*tden);\n"
+                         "    const S dF_dFc = 1.0/opx2 + tg * (-0.67*tn + 1.27*tu) / (tden*tden);\n"
+                         "    const S dlogFc_dT = dFc / (Fc * " << lit(std::log(10.0)) << ");\n";
                 }
             } else {
-                o << "    const double Fb = 1.0;\n";
-                if (jac) o << "    const double dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
+                o << "    const S Fb = 1.0;\n";
+                if (jac || vjp) o << "    const S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
             }
-            o << "    const double ipr1 = 1.0 / (1.0 + Pr);\n"
-                 "    const double kf = kinf * Pr * ipr1 * Fb;\n"
-                 "    const double iKc = chem_math::exp_tang(-lnKc);\n"
-                 "    const double kr = kf * iKc;\n";
+            o << "    const S ipr1 = 1.0 / (1.0 + Pr);\n"
+                 "    const S kf = kinf * Pr * ipr1 * Fb;\n"
+                 "    const S iKc = chem_math::exp_tang(-lnKc);\n"
+                 "    const S kr = kf * iKc;\n";
         }
-        o << "    const double pf = " << side_product(r.reac) << ";\n"
-             "    const double pr = " << side_product(r.prod) << ";\n"
-             "    const double fwd = kf * pf;\n"
-             "    const double rev = kr * pr;\n";
-        if (r.kind == RxnKind::ThirdBody) o << "    const double q = Mc * (fwd - rev);\n";
-        else o << "    const double q = fwd - rev;\n";
+        o << "    const S pf = " << side_product(r.reac) << ";\n"
+             "    const S pr = " << side_product(r.prod) << ";\n"
+             "    const S fwd = kf * pf;\n"
+             "    const S rev = kr * pr;\n";
+        if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * (fwd - rev);\n";
+        else o << "    const S q = fwd - rev;\n";
         // production rates
         std::vector<int> nu(ns, 0);
         for (auto& t : r.reac) nu[t.sp] -= t.nu;
         for (auto& t : r.prod) nu[t.sp] += t.nu;
+        if (vjp) {
+            // w . df/dq_j: species rows W_k nu_kj / rho, temperature row -R T dH_j/RT / (rho cp)
+            std::string ws, sh;
+            for (int k = 0; k < ns; ++k)
+                if (nu[k]) ws += " + " + lit(nu[k]) + "*(MW[" + std::to_string(k) + "]*w[" + std::to_string(1 + k) + "])";
+            for (int k = 0; k < ns; ++k)
+                if (nu[k]) sh += " + " + lit(nu[k]) + "*HRT[" + std::to_string(k) + "]";
+            o << "    const S wsum = (0.0" << ws << ") * irho - w[0] * (" << lit(kRu) << " * T) * (0.0" << sh
+              << ") * rcpinv;\n";
+            // d q / d ln A of the main rate (k_inf for falloff: P_r = k0 [M] / k_inf)
+            if (falloff) o << "    const S qA = q * (Pr * ipr1 - dF_dPr);\n";
+            else o << "    const S qA = q;\n";
+            o << "    const S g = wsum * qA;\n"
+                 "    gA[" << j << "] += g;\n"
+                 "    gb[" << j << "] += g * lnT;\n"
+                 "    gE[" << j << "] += g * (-iT * " << lit(1.0 / kRu) << ");\n  }\n";
+            return;
+        }
         for (int k = 0; k < ns; ++k)
             if (nu[k]) o << "    wd[" << k << "] = fma(" << lit(nu[k]) << ", q, wd[" << k << "]);\n";
         if (jac) {
@@ -292,18 +312,18 @@ struct Emitter {
             std::string sh;
             for (auto& t : r.prod) sh += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
             for (auto& t : r.reac) sh += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
-            o << "    const double dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
-            o << "    const double dlnkinf = (P[" << nr + j << "] + P[" << 2 * nr + j << "]*iT) * iT;\n";
+            o << "    const S dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
+            o << "    const S dlnkinf = (P[" << nr + j << "] + P[" << 2 * nr + j << "]*iT) * iT;\n";
             if (!falloff) {
-                o << "    const double dlnkf = dlnkinf;\n";
+                o << "    const S dlnkf = dlnkinf;\n";
             } else {
-                o << "    const double dlnk0 = (" << lit(r.b0) << " + " << lit(r.EaR0) << "*iT) * iT;\n"
-                     "    const double dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + "
+                o << "    const S dlnk0 = (" << lit(r.b0) << " + " << lit(r.EaR0) << "*iT) * iT;\n"
+                     "    const S dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + "
                   << lit(std::log(10.0)) << " * dF_dFc * dlogFc_dT;\n"
-                     "    const double dkdM = kinf * r0 * Fb * (ipr1*ipr1 + dF_dPr*ipr1);\n";
+                     "    const S dkdM = kinf * r0 * Fb * (ipr1*ipr1 + dF_dPr*ipr1);\n";
             }
             std::string fac = r.kind == RxnKind::ThirdBody ? "Mc * " : "";
-            o << "    const double dqT = " << fac << "(dlnkf * fwd - (dlnkf - dlnKc) * rev);\n";
+            o << "    const S dqT = " << fac << "(dlnkf * fwd - (dlnkf - dlnKc) * rev);\n";
             // d q / d C_m (dense over the species that enter)
             std::vector<std::string> dq(ns);
             for (int mm = 0; mm < ns; ++mm) {
@@ -320,9 +340,9 @@ struct Emitter {
                 dq[mm] = t;
             }
             // k_r = k_f / K_c, so both directions scale with d k_f / d[M]
-            if (falloff) o << "    const double dMterm = dkdM*(pf - iKc*pr);\n";
+            if (falloff) o << "    const S dMterm = dkdM*(pf - iKc*pr);\n";
             for (int mm = 0; mm < ns; ++mm)
-                if (!dq[mm].empty()) o << "    const double dq" << mm << " = " << dq[mm] << ";\n";
+                if (!dq[mm].empty()) o << "    const S dq" << mm << " = " << dq[mm] << ";\n";
             for (int k = 0; k < ns; ++k) {
                 if (!nu[k]) continue;
                 for (int mm = 0; mm < ns; ++mm)
@@ -338,9 +358,9 @@ struct Emitter {
     void rhs_tail()
     {
         // 1/(rho cp) = T sig / (p cpm)
-        o << "  const double icpm = 1.0 / cpm;\n"
-             "  const double rcpinv = T * sig * ip * icpm;\n";
-        o << "  double hw = 0.0;\n";
+        o << "  const S icpm = 1.0 / cpm;\n"
+             "  const S rcpinv = T * sig * ip * icpm;\n";
+        o << "  S hw = 0.0;\n";
         for (int k = 0; k < ns; ++k) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
         for (int k = 0; k < ns; ++k)
             o << "  f[" << 1 + k << "] = MW[" << k << "] * (irho * wd[" << k << "]);\n";
@@ -349,15 +369,15 @@ struct Emitter {
 
     void cp_sum(bool jac)
     {
-        o << "  double cpm = 0.0;\n";
+        o << "  S cpm = 0.0;\n";
         for (int k = 0; k < ns; ++k)
             o << "  cpm = fma(cpR[" << k << "], y[" << 1 + k << "] * MW[" << ns + k << "], cpm);\n";
-        o << "  const double cp = " << lit(kRu) << " * cpm;\n";
+        o << "  const S cp = " << lit(kRu) << " * cpm;\n";
         if (jac) {
-            o << "  double dcpm = 0.0;\n";
+            o << "  S dcpm = 0.0;\n";
             for (int k = 0; k < ns; ++k)
                 o << "  dcpm = fma(dcpR[" << k << "], y[" << 1 + k << "] * MW[" << ns + k << "], dcpm);\n";
-            o << "  const double dcp = " << lit(kRu) << " * dcpm;\n";
+            o << "  const S dcp = " << lit(kRu) << " * dcpm;\n";
         }
     }
 
@@ -372,31 +392,31 @@ struct Emitter {
         //   J_00 = -R (cpw + T HwT - HS) / (rho cp) - f_T (dcp / cp - 1/T)
         // where HJ_m = sum_k H_k/RT Jc_km, HS = sum_k H_k/RT S_k, HwT = sum_k H_k/RT wT_k,
         // cpw = sum_k cp_k/R wdot_k.
-        o << "  double Sk[NS];\n";
+        o << "  S Sk[NS];\n";
         for (int k = 0; k < ns; ++k) {
             o << "  Sk[" << k << "] = 0.0";
             for (int l = 0; l < ns; ++l) o << " + J[" << 1 + k << "][" << 1 + l << "]*C[" << l << "]";
             o << ";\n";
         }
-        o << "  double HS = 0.0, HwT = 0.0, cpw = 0.0;\n";
+        o << "  S HS = 0.0, HwT = 0.0, cpw = 0.0;\n";
         for (int k = 0; k < ns; ++k)
             o << "  HS = fma(HRT[" << k << "], Sk[" << k << "], HS); HwT = fma(HRT[" << k << "], J[" << 1 + k
               << "][0], HwT); cpw = fma(cpR[" << k << "], wd[" << k << "], cpw);\n";
-        o << "  const double fT = f[0];\n"
-             "  const double RT = " << lit(kRu) << " * T;\n"
-             "  const double icp = icpm * " << lit(1.0 / kRu) << ";\n";
+        o << "  const S fT = f[0];\n"
+             "  const S RT = " << lit(kRu) << " * T;\n"
+             "  const S icp = icpm * " << lit(1.0 / kRu) << ";\n";
         for (int mm = 0; mm < ns; ++mm) {
-            o << "  { double HJ = 0.0";
+            o << "  { S HJ = 0.0";
             for (int k = 0; k < ns; ++k) o << " + HRT[" << k << "]*J[" << 1 + k << "][" << 1 + mm << "]";
-            o << ";\n    double t = fma(rho, HJ, -Wbar*HS) * (-RT * rcpinv);\n"
-                 "    double u = fma(cpR[" << mm << "], icp * " << lit(kRu) << ", -Wbar);\n"
+            o << ";\n    S t = fma(rho, HJ, -Wbar*HS) * (-RT * rcpinv);\n"
+                 "    S u = fma(cpR[" << mm << "], icp * " << lit(kRu) << ", -Wbar);\n"
                  "    J[0][" << 1 + mm << "] = fma(-fT, u, t) * MW[" << ns + mm << "]; }\n";
         }
         o << "  J[0][0] = -" << lit(kRu) << " * (cpw + T*HwT - HS) * rcpinv - fT * (dcp * icp - iT);\n";
         for (int k = 0; k < ns; ++k) {
             // J_km = (1/W_m)(W_k Jc_km + Wbar g_k), g_k = f_k - W_k S_k / rho
-            o << "  { const double g = fma(-MW[" << k << "], Sk[" << k << "] * irho, f[" << 1 + k << "]);\n"
-                 "    const double wg = Wbar * g;\n";
+            o << "  { const S g = fma(-MW[" << k << "], Sk[" << k << "] * irho, f[" << 1 + k << "]);\n"
+                 "    const S wg = Wbar * g;\n";
             for (int mm = 0; mm < ns; ++mm)
                 o << "    J[" << 1 + k << "][" << 1 + mm << "] = fma(J[" << 1 + k << "][" << 1 + mm << "], MW[" << k
                   << "], wg) * MW[" << ns + mm << "];\n";
@@ -414,22 +434,31 @@ struct Emitter {
           << "constexpr int N = NS + 1;\n\n";
         // source terms only
         thermo_table();
-        o << "__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, double ip, "
-             "const double (&y)[N], double (&f)[N])\n{\n";
+        o << "template <class S>\n__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, "
+             "double ip, const S (&y)[N], S (&f)[N])\n{\n";
         prologue(false);
-        for (int j = 0; j < nr; ++j) reaction(j, false);
+        for (int j = 0; j < nr; ++j) reaction(j, 0);
         cp_sum(false);
         rhs_tail();
         o << "}\n\n";
         // source terms and Jacobian
-        o << "__device__ __forceinline__ void rhs_jac(const double* __restrict__ par, double p, double ip, "
-             "const double (&y)[N], double (&f)[N], double (&J)[N][N])\n{\n";
+        o << "template <class S>\n__device__ __forceinline__ void rhs_jac(const double* __restrict__ par, double p, "
+             "double ip, const S (&y)[N], S (&f)[N], S (&J)[N][N])\n{\n";
         o << "#pragma unroll\n  for (int i = 0; i < N; ++i)\n#pragma unroll\n    for (int j = 0; j < N; ++j) J[i][j] = 0.0;\n";
         prologue(true);
-        for (int j = 0; j < nr; ++j) reaction(j, true);
+        for (int j = 0; j < nr; ++j) reaction(j, 1);
         cp_sum(true);
         rhs_tail();
         chain_rule();
+        o << "}\n\n";
+        // parameter products: g += (df/dtheta)^T w for theta = (ln A, b, Ea [J/mol]) of each reaction
+        o << "template <class S>\n__device__ __forceinline__ void param_vjp(const double* __restrict__ par, double p, "
+             "double ip, const S (&y)[N], const double (&w)[N], S* __restrict__ gA, S* __restrict__ gb, "
+             "S* __restrict__ gE)\n{\n";
+        prologue(false);
+        cp_sum(false);
+        o << "  const S rcpinv = T * sig * ip / cpm;\n";
+        for (int j = 0; j < nr; ++j) reaction(j, 2);
         o << "}\n\n}  // namespace mech\n";
         return o.str();
     }

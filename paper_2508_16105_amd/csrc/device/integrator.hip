@@ -227,12 +227,12 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
 // accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
 // a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)
 // or 0.2; the final step is truncated to land on dt.
-__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
-                                             double* __restrict__ ul, int ls)
+__device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
+                                               double* __restrict__ ul, int ls)
 {
-    if (c.done) return;
-    if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return; }
-    if (c.h < a.hmin) { c.status = CELL_HMIN; c.done = true; return; }
+    if (c.done) return 0.0;
+    if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return 0.0; }
+    if (c.h < a.hmin) { c.status = CELL_HMIN; c.done = true; return 0.0; }
     bool last = false;
     double h = c.h;
     if (h >= a.dt - c.t) { h = a.dt - c.t; last = true; }
@@ -249,11 +249,12 @@ __device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__
         c.rej_last = false;
         ++c.nacc;
         if (last) c.done = true;
-    } else {
-        ++c.nrej;
-        c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
-        c.rej_last = true;
+        return h;
     }
+    ++c.nrej;
+    c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
+    c.rej_last = true;
+    return 0.0;
 }
 
 struct IntegrateArgs {
@@ -650,4 +651,246 @@ extern "C" __global__ void __launch_bounds__(256) chem_gather_sample(const Persi
     T[i] = fd.T[l];
     p[i] = fd.p[l];
     for (int k = 0; k < chem::NS; ++k) Y[i * chem::NS + k] = fd.Y[l * chem::NS + k];
+}
+
+
+// ---- discrete adjoint of the frozen-step map ----
+// For one RODAS4 step y -> y_new with M = I/(gamma h) - J(y), M u_s = f(Y_s) +
+// sum_{j<s} (c_sj/h) u_j, Y_s = y + sum_{j<s} a_sj u_j, y_new = y + sum m_s u_s,
+// the cotangent lambda of y_new gives, with u-bar_s = m_s lambda and stages in
+// reverse order,
+//     w_s = M^-T u-bar_s,   Ybar_s = J(Y_s)^T w_s,
+//     y-bar += Ybar_s,  u-bar_j += a_sj Ybar_s + (c_sj/h) w_s  (j < s),
+//     theta-bar += f_theta(Y_s)^T w_s,
+// and, through J(y) inside M, y-bar += sum_s D_{u_s}[J(y)^T w_s] and
+// theta-bar += sum_s D_{u_s}[f_theta(y)^T w_s] (dual numbers along u_s).
+namespace chem {
+
+__device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
+                                           double (&b)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double v = b[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) v = fma(-A[j][i], b[j], v);
+        b[i] = v * A[i][i];
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        double v = b[k];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) v = fma(-A[i][k], b[i], v);
+        b[k] = v;
+        if (swaps & (1u << k)) {
+            const int p = piv[k];
+#pragma unroll
+            for (int i = k + 1; i < N; ++i) {
+                const bool s = (p == i);
+                const double bk = b[k], bi = b[i];
+                b[k] = s ? bi : bk;
+                b[i] = s ? bk : bi;
+            }
+        }
+    }
+}
+
+__device__ __noinline__ void step_adjoint(const double* __restrict__ par, double p, double ip,
+                                          const double (&y)[N], double h, double (&lam)[N],
+                                          double* __restrict__ gA, double* __restrict__ gb,
+                                          double* __restrict__ gE)
+{
+    using chem_math::Dual;
+    double J0[N][N], M[N][N], f[N];
+    mech::rhs_jac(par, p, ip, y, f, J0);
+    const double ghinv = 1.0 / (h * Rodas4::gamma);
+    const double hinv = 1.0 / h;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) M[i][j] = (i == j ? ghinv : 0.0) - J0[i][j];
+    int piv[N];
+    bool ok;
+    const unsigned swaps = lu_factor(M, piv, ok);
+    double u[Rodas4::S][N], Ys[Rodas4::S][N];
+    for (int k = 0; k < N; ++k) { Ys[0][k] = y[k]; u[0][k] = f[k]; }
+    lu_solve(M, piv, swaps, u[0]);
+    for (int s = 1; s < Rodas4::S; ++s) {
+        double acc[N], fs[N];
+        for (int k = 0; k < N; ++k) {
+            double v = y[k], w = 0.0;
+            for (int j = 0; j < s; ++j) {
+                v = fma(RA[s][j], u[j][k], v);
+                w = fma(RC[s][j], u[j][k], w);
+            }
+            Ys[s][k] = v;
+            acc[k] = w;
+        }
+        mech::rhs(par, p, ip, Ys[s], fs);
+        for (int k = 0; k < N; ++k) u[s][k] = fma(acc[k], hinv, fs[k]);
+        lu_solve(M, piv, swaps, u[s]);
+    }
+    // reverse over the stages
+    const double mw[Rodas4::S] = {RA[5][0], RA[5][1], RA[5][2], RA[5][3], 1.0, 1.0};
+    double ub[Rodas4::S][N], w[Rodas4::S][N], yb[N];
+    for (int k = 0; k < N; ++k) {
+        yb[k] = lam[k];
+        for (int s = 0; s < Rodas4::S; ++s) ub[s][k] = mw[s] * lam[k];
+    }
+    for (int s = Rodas4::S - 1; s >= 0; --s) {
+        for (int k = 0; k < N; ++k) w[s][k] = ub[s][k];
+        lu_solve_t(M, piv, swaps, w[s]);
+        double Js[N][N], fs[N], Yb[N];
+        if (s == 0) {
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) Js[i][j] = J0[i][j];
+        } else {
+            mech::rhs_jac(par, p, ip, Ys[s], fs, Js);
+        }
+        for (int k = 0; k < N; ++k) {
+            double v = 0.0;
+            for (int i = 0; i < N; ++i) v = fma(Js[i][k], w[s][i], v);
+            Yb[k] = v;
+            yb[k] += v;
+        }
+        mech::param_vjp(par, p, ip, Ys[s], w[s], gA, gb, gE);
+        for (int j = 0; j < s; ++j)
+            for (int k = 0; k < N; ++k) ub[j][k] = fma(RA[s][j], Yb[k], fma(RC[s][j] * hinv, w[s][k], ub[j][k]));
+    }
+    // second-order terms at y, one dual evaluation per stage direction
+    for (int s = 0; s < Rodas4::S; ++s) {
+        Dual yd[N], fd[N], Jd[N][N];
+        for (int k = 0; k < N; ++k) yd[k] = Dual(y[k], u[s][k]);
+        mech::rhs_jac(par, p, ip, yd, fd, Jd);
+        for (int k = 0; k < N; ++k) {
+            double v = 0.0;
+            for (int i = 0; i < N; ++i) v = fma(Jd[i][k].d, w[s][i], v);
+            yb[k] += v;
+        }
+        Dual gAd[mech::NR], gbd[mech::NR], gEd[mech::NR];
+        for (int j = 0; j < mech::NR; ++j) { gAd[j] = 0.0; gbd[j] = 0.0; gEd[j] = 0.0; }
+        mech::param_vjp(par, p, ip, yd, w[s], gAd, gbd, gEd);
+        for (int j = 0; j < mech::NR; ++j) {
+            gA[j] += gAd[j].d;
+            gb[j] += gbd[j].d;
+            gE[j] += gEd[j].d;
+        }
+    }
+    for (int k = 0; k < N; ++k) lam[k] = yb[k];
+}
+
+}  // namespace chem
+
+struct AdjointArgs {
+    const double* par;
+    const double* T0;
+    const double* p;
+    const double* Y0;
+    long ncell;
+    const double* gT;
+    const double* gY;
+    double* gT0;
+    double* gY0;
+    double* gpar;          // [ncell][3 NR]: per-cell parameter gradients (ln A, b, Ea)
+    double* Tend;
+    double* Yend;
+    const long* off_h;     // first step size of each cell in hs
+    const long* off_ck;    // first checkpoint of each cell (in states of N doubles)
+    const int* nacc_fwd;   // accepted steps of the sizing pass
+    const double* h0;      // nullable: per-cell first step, else dt
+    double* hs;
+    double* ck;
+    int* status;
+    int* nacc;
+    int* nrej;
+    chem::StepArgs step;
+    int K;                 // accepted steps per checkpoint
+};
+
+extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
+{
+    using namespace chem;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= a.ncell) return;
+    extern __shared__ double lds[];
+    double* ul = lds + threadIdx.x;
+    const int ls = blockDim.x;
+    Cell c;
+    cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
+    double* hs = a.hs + a.off_h[cell];
+    double* ck = a.ck + a.off_ck[cell] * N;
+    const int cap = a.nacc_fwd[cell];
+    int stored = -1;
+    while (!c.done) {
+        if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
+            for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
+            stored = c.nacc;
+        }
+        const double hacc = cell_attempt(c, a.par, a.step, ul, ls);
+        if (hacc > 0.0) {
+            if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
+            hs[c.nacc - 1] = hacc;
+        }
+    }
+    cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
+    if (c.status == CELL_BADINPUT) {
+        a.Tend[cell] = a.T0[cell];
+        for (int k = 0; k < NS; ++k) a.Yend[cell * NS + k] = a.Y0[cell * NS + k];
+    }
+    double* g = a.gpar + cell * 3 * mech::NR;
+    double gA[mech::NR], gb[mech::NR], gE[mech::NR];
+    for (int j = 0; j < mech::NR; ++j) { gA[j] = 0.0; gb[j] = 0.0; gE[j] = 0.0; }
+    double lam[N];
+    lam[0] = a.gT[cell];
+    for (int k = 0; k < NS; ++k) lam[1 + k] = a.gY[cell * NS + k];
+    if (c.status != CELL_OK) {
+        a.gT0[cell] = __builtin_nan("");
+        for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = __builtin_nan("");
+        for (int j = 0; j < 3 * mech::NR; ++j) g[j] = 0.0;
+        return;
+    }
+    const int na = c.nacc;
+    const double p = c.p, ip = c.ip;
+    for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
+        const int first = seg * a.K;
+        const int last = min(na, first + a.K) - 1;
+        double ys[16][N];                     // the segment's states (K <= 16)
+        for (int k = 0; k < N; ++k) ys[0][k] = ck[seg * N + k];
+        for (int i = first; i < last; ++i) {
+            double yn[N], en;
+            ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
+            for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+        }
+        for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE);
+    }
+    a.gT0[cell] = lam[0];
+    for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = lam[1 + k];
+    for (int j = 0; j < mech::NR; ++j) {
+        g[j] = gA[j];
+        g[mech::NR + j] = gb[j];
+        g[2 * mech::NR + j] = gE[j];
+    }
+}
+
+// Parameter gradients summed over cells in a fixed order: one workgroup per
+// parameter; thread t adds cells t, t + 256, ... in turn, then a fixed tree.
+extern "C" __global__ void __launch_bounds__(256) chem_reduce_params(const double* __restrict__ gpar, long ncell,
+                                                                    int nparam, double* __restrict__ gA,
+                                                                    double* __restrict__ gb, double* __restrict__ gE)
+{
+    __shared__ double s[256];
+    const int q = blockIdx.x;
+    double v = 0.0;
+    for (long c = threadIdx.x; c < ncell; c += 256) v += gpar[c * nparam + q];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int nr = nparam / 3;
+        if (q < nr) gA[q] = s[0];
+        else if (q < 2 * nr) gb[q - nr] = s[0];
+        else gE[q - 2 * nr] = s[0];
+    }
 }

@@ -47,3 +47,69 @@ __device__ __forceinline__ double exp_tang(double x)
 }
 
 }  // namespace chem_math
+
+// ---- forward-mode dual numbers (value, derivative along one direction) ----
+// Used by the discrete adjoint for the second-order terms of a Rosenbrock
+// step: D_u [J(y)^T w] and D_u [f_theta(y)^T w] come from evaluating the
+// generated Jacobian and parameter products at y + eps u.
+namespace chem_math {
+
+struct Dual {
+    double v, d;
+    Dual() = default;
+    __device__ constexpr Dual(double x) : v(x), d(0.0) {}
+    __device__ constexpr Dual(double a, double b) : v(a), d(b) {}
+};
+
+__device__ __forceinline__ double value(double x) { return x; }
+__device__ __forceinline__ double value(const Dual& x) { return x.v; }
+__device__ __forceinline__ double tangent(double) { return 0.0; }
+__device__ __forceinline__ double tangent(const Dual& x) { return x.d; }
+
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b)
+{
+    const double q = a.v / b.v;
+    return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ Dual operator/(double a, Dual b)
+{
+    const double q = a / b.v;
+    return {q, -q * b.d / b.v};
+}
+__device__ __forceinline__ Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+__device__ __forceinline__ Dual& operator*=(Dual& a, Dual b) { return a = a * b; }
+__device__ __forceinline__ bool operator<(Dual a, double b) { return a.v < b; }
+__device__ __forceinline__ bool operator>=(Dual a, double b) { return a.v >= b; }
+__device__ __forceinline__ Dual fma(Dual a, Dual b, Dual c) { return {::fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d}; }
+__device__ __forceinline__ Dual fma(Dual a, double b, Dual c) { return {::fma(a.v, b, c.v), ::fma(a.d, b, c.d)}; }
+__device__ __forceinline__ Dual fma(double a, Dual b, Dual c) { return {::fma(a, b.v, c.v), ::fma(a, b.d, c.d)}; }
+__device__ __forceinline__ Dual fma(Dual a, Dual b, double c) { return {::fma(a.v, b.v, c), a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual fma(Dual a, double b, double c) { return {::fma(a.v, b, c), a.d * b}; }
+__device__ __forceinline__ Dual fma(double a, Dual b, double c) { return {::fma(a, b.v, c), a * b.d}; }
+__device__ __forceinline__ Dual fma(double a, double b, Dual c) { return {::fma(a, b, c.v), c.d}; }
+__device__ __forceinline__ Dual exp_tang(Dual x)
+{
+    const double e = exp_tang(x.v);
+    return {e, e * x.d};
+}
+__device__ __forceinline__ Dual exp(Dual x)
+{
+    const double e = ::exp(x.v);
+    return {e, e * x.d};
+}
+__device__ __forceinline__ Dual log(Dual x) { return {::log(x.v), x.d / x.v}; }
+__device__ __forceinline__ Dual log10(Dual x) { return {::log10(x.v), x.d / (x.v * 2.302585092994045684)}; }
+
+}  // namespace chem_math

@@ -90,6 +90,8 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
         rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
         rc = rc ? rc : load_function(d.module, "chem_order_scatter", &d.f_oscatter);
+        rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
+        rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
         if (rc) return rc;
         HIPCHECK(hipMalloc((void**)&d.par, sizeof(double) * std::max<size_t>(m->params.size(), 1)), "hipMalloc par");
         HIPCHECK(hipMalloc((void**)&d.stats, sizeof(unsigned long long) * 4), "hipMalloc stats");
@@ -428,6 +430,110 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
     *stats = tot;
     if (tot.failed) return set_error(CHEM_E_CELL_FAILED, std::to_string(tot.failed) + " cells failed");
     return 0;
+}
+
+// ---------------- discrete adjoint ----------------
+
+namespace {
+
+// Device temporaries of one adjoint call; freed after the stream drains.
+struct Scratch {
+    hipStream_t stream;
+    std::vector<void*> ptrs;
+    explicit Scratch(hipStream_t s) : stream(s) {}
+    ~Scratch()
+    {
+        (void)hipStreamSynchronize(stream);
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    int alloc(T** out, size_t count, const char* what)
+    {
+        *out = nullptr;
+        void* p = nullptr;
+        HIPCHECK(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)), what);
+        ptrs.push_back(p);
+        *out = (T*)p;
+        return 0;
+    }
+};
+
+}  // namespace
+
+int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double* p, const double* Y0,
+                double dt, double rtol, double atol, const double* gT, const double* gY, double* gT0,
+                double* gY0, double* g_lnA, double* g_b, double* g_Ea, double* T_end, double* Y_end,
+                const Options& o, chem_stats* stats, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    const int ns = m->data.ns(), n = ns + 1, nr = m->data.nr();
+    const int K = o.checkpoint_every;
+    if (K < 1 || K > 16) return set_error(CHEM_E_INVAL, "checkpoint_every must be 1..16");
+    if (ncell == 0) {   // parameter gradients are zero; nothing else to do
+        struct {
+            const double* g;
+            long n;
+            int np;
+            double *a, *b, *e;
+        } rp{nullptr, 0, 3 * nr, g_lnA, g_b, g_Ea};
+        return launch_1d(d->f_rparams, (int64_t)3 * nr * 256, 256, &rp, sizeof rp, stream, "chem_reduce_params");
+    }
+    Scratch s(stream);
+    double *Tw, *Yw;
+    int32_t* i32;
+    if (int rc = s.alloc(&Tw, ncell, "adjoint T")) return rc;
+    if (int rc = s.alloc(&Yw, (size_t)ncell * ns, "adjoint Y")) return rc;
+    if (int rc = s.alloc(&i32, 4 * (size_t)ncell, "adjoint counters")) return rc;
+    int32_t *st = i32, *na_fwd = i32 + ncell, *na = i32 + 2 * ncell, *nj = i32 + 3 * ncell;
+    // sizing pass: the accepted steps of every cell fix the arena offsets
+    HIPCHECK(hipMemcpyAsync(Tw, T0, sizeof(double) * ncell, hipMemcpyDeviceToDevice, stream), "copy T0");
+    HIPCHECK(hipMemcpyAsync(Yw, Y0, sizeof(double) * ncell * ns, hipMemcpyDeviceToDevice, stream), "copy Y0");
+    const StepArgs step = step_args(dt, rtol, atol, o);
+    IntegrateArgs ia{d->par, Tw, p, Yw, (long)ncell, o.h0, st, na_fwd, nj, step};
+    if (int rc = launch_1d(d->f_plain, ncell, 64, &ia, sizeof ia, stream, "chem_plain", d->stage_lds(64)))
+        return rc;
+    std::vector<int32_t> nacc_h(ncell);
+    HIPCHECK(hipMemcpyAsync(nacc_h.data(), na_fwd, sizeof(int32_t) * ncell, hipMemcpyDeviceToHost, stream),
+             "copy step counts");
+    HIPCHECK(hipStreamSynchronize(stream), "sync sizing pass");
+    std::vector<long> off(2 * (size_t)ncell);
+    long th = 0, tc = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        off[c] = th;
+        off[ncell + c] = tc;
+        const long k = std::max<int32_t>(nacc_h[c], 0);
+        th += k;
+        tc += (k + K - 1) / K;
+    }
+    long* off_d;
+    double *hs, *ck, *gpar;
+    if (int rc = s.alloc(&off_d, 2 * (size_t)ncell, "adjoint offsets")) return rc;
+    if (int rc = s.alloc(&hs, (size_t)th, "adjoint step sizes")) return rc;
+    if (int rc = s.alloc(&ck, (size_t)tc * n, "adjoint checkpoints")) return rc;
+    if (int rc = s.alloc(&gpar, (size_t)ncell * 3 * nr, "adjoint parameter gradients")) return rc;
+    HIPCHECK(hipMemcpyAsync(off_d, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, stream),
+             "copy offsets");
+    AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, T_end, Y_end, off_d,
+                   off_d + ncell, na_fwd, o.h0, hs, ck, st, na, nj, step, K};
+    HIPCHECK(hipEventRecord(d->ev0, stream), "event");
+    if (int rc = launch_1d(d->f_adjoint, ncell, 64, &aa, sizeof aa, stream, "chem_adjoint", d->stage_lds(64)))
+        return rc;
+    HIPCHECK(hipEventRecord(d->ev1, stream), "event");
+    struct {
+        const double* g;
+        long n;
+        int np;
+        double *a, *b, *e;
+    } rp{gpar, (long)ncell, 3 * nr, g_lnA, g_b, g_Ea};
+    if (int rc = launch_1d(d->f_rparams, (int64_t)3 * nr * 256, 256, &rp, sizeof rp, stream,
+                           "chem_reduce_params"))
+        return rc;
+    HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, d->ev0, d->ev1), "elapsed");
+    chem_stats local{};
+    return collect_stats(*d, st, na, nj, ncell, ms, stats ? stats : &local, stream);
 }
 
 }  // namespace chemmi

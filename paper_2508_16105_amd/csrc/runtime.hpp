@@ -58,6 +58,32 @@ struct FixedStepArgs {
     int* ok;
 };
 
+struct AdjointArgs {
+    const double* par;
+    const double* T0;
+    const double* p;
+    const double* Y0;
+    long ncell;
+    const double* gT;
+    const double* gY;
+    double* gT0;
+    double* gY0;
+    double* gpar;
+    double* Tend;
+    double* Yend;
+    const long* off_h;
+    const long* off_ck;
+    const int* nacc_fwd;
+    const double* h0;
+    double* hs;
+    double* ck;
+    int* status;
+    int* nacc;
+    int* nrej;
+    StepArgs step;
+    int K;
+};
+
 struct FieldDesc {
     double* T;
     const double* p;
@@ -127,7 +153,8 @@ struct DeviceState {
     hipModule_t module = nullptr;
     hipFunction_t f_plain = nullptr, f_eval = nullptr, f_fixed = nullptr, f_zero = nullptr,
                   f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr,
-                  f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr;
+                  f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr, f_adjoint = nullptr,
+                  f_rparams = nullptr;
     double* par = nullptr;               // 3 * nr device doubles
     uint64_t par_version = 0;
     unsigned long long* stats = nullptr; // 4 counters
@@ -185,5 +212,12 @@ int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, doub
 
 int run_persistent(chem_mechanism* m, const FieldView* fields, int nfield, double dt, double rtol,
                    double atol, const Options& o, chem_stats* stats, hipStream_t stream);
+
+// Discrete adjoint (see chem_integrate_adjoint); the arrays are as there, with
+// T_end/Y_end non-null.
+int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double* p, const double* Y0,
+                double dt, double rtol, double atol, const double* gT, const double* gY, double* gT0,
+                double* gY0, double* g_lnA, double* g_b, double* g_Ea, double* T_end, double* Y_end,
+                const Options& o, chem_stats* stats, hipStream_t stream);
 
 }  // namespace chemmi
