@@ -94,6 +94,123 @@ def cpu_baseline(T, p, Y, w, frac, seed=7):
                       f"{el:.2f} s wall"}
 
 
+def amr_leg(chem, torch, dev, steps):
+    """64 independent fields of log-uniform 10k-2M cells (28.0 M cells in all),
+    RDE-shaped states, for the 9- and the 13-species (third-body + Troe)
+    mechanism: one persistent work-stealing launch over all fields against one
+    plain launch per field, same tolerances.  Each timed step restores the
+    initial fields first (device-to-device copies, inside the timing)."""
+    from workloads import WORKLOADS, mech_path, mech_text
+    from workloads.states import amr_field_sizes, rde_field_n
+    w = WORKLOADS["amr64"]
+    sizes = amr_field_sizes(w["seed"], w["n_fields"])
+    out = {"workload": "amr64", "fields": len(sizes), "cells": int(sum(sizes)), "dt": w["dt"],
+           "rtol": w["rtol"], "atol": w["atol"]}
+    for name in w["mechs"]:
+        mech = chem.Mechanism(mech_path(name))
+        text = mech_text(name)
+        init, work = [], []
+        for i, n in enumerate(sizes):
+            T, p, Y, _ = rde_field_n(text, n, w["seed"] * 100 + i)
+            t = [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev) for a in (T, p, Y)]
+            init.append(t)
+            work.append([x.clone() for x in t])
+
+        def restore():
+            for (T0, _, Y0), (Tw, _, Yw) in zip(init, work):
+                Tw.copy_(T0)
+                Yw.copy_(Y0)
+
+        def persistent(stats=False):
+            return chem.integrate_batched(mech, [f[0] for f in work], [f[1] for f in work],
+                                          [f[2] for f in work], w["dt"], w["rtol"], w["atol"],
+                                          form=chem.FORM_PERSISTENT, stats=stats)
+
+        def plain():
+            for Tw, pw, Yw in work:
+                chem.integrate(mech, Tw, pw, Yw, w["dt"], w["rtol"], w["atol"], form=chem.FORM_PLAIN,
+                               inplace=True, stats=False)
+
+        restore()
+        st = persistent(stats=True)                      # autotunes on first use
+        res = {}
+        for form, fn in (("persistent", persistent), ("plain_per_field", plain)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                restore()
+                fn()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            res[form] = {"ms_per_step": ms, "cell_steps_per_s": out["cells"] / (ms * 1e-3)}
+        res["persistent_over_plain"] = res["plain_per_field"]["ms_per_step"] / res["persistent"]["ms_per_step"]
+        res["substeps"] = st["accepted"] + st["rejected"]
+        res["failed"] = st["failed"]
+        res["mechanism"] = f"{name} ({mech.ns} species, {mech.nr} reactions)"
+        out[name] = res
+        del init, work, mech
+        torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_leg(chem, torch, dev, steps, cpu_cells):
+    """The discrete adjoint on the 512 x 512 adjoint field (262,144 cells, dt
+    1e-8 s): L = sum over cells of T_end / 1000 K + Y_H2O,end; gradients with
+    respect to T0, Y0 and every reaction's ln A, b, Ea.  Times whole calls
+    (sizing pass, arena set-up, adjoint kernel, parameter reduction) against
+    the forward integration of the same field."""
+    from workloads import WORKLOADS, mech_path, mech_text
+    from workloads.states import parse_species, rde_field
+    w = WORKLOADS["adj256k"]
+    mech = chem.Mechanism(mech_path(w["mech"]))
+    T, p, Y, _ = rde_field(mech_text(w["mech"]), w["width"], w["height"], w["seed"])
+    n = len(T)
+    species = parse_species(mech_text(w["mech"]))[0]
+    gT = np.full(n, 1.0 / w["t_ref"])
+    gY = np.zeros((n, len(species)))
+    gY[:, species.index("H2O")] = 1.0
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    T0, p0, Y0, gTd, gYd = t(T), t(p), t(Y), t(gT), t(gY)
+    args = (mech, T0, p0, Y0, w["dt"], w["rtol"], w["atol"])
+    chem.integrate(*args, form=chem.FORM_PLAIN)                        # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, fst = chem.integrate(*args, form=chem.FORM_PLAIN)
+    fwd_ms = 1e3 * (time.perf_counter() - t0) / steps
+    chem.integrate_adjoint(*args, gTd, gYd)                            # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for _ in range(steps):
+        out = chem.integrate_adjoint(*args, gTd, gYd)
+        kms.append(out[7]["kernel_ms"])
+    adj_ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = out[7]
+    res = {"workload": "adj256k", "cells": n,
+           "mechanism": f"{w['mech']} ({mech.ns} species, {mech.nr} reactions)",
+           "dt": w["dt"], "params": 3 * mech.nr,
+           "ms_per_call": adj_ms, "adjoint_kernel_ms": float(np.mean(kms)),
+           "forward_ms": fwd_ms, "adjoint_over_forward": adj_ms / fwd_ms,
+           "cell_steps_per_s": n / (adj_ms * 1e-3),
+           "accepted": st["accepted"], "max_substeps_cell": st["max_substeps"],
+           "checkpoint_every": 4}
+    if cpu_cells:
+        import oracle
+        om = oracle.Mechanism(mech_path(w["mech"]))
+        idx = np.sort(np.random.default_rng(8).choice(n, cpu_cells, replace=False))
+        cores = host_cores()
+        t0 = time.perf_counter()
+        om.adjoint(T[idx], p[idx], Y[idx], w["dt"], w["rtol"], w["atol"], gT[idx], gY[idx],
+                   nthreads=cores)
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": cpu_cells / el, "unit": "cell-steps/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{cpu_cells} cells (uniform random sample of the field, "
+                                         f"seed 8), {el:.2f} s wall"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +221,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="persistent,persistent_adjacent,persistent_history,"
                                         "persistent_natural,plain")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--amr-only", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true")
+    ap.add_argument("--adjoint-cpu-cells", type=int, default=192)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -126,6 +248,14 @@ def main():
     import paper_2508_16105_amd as chem
     from workloads import WORKLOADS, mech_path, mech_text
     from workloads.states import rde_field
+
+    if args.amr_only:
+        print(json.dumps({"amr64": amr_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps))}))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps),
+                                                 0 if args.no_cpu else args.adjoint_cpu_cells)}))
+        return
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
@@ -232,6 +362,10 @@ def main():
         line["persistent_over_plain"] = results["plain"]["ms_per_step"] / results["persistent"]["ms_per_step"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
+    if not args.no_amr:
+        line["amr64"] = amr_leg(chem, torch, dev, 1)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else args.adjoint_cpu_cells)
     print(json.dumps(line))
 
 

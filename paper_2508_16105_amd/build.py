@@ -1,8 +1,8 @@
 """Build the chemistry library in-tree.
 
-1. Embed csrc/device/integrator.hip into the host library as a string
-   (the device code is compiled per mechanism, with the generated
-   mechanism-specific code in front of it, by hipRTC for gfx950).
+1. Embed csrc/device/*.hip into the host library as strings (the device
+   code is compiled per mechanism, with the generated mechanism-specific
+   code in front of it, by hipRTC for gfx950).
 2. Compile the host library libchemmi.so with hipcc (HIP runtime + hipRTC).
 3. Load each mechanism under workloads/mech so its gfx950 code object is
    compiled now and stored in the kernel cache beside the library.
@@ -18,14 +18,17 @@ PKG = pathlib.Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libchemmi.so"
 ROOT = PKG.parent
-LANE_MECHANISMS = ["m9", "m13"]     # one cell per lane
+PREBUILT_MECHANISMS = ["m9", "m13", "m32"]
+# also built in the wave-cooperative form (their lane form is the default)
+PREBUILT_WIDE = ["m9", "m13"]
 HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "codegen.cpp"]
 
 
 def embed_device_source():
     delim = "CHEMDEV"
     out = "// generated from device/*.hip by build.py; do not edit\n"
-    for var, name in (("kMathSource", "math.hip"), ("kIntegratorSource", "integrator.hip")):
+    for var, name in (("kMathSource", "math.hip"), ("kCommonSource", "common.hip"),
+                      ("kIntegratorSource", "integrator.hip"), ("kWideSource", "wide.hip")):
         src = (CSRC / "device" / name).read_text()
         assert f"){delim}\"" not in src
         out += f"static const char {var}[] = R\"{delim}(\n{src}){delim}\";\n"
@@ -51,8 +54,19 @@ def prebuild_mechanisms(names=None):
     sys.path.insert(0, str(ROOT))
     from paper_2508_16105_amd import _lib
     mdir = ROOT / "workloads" / "mech"
-    for nm in names or LANE_MECHANISMS:
+    for nm in names or PREBUILT_MECHANISMS:
         _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
+    if names is None:
+        old = os.environ.get("CHEM_LANE_MAX_SPECIES")
+        os.environ["CHEM_LANE_MAX_SPECIES"] = "0"
+        try:
+            for nm in PREBUILT_WIDE:
+                _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
+        finally:
+            if old is None:
+                del os.environ["CHEM_LANE_MAX_SPECIES"]
+            else:
+                os.environ["CHEM_LANE_MAX_SPECIES"] = old
 
 
 def prune_cache(since):

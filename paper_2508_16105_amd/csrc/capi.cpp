@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -22,7 +23,20 @@ using namespace chemmi;
 
 namespace {
 // a cell's state, Jacobian and LU factors live in one lane's registers
+// Mechanisms with up to this many species run one cell per lane (the cell's
+// Jacobian and LU factors in one lane's registers); larger ones run
+// wave-cooperatively.  CHEM_LANE_MAX_SPECIES overrides it at load time.
 constexpr int kMaxLaneSpecies = 20;
+
+int lane_max_species()
+{
+    const char* e = std::getenv("CHEM_LANE_MAX_SPECIES");
+    if (e && *e) {
+        const int v = std::atoi(e);
+        if (v >= 0) return std::min(v, kMaxLaneSpecies);
+    }
+    return kMaxLaneSpecies;
+}
 }  // namespace
 
 namespace chemmi {
@@ -103,11 +117,18 @@ int chem_load_mechanism(const char* path, chem_mechanism** out)
     auto m = std::make_unique<chem_mechanism>();
     std::string err;
     if (int rc = parse_mechanism(path, m->data, err)) return set_error(rc, err);
-    if (m->data.ns() > kMaxLaneSpecies)
-        return set_error(CHEM_E_UNSUPPORTED, "one-cell-per-lane kernels hold at most " +
-                                                 std::to_string(kMaxLaneSpecies) + " species");
+    if (m->data.ns() > CHEM_MAX_SPECIES)
+        return set_error(CHEM_E_UNSUPPORTED, "more than " + std::to_string(CHEM_MAX_SPECIES) + " species");
     m->params = pack_params(m->data);
-    m->source = device_source(generate_mechanism_source(m->data));
+    if (m->data.ns() <= lane_max_species()) {
+        m->source = device_source(generate_mechanism_source(m->data), false);
+    } else {
+        m->layout = wide_layout(m->data);
+        if (m->layout.G == 0)
+            return set_error(CHEM_E_UNSUPPORTED, "reaction with more than 3 terms on one side");
+        m->wide = true;
+        m->source = device_source(generate_wide_source(m->data, m->layout), true);
+    }
     if (int rc = build_code_object(m->source, m->code, err, &m->cache_file)) return set_error(rc, err);
     *out = m.release();
     return CHEM_OK;
@@ -170,6 +191,9 @@ int chem_eval_source(const chem_mechanism* mc, int64_t ncell, const double* T, c
     DeviceState* d;
     if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
     EvalArgs a{d->par, T, p, Y, (long)ncell, f, J};
+    if (m->wide)
+        return launch_1d(d->f_eval, ncell * m->layout.G, 64, &a, sizeof a, (hipStream_t)stream, "chem_eval",
+                         m->layout.lds_bytes());
     return launch_1d(d->f_eval, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_eval");
 }
 
@@ -181,6 +205,7 @@ int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, co
     auto* m = const_cast<chem_mechanism*>(mc);
     if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
     if (int rc = check_tolerances(h, rtol, atol)) return rc;
+    if (m->wide) return set_error(CHEM_E_UNSUPPORTED, "fixed steps are not built for the wave-cooperative form");
     if (ncell == 0) return CHEM_OK;
     if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {ynew, "ynew"},
                                     {errnorm, "errnorm"}, {ok, "ok"}}))
@@ -287,6 +312,7 @@ int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double
     if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
     if (int rc = check_tolerances(dt, rtol, atol)) return rc;
     if (stats) std::memset(stats, 0, sizeof *stats);
+    if (m->wide) return set_error(CHEM_E_UNSUPPORTED, "the adjoint is not built for the wave-cooperative form");
     if (int rc = check_device_ptrs({{g_lnA, "g_lnA"}, {g_b, "g_b"}, {g_Ea, "g_Ea"}})) return rc;
     if (ncell > 0)
         if (int rc = check_device_ptrs({{T0, "T0"}, {p, "p"}, {Y0, "Y0"}, {gT, "gT"}, {gY, "gY"},

@@ -9,6 +9,7 @@
 // they can change without recompiling; every other constant is a literal.
 #include "codegen.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <sstream>
@@ -467,5 +468,146 @@ struct Emitter {
 }  // namespace
 
 std::string generate_mechanism_source(const MechanismData& m) { return Emitter(m).run(); }
+
+WideLayout wide_layout(const MechanismData& m)
+{
+    WideLayout w;
+    const int ns = m.ns(), nr = m.nr(), n = ns + 1;
+    if (n > 64) {
+        w.G = 0;
+        return w;
+    }
+    w.G = 16;
+    while (w.G < n) w.G *= 2;
+    w.maxt = 1;
+    for (const auto& r : m.reactions) w.maxt = std::max<int>(w.maxt, (int)std::max(r.reac.size(), r.prod.size()));
+    if (w.maxt > 3) {
+        w.G = 0;
+        return w;
+    }
+    w.nslot = 2 * w.maxt;
+    w.pw = w.nslot + 2;
+    w.jw = (ns + 1) % 2 ? ns + 1 : ns + 2;
+    w.l_y = 0;
+    w.l_c = w.l_y + n;
+    w.l_g = w.l_c + ns;
+    w.l_h = w.l_g + ns;
+    w.l_q = w.l_h + ns;
+    w.l_p = w.l_q + nr;
+    w.l_j = w.l_p + nr * w.pw;
+    w.l_t0 = w.l_j + ns * w.jw;
+    w.lds_cell = w.l_t0 + ns;
+    return w;
+}
+
+std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
+{
+    Emitter e(m);
+    std::ostringstream& o = e.o;
+    const int ns = m.ns(), nr = m.nr();
+    o << "// generated mechanism tables (wave-cooperative form): " << m.name << " (" << ns << " species, " << nr
+      << " reactions)\n"
+      << "namespace mech {\n"
+      << "constexpr int NS = " << ns << ";\n"
+      << "constexpr int NR = " << nr << ";\n"
+      << "constexpr int N = NS + 1;\n"
+      << "constexpr int G = " << w.G << ";            // lanes per cell\n"
+      << "constexpr int MAXT = " << w.maxt << ";         // most terms on a reaction side\n"
+      << "constexpr int NSLOT = " << w.nslot << ", PW = " << w.pw << ", JW = " << w.jw << ";\n"
+      << "constexpr int L_Y = " << w.l_y << ", L_C = " << w.l_c << ", L_G = " << w.l_g << ", L_H = " << w.l_h
+      << ", L_Q = " << w.l_q << ", L_P = " << w.l_p << ", L_J = " << w.l_j << ", L_T0 = " << w.l_t0 << ";\n"
+      << "constexpr int LDS_CELL = " << w.lds_cell << ";  // doubles of LDS scratch per cell\n"
+      << "constexpr double RU = " << lit(kRu) << ";\n"
+      << "constexpr double LN_PATM_R = " << lit(std::log(kPatm / kRu)) << ";\n"
+      << "constexpr double LN10 = " << lit(std::log(10.0)) << ";\n";
+    e.thermo_table();
+    o << "__constant__ double TMID[NS] = {";
+    for (int k = 0; k < ns; ++k) o << lit(m.species[k].tmid) << (k + 1 < ns ? ", " : "};\n");
+    // reactions in evaluation order: grouped by kind so a round of lanes mostly
+    // takes one branch
+    std::vector<int> order;
+    for (int kind = 0; kind < 4; ++kind)
+        for (int j = 0; j < nr; ++j)
+            if ((int)m.reactions[j].kind == kind) order.push_back(j);
+    std::vector<int> slot_of(nr);
+    for (int s = 0; s < nr; ++s) slot_of[order[s]] = s;
+    std::vector<int> effrow(nr, -1);
+    int neff = 0;
+    for (int s = 0; s < nr; ++s)
+        if (m.reactions[order[s]].kind != RxnKind::Elementary) effrow[s] = neff++;
+    auto ints = [&](const char* name, const std::vector<int>& v) {
+        o << "__constant__ int " << name << "[" << std::max<size_t>(v.size(), 1) << "] = {";
+        if (v.empty()) o << "0";
+        for (size_t i = 0; i < v.size(); ++i) o << v[i] << (i + 1 < v.size() ? ", " : "");
+        o << "};\n";
+    };
+    auto dbls = [&](const char* name, const std::vector<double>& v) {
+        o << "__constant__ double " << name << "[" << std::max<size_t>(v.size(), 1) << "] = {";
+        if (v.empty()) o << "0.0";
+        for (size_t i = 0; i < v.size(); ++i) o << lit(v[i]) << (i + 1 < v.size() ? ", " : "");
+        o << "};\n";
+    };
+    std::vector<int> orig, kind, dnu, sp, nu;
+    std::vector<double> low, troe, eff;
+    for (int s = 0; s < nr; ++s) {
+        const auto& r = m.reactions[order[s]];
+        orig.push_back(order[s]);
+        kind.push_back((int)r.kind);
+        dnu.push_back(r.dnu);
+        for (int t = 0; t < w.maxt; ++t) {
+            sp.push_back(t < (int)r.reac.size() ? r.reac[t].sp : -1);
+            nu.push_back(t < (int)r.reac.size() ? r.reac[t].nu : 0);
+        }
+        for (int t = 0; t < w.maxt; ++t) {
+            sp.push_back(t < (int)r.prod.size() ? r.prod[t].sp : -1);
+            nu.push_back(t < (int)r.prod.size() ? r.prod[t].nu : 0);
+        }
+        low.insert(low.end(), {r.lnA0, r.b0, r.EaR0});
+        const bool tr = r.kind == RxnKind::Troe;
+        troe.insert(troe.end(), {tr ? 1.0 - r.alpha : 0.0, tr ? r.alpha : 0.0, tr ? 1.0 / r.T3 : 0.0,
+                                 tr ? 1.0 / r.T1 : 0.0, tr && r.has_T2 ? r.T2 : 0.0,
+                                 tr ? -(1.0 - r.alpha) / r.T3 : 0.0, tr ? -r.alpha / r.T1 : 0.0,
+                                 tr && r.has_T2 ? 1.0 : 0.0});
+        if (effrow[s] >= 0)
+            for (int k = 0; k < ns; ++k) eff.push_back(r.eff[k]);
+    }
+    o << "// reactions in evaluation order (slot s): original index, kind (0 elementary,\n"
+         "// 1 third-body, 2 Lindemann, 3 Troe), sum nu'' - sum nu', species and\n"
+         "// coefficients of the MAXT reactant then MAXT product slots (-1: unused)\n";
+    ints("RX_ORIG", orig);
+    ints("RX_KIND", kind);
+    ints("RX_DNU", dnu);
+    ints("RX_SP", sp);
+    ints("RX_NU", nu);
+    o << "// low-pressure limit (ln A0 SI, b0, Ea0/R); Troe: 1-alpha, alpha, 1/T***,\n"
+         "// 1/T*, T**, -(1-alpha)/T***, -alpha/T*, [T** given]\n";
+    dbls("RX_LOW", low);
+    dbls("RX_TROE", troe);
+    o << "// third-body efficiencies, one dense row per non-elementary reaction\n";
+    ints("RX_EFFROW", effrow);
+    dbls("EFF", eff);
+    // species -> reactions that change it (slot, net coefficient)
+    std::vector<int> off(1, 0), srx, snu;
+    for (int k = 0; k < ns; ++k) {
+        for (int s = 0; s < nr; ++s) {
+            const auto& r = m.reactions[order[s]];
+            int v = 0;
+            for (auto& t : r.reac) if (t.sp == k) v -= t.nu;
+            for (auto& t : r.prod) if (t.sp == k) v += t.nu;
+            if (v) {
+                srx.push_back(s);
+                snu.push_back(v);
+            }
+        }
+        off.push_back((int)srx.size());
+    }
+    o << "// species k: the reactions that change it, SP_RX[SP_OFF[k] .. SP_OFF[k+1]),\n"
+         "// with net coefficients SP_NU\n";
+    ints("SP_OFF", off);
+    ints("SP_RX", srx);
+    ints("SP_NU", snu);
+    o << "}  // namespace mech\n";
+    return o.str();
+}
 
 }  // namespace chemmi

@@ -1,0 +1,152 @@
+// common.hip -- device declarations shared by the per-lane and the
+// wave-cooperative integrators: the RODAS4 tableau, cell status codes, kernel
+// argument structs, the field table of the persistent launches, and the
+// counter kernels.
+
+namespace chem {
+
+// ---- RODAS4 in the transformed variables u_i ----
+struct Rodas4 {
+    static constexpr int S = 6;
+    static constexpr double gamma = 0.25;
+};
+__device__ constexpr double RA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.544, 0, 0, 0, 0},
+    {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
+    {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.687886036105895, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.687886036105895, 1.0}};
+__device__ constexpr double RC[6][5] = {
+    {0, 0, 0, 0, 0},
+    {-5.6688, 0, 0, 0, 0},
+    {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
+    {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
+    {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.7089089320616, 0},
+    {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+     -6.058818238834054}};
+// y_new = y + sum_i m_i u_i with m = (a_51, a_52, a_53, a_54, 1, 1): the stage-6
+// argument plus u_6 (stiffly accurate); the error estimate is u_6.
+
+enum : int { CELL_OK = 0, CELL_MAXSTEPS = 1, CELL_HMIN = 2, CELL_NONFINITE = 3, CELL_BADINPUT = 4 };
+
+struct StepArgs {
+    double dt, rtol, atol, hmin;
+    int max_substeps;
+};
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+struct IntegrateArgs {
+    const double* par;
+    double* T;
+    const double* p;
+    double* Y;
+    long ncell;
+    const double* h0;          // nullable: per-cell first step, else dt
+    int* status;
+    int* nacc;
+    int* nrej;
+    StepArgs step;
+};
+
+}  // namespace chem
+
+// source terms and Jacobian at given states (no integration)
+struct EvalArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double* f;      // [ncell][N]
+    double* J;      // [ncell][N][N] or null
+};
+
+// ---- counters: sums of accepted / rejected substeps, failed cells, max attempts ----
+extern "C" __global__ void __launch_bounds__(256) chem_zero_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+extern "C" __global__ void __launch_bounds__(256) chem_reduce_stats(const int* __restrict__ status,
+                                                                    const int* __restrict__ nacc,
+                                                                    const int* __restrict__ nrej,
+                                                                    long ncell,
+                                                                    unsigned long long* __restrict__ out)
+{
+    unsigned long long acc = 0, rej = 0, fail = 0, mx = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (long)gridDim.x * blockDim.x) {
+        const int a = nacc[i], r = nrej[i];
+        acc += (unsigned long long)a;
+        rej += (unsigned long long)r;
+        fail += status[i] != 0 ? 1ull : 0ull;
+        const unsigned long long t = (unsigned long long)(a + r);
+        mx = t > mx ? t : mx;
+    }
+    __shared__ unsigned long long s[4][256];
+    s[0][threadIdx.x] = acc;
+    s[1][threadIdx.x] = rej;
+    s[2][threadIdx.x] = fail;
+    s[3][threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+            s[2][threadIdx.x] += s[2][threadIdx.x + w];
+            s[3][threadIdx.x] = s[3][threadIdx.x] > s[3][threadIdx.x + w] ? s[3][threadIdx.x] : s[3][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], s[0][0]);
+        atomicAdd(&out[1], s[1][0]);
+        atomicAdd(&out[2], s[2][0]);
+        atomicMax(&out[3], s[3][0]);
+    }
+}
+
+// ---- field table of the persistent launches ----
+constexpr int kCostBuckets = 256;
+
+struct FieldDesc {
+    double* T;
+    const double* p;
+    double* Y;
+    int* status;
+    int* nacc;
+    int* nrej;
+    const int* cost;          // nullable: per-cell cost hint
+    long ncell;
+    long start;               // first global index of this field
+};
+
+struct PersistBlock {
+    long total;
+    int nfield;
+    int nq;
+    int refill;
+    int order;                // 1: cost-ordered
+    chem::StepArgs step;
+    unsigned char* bucket;    // [total] cost bucket per cell
+    int* perm;                // [total] cells by descending cost
+    unsigned* hist;           // [kCostBuckets]
+    unsigned* cursor;         // [kCostBuckets]
+    FieldDesc fields[1];      // nfield entries
+};
+
+__device__ __forceinline__ int field_of(const PersistBlock* __restrict__ blk, long g)
+{
+    int f = 0;
+    while (f + 1 < blk->nfield && blk->fields[f + 1].start <= g) ++f;
+    return f;
+}
+
+extern "C" __global__ void chem_reset_heads(const PersistBlock* __restrict__ blk, unsigned long long* heads)
+{
+    const int i = threadIdx.x;
+    if (i < 64) heads[i] = 0ull;
+    for (int b = i; b < kCostBuckets; b += blockDim.x) blk->hist[b] = 0u;
+}

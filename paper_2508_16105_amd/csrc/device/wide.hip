@@ -1,0 +1,630 @@
+// wide.hip -- the chemistry step for mechanisms whose per-cell matrices do not
+// fit the registers of one lane (CDNA4, gfx950).
+//
+// G lanes (a power of two, at least n = ns + 1) cooperate on one cell, so a
+// 64-lane wave holds 64 / G cells.  Lane i of a group owns component i of
+// every state-sized vector (i = 0: T, i = 1 + k: Y_k) and row i of the
+// Jacobian, of the step matrix and of its LU factors: n doubles of matrix row
+// and one double per vector stay in registers.  Per source-term evaluation:
+//   - species thermo (NASA-7) in the species' own lanes;
+//   - mixture sums (sum Y/W, c_p, heat release) as group reductions;
+//   - reaction rates spread over the lanes, read from the mechanism tables
+//     (reactions grouped by kind so a round of lanes mostly takes one branch);
+//   - production rates and Jacobian rows gathered by each species lane from
+//     the cell's LDS scratch in a fixed order (results are reproducible);
+// and per step the LU factorisation with partial pivoting (pivot search as a
+// group arg-max, the pivot row broadcast from its lane), the triangular
+// solves (one broadcast per column) and the RMS error norm (a group sum).
+// Reductions are xor-butterflies: every lane of a group ends with the same
+// bits, so the step-size controller runs identically in all of them.
+//
+// The equations, the RODAS4 tableau and the controller are those of the
+// one-cell-per-lane integrator (the species/energy source of eqs. (20)-(21)
+// at constant pressure over one flow step).
+
+namespace chemw {
+
+using chem::RA;
+using chem::RC;
+using chem::Rodas4;
+using chem::StepArgs;
+using chem::finite;
+constexpr int N = mech::N, NS = mech::NS, NR = mech::NR, G = mech::G;
+constexpr int CPW = 64 / G;
+constexpr int NSLOT = mech::NSLOT, PW = mech::PW, JW = mech::JW;
+constexpr int ROUNDS = (NR + G - 1) / G;
+static_assert(N <= G && G <= 64 && (G & (G - 1)) == 0, "group size");
+
+__device__ __forceinline__ int gl() { return (int)(threadIdx.x & (unsigned)(G - 1)); }
+__device__ __forceinline__ int gbase() { return (int)(threadIdx.x & 63u & ~(unsigned)(G - 1)); }
+
+// value of x in lane `src` of this group; src is the same in every lane of the group
+__device__ __forceinline__ double bcast(double x, int src)
+{
+    if constexpr (G == 64) {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readlane((int)b, src);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return __shfl(x, gbase() + src, 64);
+    }
+}
+
+// value of x in lane `src` of this group; src may differ per lane
+__device__ __forceinline__ double gather(double x, int src) { return __shfl(x, gbase() + src, 64); }
+
+__device__ __forceinline__ double gsum(double x)
+{
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// true in every lane of the group if `bad` holds in any lane of it
+__device__ __forceinline__ bool gany(bool bad)
+{
+    const unsigned long long b = __ballot(bad);
+    if constexpr (G == 64) return b != 0ull;
+    else return ((b >> gbase()) & ((1ull << G) - 1ull)) != 0ull;
+}
+
+// LDS writes of this wave visible to its later LDS reads
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ double ipow(double c, int nu) { return nu == 1 ? c : (nu == 2 ? c * c : c * c * c); }
+
+// d(c^nu)/dc
+__device__ __forceinline__ double dipow(double c, int nu) { return nu == 1 ? 1.0 : (nu == 2 ? 2.0 * c : 3.0 * c * c); }
+
+// Rate of progress of the reaction in slot j (and, with JAC, its partials:
+// d q / d C of each species slot, d q / dT at fixed C, and the coefficient of
+// the third-body efficiencies in d q / d C), written to the cell's LDS.
+template <bool JAC>
+__device__ __forceinline__ void reaction(int j, const double* __restrict__ par, double* __restrict__ L, double T,
+                                         double lnT, double iT, double lnPRT, double ctot)
+{
+    const int kind = mech::RX_KIND[j];
+    const int oj = mech::RX_ORIG[j];
+    const double pb = par[NR + oj], pe = par[2 * NR + oj];
+    double lnk = lnT * pb;
+    lnk = fma(-iT, pe, lnk);
+    lnk = lnk + par[oj];
+    int sp[NSLOT], nu[NSLOT];
+    double c[NSLOT];
+    double lnKc = 0.0, dH = 0.0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        sp[s] = mech::RX_SP[j * NSLOT + s];
+        nu[s] = mech::RX_NU[j * NSLOT + s];
+        c[s] = 1.0;
+        if (sp[s] >= 0) {
+            const double sgn = s < mech::MAXT ? -(double)nu[s] : (double)nu[s];
+            lnKc = fma(sgn, L[mech::L_G + sp[s]], lnKc);
+            if (JAC) dH = fma(sgn, L[mech::L_H + sp[s]], dH);
+            c[s] = L[mech::L_C + sp[s]];
+        }
+    }
+    const int dnu = mech::RX_DNU[j];
+    lnKc = fma((double)dnu, lnPRT, lnKc);
+    const int er = mech::RX_EFFROW[j];
+    double Mc = ctot;
+    if (er >= 0) {
+        for (int m = 0; m < NS; ++m) Mc = fma(mech::EFF[er * NS + m] - 1.0, L[mech::L_C + m], Mc);
+    }
+    double kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0;
+    double dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;
+    if (kind < 2) {
+        kf = chem_math::exp_tang(lnk);
+        kr = chem_math::exp_tang(lnk - lnKc);
+    } else {
+        // P_r = k0 [M] / k_inf, one exponential for the ratio
+        const double* lo = &mech::RX_LOW[j * 3];
+        kinf = chem_math::exp_tang(lnk);
+        const double lnr0 = lo[0] + lo[1] * lnT - lo[2] * iT - lnk;
+        r0 = chem_math::exp_tang(lnr0);
+        const double Pr = r0 * Mc;
+        const bool floored = !(Pr >= 1e-300);
+        const double logPr = floored ? -300.0 : log10(Pr);
+        if (kind == 3) {
+            const double* tr = &mech::RX_TROE[j * 8];
+            const double e3 = exp(-T * tr[2]);
+            const double e1 = exp(-T * tr[3]);
+            double Fc = tr[0] * e3 + tr[1] * e1;
+            double dFc = tr[5] * e3 + tr[6] * e1;
+            if (tr[7] != 0.0) {
+                const double e2 = exp(-tr[4] * iT);
+                Fc += e2;
+                dFc += tr[4] * iT * iT * e2;
+            }
+            const double logFc = log10(Fc);
+            const double tc = -0.4 - 0.67 * logFc;
+            const double tn = 0.75 - 1.27 * logFc;
+            const double tu = logPr + tc;
+            const double tden = tn - 0.14 * tu;
+            const double tx = tu / tden;
+            const double opx2 = 1.0 + tx * tx;
+            const double logF = logFc / opx2;
+            Fb = exp(mech::LN10 * logF);
+            if (JAC) {
+                const double tg = -logFc * 2.0 * tx / (opx2 * opx2);
+                dF_dPr = floored ? 0.0 : tg * tn / (tden * tden);
+                dF_dFc = 1.0 / opx2 + tg * (-0.67 * tn + 1.27 * tu) / (tden * tden);
+                dlogFc_dT = dFc / (Fc * mech::LN10);
+            }
+        }
+        ipr1 = 1.0 / (1.0 + Pr);
+        kf = kinf * Pr * ipr1 * Fb;
+        iKc = chem_math::exp_tang(-lnKc);
+        kr = kf * iKc;
+    }
+    double pf = 1.0, pr = 1.0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        if (sp[s] >= 0) {
+            if (s < mech::MAXT) pf *= ipow(c[s], nu[s]);
+            else pr *= ipow(c[s], nu[s]);
+        }
+    }
+    const double fwd = kf * pf, rev = kr * pr;
+    L[mech::L_Q + j] = kind == 1 ? Mc * (fwd - rev) : fwd - rev;
+    if (!JAC) return;
+    double* P = L + mech::L_P + j * PW;
+    const double fac = kind == 1 ? Mc : 1.0;
+    const double dlnKc = (dH - (double)dnu) * iT;
+    const double dlnkinf = (pb + pe * iT) * iT;
+    double dlnkf = dlnkinf;
+    double dM = kind == 1 ? fwd - rev : 0.0;
+    if (kind >= 2) {
+        const double* lo = &mech::RX_LOW[j * 3];
+        const double dlnk0 = (lo[1] + lo[2] * iT) * iT;
+        dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + mech::LN10 * dF_dFc * dlogFc_dT;
+        const double dkdM = kinf * r0 * Fb * (ipr1 * ipr1 + dF_dPr * ipr1);
+        dM = dkdM * (pf - iKc * pr);
+    }
+    P[NSLOT] = fac * (dlnkf * fwd - (dlnkf - dlnKc) * rev);
+    P[NSLOT + 1] = dM;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        // derivative of this side's product with respect to the slot's species
+        double d = 0.0;
+        if (sp[s] >= 0) {
+            const int lo = s < mech::MAXT ? 0 : mech::MAXT;
+            d = dipow(c[s], nu[s]);
+#pragma unroll
+            for (int t = 0; t < mech::MAXT; ++t)
+                if (lo + t != s && sp[lo + t] >= 0) d *= ipow(c[lo + t], nu[lo + t]);
+            d = s < mech::MAXT ? fac * kf * d : -fac * kr * d;
+        }
+        P[s] = d;
+    }
+}
+
+// Source terms f = dy/dt of the group's cell at the state whose component i
+// is yi (lane i), and with JAC row i of the Jacobian in A.  Every lane of the
+// group calls it together.
+template <bool JAC>
+__device__ __forceinline__ double rhs(const double* __restrict__ par, double p, double ip, double yi,
+                                      double* __restrict__ L, double (&A)[N])
+{
+    const int i = gl();
+    const bool sp = i >= 1 && i <= NS;
+    const int k = sp ? i - 1 : 0;
+    if (i < N) L[mech::L_Y + i] = yi;
+    lds_sync();
+    const double T = L[mech::L_Y];
+    const double lnT = log(T);
+    const double iT = 1.0 / T;
+    const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;
+    double cpR = 0.0, HRT = 0.0, Gk = 0.0, dcpR = 0.0;
+    if (sp) {
+        const double* c = &mech::THERMO[k][T < mech::TMID[k] ? 0 : 1][0];
+        double a = T4 * c[4];
+        a = fma(T3, c[3], a);
+        a = fma(T2, c[2], a);
+        a = fma(T, c[1], a);
+        cpR = a + c[0];
+        a = T4 * c[8];
+        a = fma(T3, c[7], a);
+        a = fma(T2, c[6], a);
+        a = fma(T, c[5], a);
+        a = fma(iT, c[9], a);
+        HRT = a + c[0];
+        a = T4 * c[13];
+        a = fma(T3, c[12], a);
+        a = fma(T2, c[11], a);
+        a = fma(T, c[10], a);
+        a = fma(lnT, c[0], a);
+        a = fma(-iT, c[9], a);
+        Gk = a + c[14];
+        if (JAC) {
+            a = T3 * c[18];
+            a = fma(T2, c[17], a);
+            a = fma(T, c[16], a);
+            dcpR = a + c[15];
+        }
+    }
+    const double W = sp ? mech::MWTAB[k] : 0.0;
+    const double iW = sp ? mech::MWTAB[NS + k] : 0.0;
+    const double yw = sp ? yi * iW : 0.0;
+    const double sig = gsum(yw);
+    const double Wbar = 1.0 / sig;
+    const double rho = p * Wbar * iT * (1.0 / mech::RU);
+    const double irho = mech::RU * T * sig * ip;
+    const double ctot = p * iT * (1.0 / mech::RU);
+    if (sp) {
+        L[mech::L_C + k] = rho * yw;
+        L[mech::L_G + k] = Gk;
+        L[mech::L_H + k] = HRT;
+    }
+    lds_sync();
+    const double lnPRT = mech::LN_PATM_R - lnT;
+#pragma unroll 1
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int j = r * G + i;
+        if (j < NR) reaction<JAC>(j, par, L, T, lnT, iT, lnPRT, ctot);
+    }
+    lds_sync();
+    double wdot = 0.0;
+    if (sp) {
+        for (int e = mech::SP_OFF[k]; e < mech::SP_OFF[k + 1]; ++e)
+            wdot = fma((double)mech::SP_NU[e], L[mech::L_Q + mech::SP_RX[e]], wdot);
+    }
+    const double cpm = gsum(cpR * yw);
+    const double hw = gsum(HRT * wdot);
+    const double icpm = 1.0 / cpm;
+    const double rcpinv = T * sig * ip * icpm;
+    const double fT = -mech::RU * T * hw * rcpinv;
+    const double fk = W * (irho * wdot);
+    const double fi = sp ? fk : (i == 0 ? fT : 0.0);
+    if (!JAC) return fi;
+
+    // concentration Jacobian row k: Jc_km = d wdot_k / d C_m (fixed T), and
+    // column NS: wT_k = d wdot_k / dT (fixed C)
+    double* Jr = L + mech::L_J + k * JW;
+    if (sp) {
+        for (int m = 0; m <= NS; ++m) Jr[m] = 0.0;
+        for (int e = mech::SP_OFF[k]; e < mech::SP_OFF[k + 1]; ++e) {
+            const int j = mech::SP_RX[e];
+            const double nu = (double)mech::SP_NU[e];
+            const double* P = L + mech::L_P + j * PW;
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) {
+                const int m = mech::RX_SP[j * NSLOT + s];
+                if (m >= 0) Jr[m] = fma(nu, P[s], Jr[m]);
+            }
+            Jr[NS] = fma(nu, P[NSLOT], Jr[NS]);
+            const int er = mech::RX_EFFROW[j];
+            if (er >= 0) {
+                const double dM = nu * P[NSLOT + 1];
+                for (int m = 0; m < NS; ++m) Jr[m] = fma(mech::EFF[er * NS + m], dM, Jr[m]);
+            }
+        }
+    }
+    lds_sync();
+    // chain rule to (T, Y), with S_k = sum_l Jc_kl C_l:
+    //   J_km = (W_k/W_m) Jc_km + (Wbar/W_m)(f_k - W_k S_k / rho)
+    //   J_k0 = (W_k / rho)(wT_k - S_k / T) + f_k / T
+    //   J_0m = -R T (rho HJ_m - Wbar HS) / (W_m rho cp) - f_T (cp_m / cp - Wbar / W_m)
+    //   J_00 = -R (cpw + T HwT - HS) / (rho cp) - f_T (dcp / cp - 1/T)
+    // HJ_m = sum_k H_k/RT Jc_km, HS = sum_k H_k/RT S_k, HwT = sum_k H_k/RT wT_k,
+    // cpw = sum_k cp_k/R wdot_k
+    double Sk = 0.0, wT = 0.0;
+    if (sp) {
+        for (int m = 0; m < NS; ++m) Sk = fma(Jr[m], L[mech::L_C + m], Sk);
+        wT = Jr[NS];
+    }
+    const double HS = gsum(HRT * Sk);
+    const double HwT = gsum(HRT * wT);
+    const double cpw = gsum(cpR * wdot);
+    const double dcpm = gsum(dcpR * yw);
+    const double RT = mech::RU * T;
+    const double icp = icpm * (1.0 / mech::RU);
+    const double dcp = mech::RU * dcpm;
+    if (sp) {
+        double HJ = 0.0;
+        for (int l = 0; l < NS; ++l) HJ = fma(L[mech::L_H + l], L[mech::L_J + l * JW + k], HJ);
+        const double t = fma(rho, HJ, -Wbar * HS) * (-RT * rcpinv);
+        const double u = fma(cpR, icp * mech::RU, -Wbar);
+        L[mech::L_T0 + k] = fma(-fT, u, t) * iW;
+    }
+    lds_sync();
+    if (sp) {
+        const double g = fma(-W, Sk * irho, fk);
+        const double wg = Wbar * g;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) A[1 + m] = fma(Jr[m], W, wg) * mech::MWTAB[NS + m];
+        A[0] = fma(W * irho, wT - Sk * iT, fk * iT);
+    } else if (i == 0) {
+        A[0] = -mech::RU * (cpw + T * HwT - HS) * rcpinv - fT * (dcp * icp - iT);
+#pragma unroll
+        for (int m = 0; m < NS; ++m) A[1 + m] = L[mech::L_T0 + m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) A[m] = 0.0;
+    }
+    return fi;
+}
+
+// LU with partial pivoting of the group's matrix (row i in lane i), in place:
+// multipliers below the diagonal, U above, reciprocal pivots on the diagonal.
+// piv[k]: row swapped into k at step k (LINPACK order, the lowest row index
+// among equal magnitudes); bit k of the result: some group of the wave swapped.
+__device__ __forceinline__ unsigned long long lu(double (&A)[N], int (&piv)[N], bool& ok)
+{
+    const int i = gl();
+    unsigned long long swaps = 0ull;
+    ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double v = (i >= k && i < N) ? fabs(A[k]) : -1.0;
+        int idx = i;
+#pragma unroll
+        for (int m = 1; m < G; m <<= 1) {
+            const double v2 = __shfl_xor(v, m, 64);
+            const int i2 = __shfl_xor(idx, m, 64);
+            const bool take = v2 > v || (v2 == v && i2 < idx);
+            v = take ? v2 : v;
+            idx = take ? i2 : idx;
+        }
+        piv[k] = idx;
+        ok = ok && (v > 0.0);
+        if (__any(idx != k)) {
+            swaps |= 1ull << k;
+            const int src = (i == k) ? idx : (i == idx ? k : i);
+#pragma unroll
+            for (int j = k; j < N; ++j) A[j] = gather(A[j], src);
+        }
+        double prow[N];
+#pragma unroll
+        for (int j = k; j < N; ++j) prow[j] = bcast(A[j], k);
+        const double rp = 1.0 / prow[k];
+        if (i == k) {
+            A[k] = rp;
+        } else if (i > k && i < N) {
+            const double l = A[k] * rp;
+            A[k] = l;
+#pragma unroll
+            for (int j = k + 1; j < N; ++j) A[j] = fma(-l, prow[j], A[j]);
+        }
+    }
+    return swaps;
+}
+
+// Solve (LU) x = b for the group's vector b (component i in lane i).
+__device__ __forceinline__ double solve(const double (&A)[N], const int (&piv)[N], unsigned long long swaps,
+                                        double b)
+{
+    const int i = gl();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (swaps & (1ull << k)) {
+            const int pk = piv[k];
+            b = gather(b, (i == k) ? pk : (i == pk ? k : i));
+        }
+        const double zk = bcast(b, k);
+        if (i > k && i < N) b = fma(-A[k], zk, b);
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        if (i == k) b *= A[k];
+        const double zk = bcast(b, k);
+        if (i < k) b = fma(-A[k], zk, b);
+    }
+    return b;
+}
+
+// One RODAS4 step from y (component yi) with step h; false if the step
+// matrix is singular or a result is not finite.
+__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip, double yi, double h,
+                                         double rtol, double atol, double* __restrict__ L, double& ynew,
+                                         double& errn)
+{
+    const int i = gl();
+    double A[N];
+    const double f0 = rhs<true>(par, p, ip, yi, L, A);
+    const double ghinv = 1.0 / (h * Rodas4::gamma);
+    const double hinv = 1.0 / h;
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - A[j];
+    int piv[N];
+    bool ok;
+    const unsigned long long swaps = lu(A, piv, ok);
+    double u[Rodas4::S];
+    u[0] = solve(A, piv, swaps, f0);
+    double dummy[N];
+#pragma unroll
+    for (int s = 1; s < Rodas4::S; ++s) {
+        double Ys = yi, acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < s; ++j) {
+            Ys = fma(RA[s][j], u[j], Ys);
+            acc = fma(RC[s][j], u[j], acc);
+        }
+        if (s == Rodas4::S - 1) ynew = Ys;
+        const double fs = rhs<false>(par, p, ip, Ys, L, dummy);
+        u[s] = solve(A, piv, swaps, fma(acc, hinv, fs));
+    }
+    ynew += u[Rodas4::S - 1];
+    const double sc = atol + rtol * fmax(fabs(yi), fabs(ynew));
+    const double e = u[Rodas4::S - 1] / sc;
+    errn = sqrt(gsum(i < N ? e * e : 0.0) * (1.0 / N));
+    const bool bad = gany(i < N && !finite(ynew));
+    return ok && !bad && finite(errn);
+}
+
+// Per-group integration state (component yi in lane i, the rest replicated).
+struct Cell {
+    double y, p, ip, t, h;
+    int nacc, nrej, status;
+    bool rej_last, done;
+};
+
+__device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const double* __restrict__ Y, double h0)
+{
+    const int i = gl();
+    c.y = i == 0 ? T : (i <= NS ? Y[i - 1] : 0.0);
+    c.p = p;
+    c.ip = 1.0 / p;
+    c.t = 0.0;
+    c.h = h0;
+    c.nacc = 0;
+    c.nrej = 0;
+    c.rej_last = false;
+    const bool bad = gany(!finite(c.y)) || !(T > 0.0) || !(p > 0.0) || !finite(p);
+    c.status = bad ? chem::CELL_BADINPUT : chem::CELL_OK;
+    c.done = bad;
+}
+
+// One attempted substep with the controller of the one-cell-per-lane form.
+__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
+                                             double* __restrict__ L)
+{
+    if (c.done) return;
+    if (c.nacc + c.nrej >= a.max_substeps) {
+        c.status = chem::CELL_MAXSTEPS;
+        c.done = true;
+        return;
+    }
+    if (c.h < a.hmin) {
+        c.status = chem::CELL_HMIN;
+        c.done = true;
+        return;
+    }
+    bool last = false;
+    double h = c.h;
+    if (h >= a.dt - c.t) {
+        h = a.dt - c.t;
+        last = true;
+    }
+    double ynew, en;
+    const bool ok = ros_step(par, c.p, c.ip, c.y, h, a.rtol, a.atol, L, ynew, en);
+    if (ok && en <= 1.0) {
+        c.y = ynew;
+        c.t = last ? a.dt : c.t + h;
+        double fac = 0.9 * pow(fmax(en, 1e-16), -0.25);
+        fac = fmin(6.0, fmax(0.2, fac));
+        if (c.rej_last) fac = fmin(1.0, fac);
+        c.h = h * fac;
+        c.rej_last = false;
+        ++c.nacc;
+        if (last) c.done = true;
+        return;
+    }
+    ++c.nrej;
+    c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
+    c.rej_last = true;
+}
+
+__device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T, double* __restrict__ Y, long cell,
+                                           int* status, int* nacc, int* nrej)
+{
+    const int i = gl();
+    if (c.status != chem::CELL_BADINPUT) {
+        if (i == 0) T[cell] = c.y;
+        else if (i <= NS) Y[cell * NS + i - 1] = c.y;
+    }
+    if (i == 0) {
+        status[cell] = c.status;
+        nacc[cell] = c.nacc;
+        nrej[cell] = c.nrej;
+    }
+}
+
+}  // namespace chemw
+
+// ---- plain form: one group of G lanes per cell, cells in index order ----
+extern "C" __global__ void __launch_bounds__(64) chem_plain(chem::IntegrateArgs a)
+{
+    using namespace chemw;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    extern __shared__ double lds[];
+    const int grp = (int)threadIdx.x / G;
+    const long cell = (long)blockIdx.x * CPW + grp;
+    if (cell >= a.ncell) return;
+    double* L = lds + grp * mech::LDS_CELL;
+    Cell c;
+    cell_begin(c, a.T[cell], a.p[cell], a.Y + cell * NS, a.h0 ? a.h0[cell] : a.step.dt);
+    while (!c.done) cell_attempt(c, a.par, a.step, L);
+    cell_store(c, a.T, a.Y, cell, a.status, a.nacc, a.nrej);
+}
+
+// ---- source terms and Jacobian at given states ----
+extern "C" __global__ void __launch_bounds__(64) chem_eval(EvalArgs a)
+{
+    using namespace chemw;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    extern __shared__ double lds[];
+    const int grp = (int)threadIdx.x / G;
+    const long cell = (long)blockIdx.x * CPW + grp;
+    if (cell >= a.ncell) return;
+    double* L = lds + grp * mech::LDS_CELL;
+    const int i = gl();
+    const double p = a.p[cell];
+    const double yi = i == 0 ? a.T[cell] : (i <= NS ? a.Y[cell * NS + i - 1] : 0.0);
+    double A[N];
+    double f;
+    if (a.J) {
+        f = rhs<true>(a.par, p, 1.0 / p, yi, L, A);
+        if (i < N) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) a.J[(cell * N + i) * N + j] = A[j];
+        }
+    } else {
+        f = rhs<false>(a.par, p, 1.0 / p, yi, L, A);
+    }
+    if (i < N) a.f[cell * N + i] = f;
+}
+
+// ---- persistent form: groups pull cells from one global counter ----
+// Cells of all fields form one index space [0, total); each group takes the
+// next cell when its current one is done, so no group idles while cells
+// remain (the hardware already balances whole waves; this also balances the
+// groups inside a wave and spans several fields in one launch).
+extern "C" __global__ void __launch_bounds__(64) chem_persistent(const PersistBlock* __restrict__ blk,
+                                                                 unsigned long long* __restrict__ heads,
+                                                                 const double* __restrict__ par)
+{
+    using namespace chemw;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    extern __shared__ double lds[];
+    const int grp = (int)threadIdx.x / G;
+    double* L = lds + grp * mech::LDS_CELL;
+    const StepArgs step = blk->step;
+    const long total = blk->total;
+    Cell c;
+    c.done = true;
+    bool have = false, exhausted = false;
+    long local = 0;
+    int f = 0;
+    while (true) {
+        if (!have && !exhausted) {
+            unsigned long long t = 0ull;
+            if (gl() == 0) t = atomicAdd(heads, 1ull);
+            t = (unsigned long long)__shfl((long long)t, gbase(), 64);
+            if ((long)t < total) {
+                f = field_of(blk, (long)t);
+                const FieldDesc& fd = blk->fields[f];
+                local = (long)t - fd.start;
+                cell_begin(c, fd.T[local], fd.p[local], fd.Y + local * NS, step.dt);
+                have = true;
+            } else {
+                exhausted = true;
+            }
+        }
+        if (__all(exhausted)) break;
+        if (have) {
+            cell_attempt(c, par, step, L);
+            if (c.done) {
+                const FieldDesc& fd = blk->fields[f];
+                cell_store(c, fd.T, fd.Y, local, fd.status, fd.nacc, fd.nrej);
+                have = false;
+            }
+        }
+    }
+}

@@ -16,11 +16,12 @@
 
 namespace chemmi {
 
-#include "_device_source.inc"   // kMathSource, kIntegratorSource: csrc/device/*.hip
+#include "_device_source.inc"   // kMathSource, kCommonSource, kIntegratorSource, kWideSource
 
-std::string device_source(const std::string& mechanism_code)
+std::string device_source(const std::string& mechanism_code, bool wide)
 {
-    return std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kIntegratorSource);
+    return std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kCommonSource) + "\n" +
+           std::string(wide ? kWideSource : kIntegratorSource);
 }
 
 const std::vector<std::string>& compile_options()

@@ -10,8 +10,9 @@
 namespace chemmi {
 
 // Full device source for a mechanism: the generated mechanism code followed by
-// the hand-written integrator and kernels.
-std::string device_source(const std::string& mechanism_code);
+// the hand-written integrator and kernels (one cell per lane, or with `wide`
+// the wave-cooperative form).
+std::string device_source(const std::string& mechanism_code, bool wide);
 
 // Compile options used for every device build (gfx950, FP64, contraction of
 // a*b+c into FMA only within an expression, no packed-FP32 instructions).

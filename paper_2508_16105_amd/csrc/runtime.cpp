@@ -81,17 +81,19 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         int rc = 0;
         rc = rc ? rc : load_function(d.module, "chem_plain", &d.f_plain);
         rc = rc ? rc : load_function(d.module, "chem_eval", &d.f_eval);
-        rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
         rc = rc ? rc : load_function(d.module, "chem_zero_u64", &d.f_zero);
         rc = rc ? rc : load_function(d.module, "chem_reduce_stats", &d.f_stats);
         rc = rc ? rc : load_function(d.module, "chem_persistent", &d.f_persistent);
         rc = rc ? rc : load_function(d.module, "chem_reset_heads", &d.f_reset);
-        rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
-        rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
-        rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
-        rc = rc ? rc : load_function(d.module, "chem_order_scatter", &d.f_oscatter);
-        rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
-        rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
+        if (!m->wide) {   // one-cell-per-lane module only
+            rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
+            rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
+            rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
+            rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
+            rc = rc ? rc : load_function(d.module, "chem_order_scatter", &d.f_oscatter);
+            rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
+            rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
+        }
         if (rc) return rc;
         HIPCHECK(hipMalloc((void**)&d.par, sizeof(double) * std::max<size_t>(m->params.size(), 1)), "hipMalloc par");
         HIPCHECK(hipMalloc((void**)&d.stats, sizeof(unsigned long long) * 4), "hipMalloc stats");
@@ -186,8 +188,10 @@ int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, doub
     int32_t* nr = nrej ? nrej : d->cells_i32 + 2 * ncell;
     IntegrateArgs a{d->par, T, p, Y, (long)ncell, o.h0, st, na, nr, step_args(dt, rtol, atol, o)};
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
-    if (int rc = launch_1d(d->f_plain, ncell, 64, &a, sizeof a, stream, "chem_plain", d->stage_lds(64)))
-        return rc;
+    // one lane per cell, or one group of G lanes per cell in the wave-cooperative form
+    const int64_t lanes = m->wide ? ncell * m->layout.G : ncell;
+    const unsigned shmem = m->wide ? m->layout.lds_bytes() : d->stage_lds(64);
+    if (int rc = launch_1d(d->f_plain, lanes, 64, &a, sizeof a, stream, "chem_plain", shmem)) return rc;
     if (!stats) return 0;
     HIPCHECK(hipEventRecord(d->ev1, stream), "event");
     HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
@@ -380,9 +384,58 @@ int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fi
 
 }  // namespace
 
+// Wave-cooperative form: groups of lanes pull cells from one counter (no
+// cost ordering: a whole wave serves one to four cells, so the hardware's
+// dispatch of waves and the refill of groups already balance the load).
+int run_persistent_wide(chem_mechanism* m, const FieldView* fv, int nfield, double dt, double rtol,
+                        double atol, const Options& o, chem_stats* stats, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    for (int f = 0; f < nfield; ++f)
+        if (fv[f].h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the persistent form");
+    std::vector<FieldDesc> fields;
+    int64_t total = 0;
+    if (int rc = fill_fields(*d, fv, nfield, fields, total)) return rc;
+    const StepArgs s = step_args(dt, rtol, atol, o);
+    LaunchConfig c{64, 1, 1};
+    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, CHEM_ORDER_NATURAL), stream)) return rc;
+    if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
+    struct { const char* blk; unsigned long long* h; } ra{d->block_buf, d->heads};
+    if (int rc = launch_1d(d->f_reset, 256, 256, &ra, sizeof ra, stream, "chem_reset_heads")) return rc;
+    struct { const char* blk; unsigned long long* heads; const double* par; } pa{d->block_buf, d->heads, d->par};
+    // resident waves: as many as the LDS scratch allows, at most 8 per CU
+    const unsigned per_cu = std::max<unsigned>(1u, std::min<unsigned>(8u, (unsigned)(160u * 1024u / std::max(1u, m->layout.lds_bytes()))));
+    const int64_t waves = std::min<int64_t>((int64_t)d->num_cu * per_cu, (total + m->layout.cells_per_wave() - 1) / m->layout.cells_per_wave());
+    if (int rc = launch_1d(d->f_persistent, waves * 64, 64, &pa, sizeof pa, stream, "chem_persistent",
+                           m->layout.lds_bytes()))
+        return rc;
+    if (!stats) return 0;
+    HIPCHECK(hipEventRecord(d->ev1, stream), "event");
+    HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, d->ev0, d->ev1), "elapsed");
+    chem_stats tot{};
+    tot.kernel_ms = ms;
+    for (int f = 0; f < nfield; ++f) {
+        chem_stats sf{};
+        int rc = collect_stats(*d, fields[f].status, fields[f].nacc, fields[f].nrej, fields[f].ncell, ms, &sf, stream);
+        if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+        tot.cells += sf.cells;
+        tot.accepted += sf.accepted;
+        tot.rejected += sf.rejected;
+        tot.failed += sf.failed;
+        tot.max_substeps = std::max(tot.max_substeps, sf.max_substeps);
+    }
+    *stats = tot;
+    if (tot.failed) return set_error(CHEM_E_CELL_FAILED, std::to_string(tot.failed) + " cells failed");
+    return 0;
+}
+
 int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt, double rtol,
                    double atol, const Options& o, chem_stats* stats, hipStream_t stream)
 {
+    if (m->wide) return run_persistent_wide(m, fv, nfield, dt, rtol, atol, o, stats, stream);
     DeviceState* d;
     if (int rc = device_state(m, stream, &d)) return rc;
     for (int f = 0; f < nfield; ++f)

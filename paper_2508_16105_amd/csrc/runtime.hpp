@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/chem.h"
+#include "codegen.hpp"
 #include "mechanism.hpp"
 
 namespace chemmi {
@@ -184,6 +185,8 @@ struct DeviceState {
 
 struct chem_mechanism {
     chemmi::MechanismData data;
+    bool wide = false;                   // wave-cooperative kernels (else one cell per lane)
+    chemmi::WideLayout layout;           // of the wave-cooperative form
     std::vector<double> params;          // lnA[nr], b[nr], Ea/R[nr]
     uint64_t params_version = 1;
     std::string source;

@@ -1,0 +1,180 @@
+"""GPU parity of the wave-cooperative form (G lanes per cell) against the
+CPU oracle: the 32-species / 150-reaction mechanism (third-body + Troe on 15
+reactions; n = 33, one cell per wave), and the 9- and 13-species mechanisms
+forced into the same form (n = 10 and 14, four cells per 16-lane groups of a
+wave) so both group sizes and the padding lanes are exercised.
+
+Tolerances are those of the one-cell-per-lane parity tests: |dT| <= 1e-6 T and
+|dY_k| <= 1e-8 at rtol 1e-8, atol 1e-12 for integrated states; source terms
+to 1e-11 and the Jacobian to 1e-10 of the row scale; persistent and plain
+forms bitwise."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workloads import WORKLOADS, mech_path, mech_text  # noqa: E402
+from workloads.states import rde_field, rde_field_n, uniform_cells  # noqa: E402
+
+RTOL, ATOL = 1e-8, 1e-12
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def chem():
+    import paper_2508_16105_amd as chem
+    return chem
+
+
+def _load_wide(chem, name):
+    """Load `name` in the wave-cooperative form (the lane form's species limit
+    lowered to 0 for this load only)."""
+    old = os.environ.get("CHEM_LANE_MAX_SPECIES")
+    os.environ["CHEM_LANE_MAX_SPECIES"] = "0"
+    try:
+        return chem.Mechanism(mech_path(name))
+    finally:
+        if old is None:
+            del os.environ["CHEM_LANE_MAX_SPECIES"]
+        else:
+            os.environ["CHEM_LANE_MAX_SPECIES"] = old
+
+
+@pytest.fixture(scope="module")
+def mechs(chem, oracle_lib):
+    out = {"m32": (chem.Mechanism(mech_path("m32")), oracle_lib.Mechanism(mech_path("m32")))}
+    for name in ("m9", "m13"):
+        out[name + "w"] = (_load_wide(chem, name), oracle_lib.Mechanism(mech_path(name)))
+    return out
+
+
+def _g(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _assert_state_parity(Tg, Yg, To, Yo, what):
+    dT = np.abs(Tg - To)
+    dY = np.abs(Yg - Yo)
+    bad = (dT > 1e-6 * To) | np.any(dY > 1e-8, axis=1)
+    assert not bad.any(), (f"{what}: {bad.sum()} cells out of tolerance; max |dT|/T "
+                           f"{(dT / To).max():.3e}, max |dY| {dY.max():.3e}")
+
+
+@pytest.mark.parametrize("key", ["m32", "m9w", "m13w"])
+def test_wide_source_terms_and_jacobian(chem, mechs, dev, key):
+    gm, om = mechs[key]
+    name = key.rstrip("w")
+    T, p, Y = uniform_cells(mech_text(name), 100, 71)
+    f, J = chem.eval_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev))
+    f2, _ = chem.eval_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev), jacobian=False)
+    assert torch.equal(f, f2)
+    f, J = f.cpu().numpy(), J.cpu().numpy()
+    for i in range(len(T)):
+        y = np.concatenate([[T[i]], Y[i]])
+        fo = om.rhs(p[i], y)
+        Jo = om.jac_cs(p[i], y)
+        assert np.all(np.abs(f[i] - fo) <= 1e-11 * np.abs(fo).max() + 1e-300), (key, i)
+        sc = np.abs(Jo).max(axis=1, keepdims=True) * np.maximum(np.abs(y), 1e-3)[None, :] \
+            / np.maximum(np.abs(y), 1e-3).max()
+        # Entries near equilibrium are small differences of large forward and
+        # reverse terms; an analytic Jacobian carries an absolute error set by
+        # those terms, which complex step does not.  The oracle's own analytic
+        # Jacobian measures that conditioning, so its gap to complex step
+        # (4x) is allowed on top of the relative bound.
+        Ja = om.jac(p[i], y)
+        tol = 1e-10 * (np.abs(Jo) + sc) + 4.0 * np.abs(Ja - Jo)
+        off = np.argwhere(~(np.abs(J[i] - Jo) <= tol))
+        assert len(off) == 0, (key, i, [(int(r), int(c), J[i][r, c], Jo[r, c], tol[r, c]) for r, c in off[:6]])
+
+
+@pytest.mark.parametrize("key", ["m32", "m9w", "m13w"])
+def test_wide_integrate_uniform_matches_oracle(chem, mechs, dev, key):
+    gm, om = mechs[key]
+    name = key.rstrip("w")
+    n = 515                                              # not a multiple of the cells per wave
+    T, p, Y = uniform_cells(mech_text(name), n, 72)
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL,
+                                               return_counts=True)
+    To, Yo, nao, nro, sto = om.integrate(T, p, Y, 1e-8, RTOL, ATOL)
+    assert stats["failed"] == 0 and np.all(sto == 0) and stats["cells"] == n
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, key)
+    differ = np.sum((na.cpu().numpy() != nao) | (nr.cpu().numpy() != nro))
+    assert differ <= max(2, 0.01 * n), f"{differ} cells took a different step sequence"
+
+
+def test_wide_big4m_field_sample(chem, mechs, dev):
+    """The 2048 x 2048 RDE-shaped field with the 32-species mechanism at full
+    size: sampled cells of every region against the oracle, and properties
+    that hold for every cell; plain and persistent forms bitwise equal."""
+    w = WORKLOADS["big4m"]
+    gm, om = mechs["m32"]
+    T, p, Y, reg = rde_field(mech_text("m32"), w["width"], w["height"], w["seed"])
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([rng.choice(np.where(reg == r)[0], 200, replace=False) for r in (0, 1, 2)])
+    To, Yo, _, _, _ = om.integrate(T[idx], p[idx], Y[idx], w["dt"], w["rtol"], w["atol"])
+    out = {}
+    for form in (chem.FORM_PLAIN, chem.FORM_PERSISTENT):
+        Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), w["dt"], w["rtol"],
+                                                   w["atol"], form=form, return_counts=True)
+        assert stats["failed"] == 0 and stats["cells"] == len(T)
+        Tn, Yn = Tg.cpu().numpy(), Yg.cpu().numpy()
+        _assert_state_parity(Tn[idx], Yn[idx], To, Yo, f"big4m form {form}")
+        nsub = (na + nr).cpu().numpy()
+        assert np.all(np.abs(Yn.sum(1) - 1.0) <= 1e-13 * np.maximum(nsub, 1) + 1e-14)
+        out[form] = (Tg, Yg, na, nr)
+    for a, b in zip(out[chem.FORM_PLAIN], out[chem.FORM_PERSISTENT]):
+        assert torch.equal(a, b)
+
+
+def test_wide_batched_fields(chem, mechs, dev):
+    """Several fields of different sizes (ragged, tiny, empty) in one
+    persistent launch equal per-field plain launches bitwise."""
+    gm, om = mechs["m32"]
+    sizes = [700, 1, 0, 3001, 64, 17]
+    fields = [rde_field_n(mech_text("m32"), n, 900 + i)[:3] for i, n in enumerate(sizes)]
+    Ts = [_g(f[0], dev) for f in fields]
+    ps = [_g(f[1], dev) for f in fields]
+    Ys = [_g(f[2].reshape(-1, gm.ns), dev) for f in fields]
+    stats = chem.integrate_batched(gm, Ts, ps, Ys, 5e-9, RTOL, ATOL)
+    assert stats["cells"] == sum(sizes) and stats["failed"] == 0
+    for (T, p, Y), Tb, Yb in zip(fields, Ts, Ys):
+        if len(T) == 0:
+            continue
+        Tr, Yr, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL)
+        assert torch.equal(Tr, Tb) and torch.equal(Yr, Yb)
+        To, Yo, _, _, _ = om.integrate(T, p, Y, 5e-9, RTOL, ATOL)
+        _assert_state_parity(Tb.cpu().numpy(), Yb.cpu().numpy(), To, Yo, "batched m32")
+
+
+def test_wide_bad_cells_and_limits(chem, mechs, dev):
+    gm, om = mechs["m13w"]
+    T, p, Y = uniform_cells(mech_text("m13"), 9, 73)
+    T[2] = -10.0
+    Y[3, 4] = np.nan
+    p[5] = 0.0
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL,
+                                               return_counts=True, allow_failed=True)
+    st = st.cpu().numpy()
+    assert list(np.where(st == 4)[0]) == [2, 3, 5] and stats["failed"] == 3
+    assert Tg[2].item() == -10.0 and np.isnan(Yg[3, 4].item())
+    ok = [i for i in range(9) if i not in (2, 3, 5)]
+    To, Yo, _, _, _ = om.integrate(T[ok], p[ok], Y[ok], 1e-8, RTOL, ATOL)
+    _assert_state_parity(Tg.cpu().numpy()[ok], Yg.cpu().numpy()[ok], To, Yo, "good cells")
+    # max_substeps = 1 as in the oracle
+    T2, p2, Y2 = uniform_cells(mech_text("m13"), 64, 74)
+    _, _, _, st2, na2, nr2 = chem.integrate(gm, _g(T2, dev), _g(p2, dev), _g(Y2, dev), 1e-8, RTOL, ATOL,
+                                            max_substeps=1, return_counts=True, allow_failed=True)
+    _, _, _, _, sto = om.integrate(T2, p2, Y2, 1e-8, RTOL, ATOL, max_substeps=1)
+    assert np.array_equal(st2.cpu().numpy(), sto)
+    # calls the form does not provide say so
+    with pytest.raises(chem.ChemError) as e:
+        chem.step_fixed(gm, _g(T2, dev), _g(p2, dev), _g(Y2, dev), 1e-9)
+    assert e.value.code == -8
