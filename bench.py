@@ -153,6 +153,44 @@ def amr_leg(chem, torch, dev, steps):
     return out
 
 
+def big_leg(chem, torch, dev, steps):
+    """The 2048 x 2048 RDE-shaped field (4,194,304 cells) with the 32-species /
+    150-reaction mechanism (third-body + Troe on 15 reactions), which runs in
+    the wave-cooperative form (one 64-lane wave per cell): plain and
+    persistent launches, same tolerances."""
+    from workloads import WORKLOADS, mech_path, mech_text
+    from workloads.states import rde_field
+    w = WORKLOADS["big4m"]
+    mech = chem.Mechanism(mech_path(w["mech"]))
+    T, p, Y, _ = rde_field(mech_text(w["mech"]), w["width"], w["height"], w["seed"])
+    n = len(T)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    T0, p0, Y0 = t(T), t(p), t(Y)
+    Tw, Yw = T0.clone(), Y0.clone()
+    fper = flops_per_substep(mech.ns, mech.nr)
+    out = {"workload": "big4m", "cells": n, "mechanism": f"{w['mech']} ({mech.ns} species, {mech.nr} reactions)",
+           "dt": w["dt"], "rtol": w["rtol"], "atol": w["atol"], "flops_per_substep": fper}
+    for name, form in (("persistent", chem.FORM_PERSISTENT), ("plain", chem.FORM_PLAIN)):
+        def step(stats=False):
+            Tw.copy_(T0)
+            Yw.copy_(Y0)
+            return chem.integrate(mech, Tw, p0, Yw, w["dt"], w["rtol"], w["atol"], form=form, inplace=True,
+                                  stats=stats)[2]
+        st = step(stats=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        subs = st["accepted"] + st["rejected"]
+        out[name] = {"ms_per_step": ms, "cell_steps_per_s": n / (ms * 1e-3), "substeps": subs,
+                     "max_substeps_cell": st["max_substeps"], "kernel_ms": st["kernel_ms"],
+                     "achieved_tflops": subs * fper / (ms * 1e-3) / 1e12,
+                     "frac_fp64_peak": subs * fper / (ms * 1e-3) / PEAK_FP64_VALU}
+    return out
+
+
 def adjoint_leg(chem, torch, dev, steps, cpu_cells):
     """The discrete adjoint on the 512 x 512 adjoint field (262,144 cells, dt
     1e-8 s): L = sum over cells of T_end / 1000 K + Y_H2O,end; gradients with
@@ -223,6 +261,8 @@ def main():
                                         "persistent_natural,plain")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-big", action="store_true")
+    ap.add_argument("--big-only", action="store_true")
     ap.add_argument("--amr-only", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true")
     ap.add_argument("--adjoint-cpu-cells", type=int, default=192)
@@ -249,6 +289,9 @@ def main():
     from workloads import WORKLOADS, mech_path, mech_text
     from workloads.states import rde_field
 
+    if args.big_only:
+        print(json.dumps({"big4m": big_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps))}))
+        return
     if args.amr_only:
         print(json.dumps({"amr64": amr_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps))}))
         return
@@ -364,6 +407,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
     if not args.no_amr:
         line["amr64"] = amr_leg(chem, torch, dev, 1)
+    if not args.no_big:
+        line["big4m"] = big_leg(chem, torch, dev, 2)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else args.adjoint_cpu_cells)
     print(json.dumps(line))
