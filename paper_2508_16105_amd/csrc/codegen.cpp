@@ -599,13 +599,35 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
                 snu.push_back(v);
             }
         }
+        while ((srx.size() - off.back()) % 4) {   // padded to a multiple of 4 (coefficient 0)
+            srx.push_back(0);
+            snu.push_back(0);
+        }
         off.push_back((int)srx.size());
     }
     o << "// species k: the reactions that change it, SP_RX[SP_OFF[k] .. SP_OFF[k+1]),\n"
-         "// with net coefficients SP_NU\n";
+         "// with net coefficients SP_NU (padded to a multiple of 4 by coefficient 0)\n";
     ints("SP_OFF", off);
     ints("SP_RX", srx);
     ints("SP_NU", snu);
+    // non-elementary reactions t: their slot, and the net coefficient of every
+    // species in them (the dense third-body part of the Jacobian rows)
+    std::vector<int> tbslot;
+    std::vector<double> nutb;
+    for (int s = 0; s < nr; ++s)
+        if (effrow[s] >= 0) tbslot.push_back(s);
+    for (int k = 0; k < ns; ++k)
+        for (int s : tbslot) {
+            const auto& r = m.reactions[order[s]];
+            int v = 0;
+            for (auto& t : r.reac) if (t.sp == k) v -= t.nu;
+            for (auto& t : r.prod) if (t.sp == k) v += t.nu;
+            nutb.push_back((double)v);
+        }
+    o << "constexpr int NTB = " << tbslot.size() << ";\n"
+         "// non-elementary reaction t: its slot (EFF row t), and NU_TB[k * NTB + t]\n";
+    ints("TB_SLOT", tbslot);
+    dbls("NU_TB", nutb);
     o << "}  // namespace mech\n";
     return o.str();
 }

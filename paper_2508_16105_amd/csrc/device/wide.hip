@@ -10,13 +10,14 @@
 //   - mixture sums (sum Y/W, c_p, heat release) as group reductions;
 //   - reaction rates spread over the lanes, read from the mechanism tables
 //     (reactions grouped by kind so a round of lanes mostly takes one branch);
-//   - production rates and Jacobian rows gathered by each species lane from
-//     the cell's LDS scratch in a fixed order (results are reproducible);
+//   - production rates gathered, and Jacobian rows assembled, by each species
+//     lane from the rates and partials in the cell's LDS scratch in a fixed
+//     order (reproducible results);
 // and per step the LU factorisation with partial pivoting (pivot search as a
 // group arg-max, the pivot row broadcast from its lane), the triangular
 // solves (one broadcast per column) and the RMS error norm (a group sum).
-// Reductions are xor-butterflies: every lane of a group ends with the same
-// bits, so the step-size controller runs identically in all of them.
+// Reductions leave the same bits in every lane of a group, so the step-size
+// controller runs identically in all of them.
 //
 // The equations, the RODAS4 tableau and the controller are those of the
 // one-cell-per-lane integrator (the species/energy source of eqs. (20)-(21)
@@ -36,6 +37,11 @@ constexpr int ROUNDS = (NR + G - 1) / G;
 static_assert(N <= G && G <= 64 && (G & (G - 1)) == 0, "group size");
 
 __device__ __forceinline__ int gl() { return (int)(threadIdx.x & (unsigned)(G - 1)); }
+
+// the lane index behind an opaque zero: compares against it (i == k for
+// every k of an unrolled loop) are made where used instead of being hoisted
+// out of the substep loop as dozens of live lane masks
+__device__ __forceinline__ int gl_local() { return gl() + mech::opaque_zero(); }
 __device__ __forceinline__ int gbase() { return (int)(threadIdx.x & 63u & ~(unsigned)(G - 1)); }
 
 // value of x in lane `src` of this group; src is the same in every lane of the group
@@ -54,19 +60,67 @@ __device__ __forceinline__ double bcast(double x, int src)
 // value of x in lane `src` of this group; src may differ per lane
 __device__ __forceinline__ double gather(double x, int src) { return __shfl(x, gbase() + src, 64); }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Group reductions.  Inside each 16-lane row a butterfly over the DPP
+// patterns xor 1, xor 2, mirror-in-8 and mirror-in-16: each step adds a
+// lane's value to its partner's and the partner adds the same two numbers,
+// so every lane of the row ends with the same bits; rows are then combined
+// in a fixed order from their last lanes.
+template <class Op>
+__device__ __forceinline__ double greduce(double x, Op op)
+{
+    x = op(x, dpp<0xB1>(x));    // quad_perm [1, 0, 3, 2]
+    x = op(x, dpp<0x4E>(x));    // quad_perm [2, 3, 0, 1]
+    x = op(x, dpp<0x141>(x));   // row_half_mirror
+    x = op(x, dpp<0x140>(x));   // row_mirror
+    if constexpr (G == 16) {
+        return x;
+    } else if constexpr (G == 32) {
+        const double r0 = readlane(x, 15), r1 = readlane(x, 31), r2 = readlane(x, 47), r3 = readlane(x, 63);
+        return gbase() == 0 ? op(r0, r1) : op(r2, r3);
+    } else {
+        const double r0 = readlane(x, 15), r1 = readlane(x, 31), r2 = readlane(x, 47), r3 = readlane(x, 63);
+        return op(op(r0, r1), op(r2, r3));
+    }
+}
+
 __device__ __forceinline__ double gsum(double x)
 {
-#pragma unroll
-    for (int m = 1; m < G; m <<= 1) x += __shfl_xor(x, m, 64);
-    return x;
+    return greduce(x, [](double a, double b) { return a + b; });
+}
+
+__device__ __forceinline__ double gmax(double x)
+{
+    return greduce(x, [](double a, double b) { return fmax(a, b); });
+}
+
+// bits of this group's lanes in a wave-wide ballot, lane 0 of the group at bit 0
+__device__ __forceinline__ unsigned long long gbits(unsigned long long ballot)
+{
+    if constexpr (G == 64) return ballot;
+    else return (ballot >> gbase()) & ((1ull << G) - 1ull);
 }
 
 // true in every lane of the group if `bad` holds in any lane of it
 __device__ __forceinline__ bool gany(bool bad)
 {
-    const unsigned long long b = __ballot(bad);
-    if constexpr (G == 64) return b != 0ull;
-    else return ((b >> gbase()) & ((1ull << G) - 1ull)) != 0ull;
+    return gbits(__ballot(bad)) != 0ull;
 }
 
 // LDS writes of this wave visible to its later LDS reads
@@ -215,6 +269,10 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     const int i = gl();
     const bool sp = i >= 1 && i <= NS;
     const int k = sp ? i - 1 : 0;
+    // constant tables at an opaque offset: their uniform loads stay inside this
+    // evaluation instead of being hoisted out of the substep loop into SGPRs
+    const int z = mech::opaque_zero();
+    mech::cdbl* MW = (mech::cdbl*)&mech::MWTAB[0] + z;
     if (i < N) L[mech::L_Y + i] = yi;
     lds_sync();
     const double T = L[mech::L_Y];
@@ -249,8 +307,8 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
             dcpR = a + c[15];
         }
     }
-    const double W = sp ? mech::MWTAB[k] : 0.0;
-    const double iW = sp ? mech::MWTAB[NS + k] : 0.0;
+    const double W = sp ? MW[k] : 0.0;
+    const double iW = sp ? MW[NS + k] : 0.0;
     const double yw = sp ? yi * iW : 0.0;
     const double sig = gsum(yw);
     const double Wbar = 1.0 / sig;
@@ -270,10 +328,21 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
         if (j < NR) reaction<JAC>(j, par, L, T, lnT, iT, lnPRT, ctot);
     }
     lds_sync();
+    // species lists come padded to multiples of 4: four entries' loads in flight
+    const double* __restrict__ Q = L + mech::L_Q;
     double wdot = 0.0;
     if (sp) {
-        for (int e = mech::SP_OFF[k]; e < mech::SP_OFF[k + 1]; ++e)
-            wdot = fma((double)mech::SP_NU[e], L[mech::L_Q + mech::SP_RX[e]], wdot);
+        const int e1 = mech::SP_OFF[k + 1];
+        for (int e = mech::SP_OFF[k]; e < e1; e += 4) {
+            double q[4], nu[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                nu[u] = (double)mech::SP_NU[e + u];
+                q[u] = Q[mech::SP_RX[e + u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) wdot = nu[u] != 0.0 ? fma(nu[u], q[u], wdot) : wdot;
+        }
     }
     const double cpm = gsum(cpR * yw);
     const double hw = gsum(HRT * wdot);
@@ -284,27 +353,62 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     const double fi = sp ? fk : (i == 0 ? fT : 0.0);
     if (!JAC) return fi;
 
-    // concentration Jacobian row k: Jc_km = d wdot_k / d C_m (fixed T), and
-    // column NS: wT_k = d wdot_k / dT (fixed C)
+    // Row k of the concentration Jacobian: Jc_km = d wdot_k / d C_m (fixed T)
+    // and wT_k = d wdot_k / dT (fixed C) in column NS.  The species partials
+    // of the lane's reactions go into its own LDS row by atomic adds (one
+    // lane per address, applied in program order: reproducible); the
+    // third-body part, dense over m, accumulates in registers.
     double* Jr = L + mech::L_J + k * JW;
     if (sp) {
-        for (int m = 0; m <= NS; ++m) Jr[m] = 0.0;
-        for (int e = mech::SP_OFF[k]; e < mech::SP_OFF[k + 1]; ++e) {
-            const int j = mech::SP_RX[e];
-            const double nu = (double)mech::SP_NU[e];
-            const double* P = L + mech::L_P + j * PW;
 #pragma unroll
-            for (int s = 0; s < NSLOT; ++s) {
-                const int m = mech::RX_SP[j * NSLOT + s];
-                if (m >= 0) Jr[m] = fma(nu, P[s], Jr[m]);
+        for (int m = 0; m <= NS; ++m) Jr[m] = 0.0;
+    }
+    lds_sync();
+    if (sp) {
+        const double* __restrict__ Pb = L + mech::L_P;
+        const int e1 = mech::SP_OFF[k + 1];
+        for (int e = mech::SP_OFF[k]; e < e1; e += 4) {
+            int j[4], ms[4][NSLOT];
+            double nu[4], P[4][NSLOT + 1];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                j[u] = mech::SP_RX[e + u];
+                nu[u] = (double)mech::SP_NU[e + u];
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) ms[u][s] = mech::RX_SP[j[u] * NSLOT + s];
+#pragma unroll
+                for (int s = 0; s <= NSLOT; ++s) P[u][s] = Pb[j[u] * PW + s];
             }
-            Jr[NS] = fma(nu, P[NSLOT], Jr[NS]);
-            const int er = mech::RX_EFFROW[j];
-            if (er >= 0) {
-                const double dM = nu * P[NSLOT + 1];
-                for (int m = 0; m < NS; ++m) Jr[m] = fma(mech::EFF[er * NS + m], dM, Jr[m]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (nu[u] == 0.0) continue;
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s)
+                    if (ms[u][s] >= 0) atomicAdd(&Jr[ms[u][s]], nu[u] * P[u][s]);
+                atomicAdd(&Jr[NS], nu[u] * P[u][NSLOT]);
             }
         }
+    }
+    double R[NS + 1];
+#pragma unroll
+    for (int m = 0; m <= NS; ++m) R[m] = 0.0;
+    // the efficiencies by scalar loads at an opaque offset, so they are loaded
+    // here, one reaction at a time, not hoisted out of the substep loop
+    mech::cdbl* EF = (mech::cdbl*)&mech::EFF[0] + z;
+#pragma unroll 1
+    for (int t = 0; t < mech::NTB; ++t) {
+        const double d = (sp ? mech::NU_TB[k * mech::NTB + t] : 0.0) *
+                         L[mech::L_P + mech::TB_SLOT[t] * PW + NSLOT + 1];
+        mech::cdbl* eff = EF + t * NS;
+#pragma unroll
+        for (int m = 0; m < NS; ++m) R[m] = fma(eff[m], d, R[m]);
+    }
+    lds_sync();
+    if (sp) {
+#pragma unroll
+        for (int m = 0; m <= NS; ++m) R[m] += Jr[m];
+#pragma unroll
+        for (int m = 0; m <= NS; ++m) Jr[m] = R[m];
     }
     lds_sync();
     // chain rule to (T, Y), with S_k = sum_l Jc_kl C_l:
@@ -316,8 +420,9 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     // cpw = sum_k cp_k/R wdot_k
     double Sk = 0.0, wT = 0.0;
     if (sp) {
-        for (int m = 0; m < NS; ++m) Sk = fma(Jr[m], L[mech::L_C + m], Sk);
-        wT = Jr[NS];
+#pragma unroll
+        for (int m = 0; m < NS; ++m) Sk = fma(R[m], L[mech::L_C + m], Sk);
+        wT = R[NS];
     }
     const double HS = gsum(HRT * Sk);
     const double HwT = gsum(HRT * wT);
@@ -338,7 +443,7 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
         const double g = fma(-W, Sk * irho, fk);
         const double wg = Wbar * g;
 #pragma unroll
-        for (int m = 0; m < NS; ++m) A[1 + m] = fma(Jr[m], W, wg) * mech::MWTAB[NS + m];
+        for (int m = 0; m < NS; ++m) A[1 + m] = fma(R[m], W, wg) * MW[NS + m];
         A[0] = fma(W * irho, wT - Sk * iT, fk * iT);
     } else if (i == 0) {
         A[0] = -mech::RU * (cpw + T * HwT - HS) * rcpinv - fT * (dcp * icp - iT);
@@ -353,36 +458,43 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
 
 // LU with partial pivoting of the group's matrix (row i in lane i), in place:
 // multipliers below the diagonal, U above, reciprocal pivots on the diagonal.
-// piv[k]: row swapped into k at step k (LINPACK order, the lowest row index
-// among equal magnitudes); bit k of the result: some group of the wave swapped.
-__device__ __forceinline__ unsigned long long lu(double (&A)[N], int (&piv)[N], bool& ok)
+// piv[k] (in the cell's LDS scratch, after the pivot row): row swapped into k
+// at step k (LINPACK order, the lowest row index among equal magnitudes); bit
+// k of the result: some group of the wave swapped.
+__device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, double* __restrict__ L)
 {
-    const int i = gl();
+    const int i = gl_local();
+    double* PR = L + mech::L_J;     // pivot row (the Jacobian rows are consumed by now)
+    int* piv = (int*)(PR + N);      // pivot indices, read by the solves only on a swap
     unsigned long long swaps = 0ull;
     ok = true;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double v = (i >= k && i < N) ? fabs(A[k]) : -1.0;
-        int idx = i;
-#pragma unroll
-        for (int m = 1; m < G; m <<= 1) {
-            const double v2 = __shfl_xor(v, m, 64);
-            const int i2 = __shfl_xor(idx, m, 64);
-            const bool take = v2 > v || (v2 == v && i2 < idx);
-            v = take ? v2 : v;
-            idx = take ? i2 : idx;
-        }
-        piv[k] = idx;
-        ok = ok && (v > 0.0);
+        // the column's largest magnitude (a max is exact in any order), then the
+        // lowest row that reaches it
+        const double v = (i >= k && i < N) ? fabs(A[k]) : -1.0;
+        const double vmax = gmax(v);
+        const unsigned long long hit = gbits(__ballot(v == vmax));
+        int idx = hit ? __builtin_ctzll(hit) : k;
+        if (!(vmax > 0.0)) idx = k;
+        if (i == 0) piv[k] = idx;
+        ok = ok && (vmax > 0.0);
         if (__any(idx != k)) {
             swaps |= 1ull << k;
             const int src = (i == k) ? idx : (i == idx ? k : i);
 #pragma unroll
             for (int j = k; j < N; ++j) A[j] = gather(A[j], src);
         }
+        // the pivot row through LDS: one lane writes it, every lane reads it
+        if (i == k) {
+#pragma unroll
+            for (int j = k; j < N; ++j) PR[j] = A[j];
+        }
+        lds_sync();
         double prow[N];
 #pragma unroll
-        for (int j = k; j < N; ++j) prow[j] = bcast(A[j], k);
+        for (int j = k; j < N; ++j) prow[j] = PR[j];
+        lds_sync();
         const double rp = 1.0 / prow[k];
         if (i == k) {
             A[k] = rp;
@@ -397,10 +509,11 @@ __device__ __forceinline__ unsigned long long lu(double (&A)[N], int (&piv)[N], 
 }
 
 // Solve (LU) x = b for the group's vector b (component i in lane i).
-__device__ __forceinline__ double solve(const double (&A)[N], const int (&piv)[N], unsigned long long swaps,
-                                        double b)
+__device__ __forceinline__ double solve(const double (&A)[N], const double* __restrict__ L,
+                                        unsigned long long swaps, double b)
 {
-    const int i = gl();
+    const int i = gl_local();
+    const int* piv = (const int*)(L + mech::L_J + N);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         if (swaps & (1ull << k)) {
@@ -425,30 +538,38 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
                                          double rtol, double atol, double* __restrict__ L, double& ynew,
                                          double& errn)
 {
-    const int i = gl();
+    const int i = gl_local();
     double A[N];
     const double f0 = rhs<true>(par, p, ip, yi, L, A);
     const double ghinv = 1.0 / (h * Rodas4::gamma);
     const double hinv = 1.0 / h;
 #pragma unroll
     for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - A[j];
-    int piv[N];
     bool ok;
-    const unsigned long long swaps = lu(A, piv, ok);
+    const unsigned long long swaps = lu(A, ok, L);
     double u[Rodas4::S];
-    u[0] = solve(A, piv, swaps, f0);
-    double dummy[N];
+    u[0] = solve(A, L, swaps, f0);
 #pragma unroll
+    for (int s = 1; s < Rodas4::S; ++s) u[s] = 0.0;
+    double dummy[N];
+    // one copy of the source-term code for the five later stages (the kernel
+    // stays inside the instruction cache); stage vectors stay in registers
+#pragma unroll 1
     for (int s = 1; s < Rodas4::S; ++s) {
         double Ys = yi, acc = 0.0;
 #pragma unroll
-        for (int j = 0; j < s; ++j) {
-            Ys = fma(RA[s][j], u[j], Ys);
-            acc = fma(RC[s][j], u[j], acc);
+        for (int j = 0; j < Rodas4::S - 1; ++j) {
+            if (j < s) {
+                Ys = fma(RA[s][j], u[j], Ys);
+                acc = fma(RC[s][j], u[j], acc);
+            }
         }
         if (s == Rodas4::S - 1) ynew = Ys;
         const double fs = rhs<false>(par, p, ip, Ys, L, dummy);
-        u[s] = solve(A, piv, swaps, fma(acc, hinv, fs));
+        const double us = solve(A, L, swaps, fma(acc, hinv, fs));
+#pragma unroll
+        for (int j = 1; j < Rodas4::S; ++j)
+            if (j == s) u[j] = us;
     }
     ynew += u[Rodas4::S - 1];
     const double sc = atol + rtol * fmax(fabs(yi), fabs(ynew));
@@ -539,7 +660,7 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
 }  // namespace chemw
 
 // ---- plain form: one group of G lanes per cell, cells in index order ----
-extern "C" __global__ void __launch_bounds__(64) chem_plain(chem::IntegrateArgs a)
+extern "C" __global__ void __launch_bounds__(64, 2) chem_plain(chem::IntegrateArgs a)
 {
     using namespace chemw;
     chem_math::exp_table_init(mech::EXP2_J64);
@@ -586,7 +707,7 @@ extern "C" __global__ void __launch_bounds__(64) chem_eval(EvalArgs a)
 // next cell when its current one is done, so no group idles while cells
 // remain (the hardware already balances whole waves; this also balances the
 // groups inside a wave and spans several fields in one launch).
-extern "C" __global__ void __launch_bounds__(64) chem_persistent(const PersistBlock* __restrict__ blk,
+extern "C" __global__ void __launch_bounds__(64, 2) chem_persistent(const PersistBlock* __restrict__ blk,
                                                                  unsigned long long* __restrict__ heads,
                                                                  const double* __restrict__ par)
 {
