@@ -18,9 +18,9 @@ PKG = pathlib.Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libchemmi.so"
 ROOT = PKG.parent
-PREBUILT_MECHANISMS = ["m9", "m13", "m32"]
-# also built in the wave-cooperative form (their lane form is the default)
-PREBUILT_WIDE = ["m9", "m13"]
+# (mechanism, CHEM_LANE_MAX_SPECIES at load): the default builds and the
+# wave-cooperative builds of the 9- and 13-species mechanisms
+PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0")]
 HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "codegen.cpp"]
 
 
@@ -49,24 +49,24 @@ def compile_host(verbose=False):
     os.replace(tmp, LIB)
 
 
-def prebuild_mechanisms(names=None):
+def prebuild_mechanisms(builds=None):
     """Compile the device code of the committed mechanisms into the cache."""
     sys.path.insert(0, str(ROOT))
     from paper_2508_16105_amd import _lib
     mdir = ROOT / "workloads" / "mech"
-    for nm in names or PREBUILT_MECHANISMS:
-        _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
-    if names is None:
-        old = os.environ.get("CHEM_LANE_MAX_SPECIES")
-        os.environ["CHEM_LANE_MAX_SPECIES"] = "0"
-        try:
-            for nm in PREBUILT_WIDE:
-                _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
-        finally:
-            if old is None:
-                del os.environ["CHEM_LANE_MAX_SPECIES"]
+    old = os.environ.get("CHEM_LANE_MAX_SPECIES")
+    try:
+        for nm, lane_max in builds or PREBUILT:
+            if lane_max is None:
+                os.environ.pop("CHEM_LANE_MAX_SPECIES", None)
             else:
-                os.environ["CHEM_LANE_MAX_SPECIES"] = old
+                os.environ["CHEM_LANE_MAX_SPECIES"] = lane_max
+            _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
+    finally:
+        if old is None:
+            os.environ.pop("CHEM_LANE_MAX_SPECIES", None)
+        else:
+            os.environ["CHEM_LANE_MAX_SPECIES"] = old
 
 
 def prune_cache(since):

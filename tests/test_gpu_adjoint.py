@@ -133,6 +133,35 @@ def test_adjoint_m13_falloff_and_third_body(chem, mechs, dev):
     _assert_grad_parity(gT0, gY0, ga, gb, ge, ref, spread, "m13")
 
 
+def test_adjoint_of_a_wave_cooperative_mechanism(chem, mechs, dev):
+    """A mechanism held in the wave-cooperative form takes its adjoint from a
+    one-cell-per-lane build made on first use: same gradients as the lane
+    form's own adjoint, bitwise, also after a parameter change."""
+    import os
+    gm, _ = mechs["m13"]
+    old = os.environ.get("CHEM_LANE_MAX_SPECIES")
+    os.environ["CHEM_LANE_MAX_SPECIES"] = "0"
+    try:
+        gw = chem.Mechanism(mech_path("m13"))
+    finally:
+        if old is None:
+            del os.environ["CHEM_LANE_MAX_SPECIES"]
+        else:
+            os.environ["CHEM_LANE_MAX_SPECIES"] = old
+    T, p, Y = uniform_cells(mech_text("m13"), 40, 67)
+    gT, gY = _loss_weights("m13", len(T), True, seed=16)
+    for scale in (0.0, 0.1):
+        lnA, b, Ea = gm.get_params()
+        for m in (gm, gw):
+            m.set_params(lnA + scale, b, Ea)
+        a = _run(chem, gm, T, p, Y, 1e-8, gT, gY, dev)
+        w = _run(chem, gw, T, p, Y, 1e-8, gT, gY, dev)
+        for x, y in zip(a[:7], w[:7]):
+            assert np.array_equal(x, y)
+        for m in (gm, gw):
+            m.set_params(lnA, b, Ea)
+
+
 def test_adjoint_forward_result_equals_integrate(chem, mechs, dev):
     gm, _ = mechs["m9"]
     T, p, Y = uniform_cells(mech_text("m9"), 300, 62)
