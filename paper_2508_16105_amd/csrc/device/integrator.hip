@@ -659,6 +659,7 @@ struct AdjointArgs {
     const long* off_h;     // first step size of each cell in hs
     const long* off_ck;    // first checkpoint of each cell (in states of N doubles)
     const int* nacc_fwd;   // accepted steps of the sizing pass
+    const int* order;      // cells by descending accepted steps (lane g takes cell order[g])
     const double* h0;      // nullable: per-cell first step, else dt
     double* hs;
     double* ck;
@@ -673,8 +674,10 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
 {
     using namespace chem;
     chem_math::exp_table_init(mech::EXP2_J64);
-    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= a.ncell) return;
+    const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.ncell) return;
+    // cells of similar cost share a wave, so no lane waits long for the slowest
+    const long cell = a.order[slot];
     extern __shared__ double lds[];
     double* ul = lds + threadIdx.x;
     const int ls = blockDim.x;

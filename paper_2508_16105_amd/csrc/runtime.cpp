@@ -543,9 +543,16 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     HIPCHECK(hipMemcpyAsync(Tw, T0, sizeof(double) * ncell, hipMemcpyDeviceToDevice, stream), "copy T0");
     HIPCHECK(hipMemcpyAsync(Yw, Y0, sizeof(double) * ncell * ns, hipMemcpyDeviceToDevice, stream), "copy Y0");
     const StepArgs step = step_args(dt, rtol, atol, o);
-    IntegrateArgs ia{d->par, Tw, p, Yw, (long)ncell, o.h0, st, na_fwd, nj, step};
-    if (int rc = launch_1d(d->f_plain, ncell, 64, &ia, sizeof ia, stream, "chem_plain", d->stage_lds(64)))
-        return rc;
+    if (o.h0) {
+        IntegrateArgs ia{d->par, Tw, p, Yw, (long)ncell, o.h0, st, na_fwd, nj, step};
+        if (int rc = launch_1d(d->f_plain, ncell, 64, &ia, sizeof ia, stream, "chem_plain", d->stage_lds(64)))
+            return rc;
+    } else {   // the persistent form takes the same steps, bitwise, sooner
+        FieldView fv{Tw, p, Yw, ncell, st, na_fwd, nj, nullptr, nullptr};
+        Options po = o;
+        po.form = CHEM_FORM_PERSISTENT;
+        if (int rc = run_persistent(m, &fv, 1, dt, rtol, atol, po, nullptr, stream)) return rc;
+    }
     std::vector<int32_t> nacc_h(ncell);
     HIPCHECK(hipMemcpyAsync(nacc_h.data(), na_fwd, sizeof(int32_t) * ncell, hipMemcpyDeviceToHost, stream),
              "copy step counts");
@@ -559,6 +566,20 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         th += k;
         tc += (k + K - 1) / K;
     }
+    // cells by descending accepted steps (a counting sort, stable in cell index)
+    std::vector<int32_t> order(ncell);
+    {
+        int32_t mx = 0;
+        for (int64_t c = 0; c < ncell; ++c) mx = std::max(mx, std::max<int32_t>(nacc_h[c], 0));
+        std::vector<int64_t> start(mx + 2, 0);
+        for (int64_t c = 0; c < ncell; ++c) ++start[mx - std::max<int32_t>(nacc_h[c], 0) + 1];
+        for (int32_t b = 0; b <= mx; ++b) start[b + 1] += start[b];
+        for (int64_t c = 0; c < ncell; ++c) order[start[mx - std::max<int32_t>(nacc_h[c], 0)]++] = (int32_t)c;
+    }
+    int32_t* order_d;
+    if (int rc = s.alloc(&order_d, (size_t)ncell, "adjoint order")) return rc;
+    HIPCHECK(hipMemcpyAsync(order_d, order.data(), sizeof(int32_t) * ncell, hipMemcpyHostToDevice, stream),
+             "copy order");
     long* off_d;
     double *hs, *ck, *gpar;
     if (int rc = s.alloc(&off_d, 2 * (size_t)ncell, "adjoint offsets")) return rc;
@@ -568,7 +589,7 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     HIPCHECK(hipMemcpyAsync(off_d, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, stream),
              "copy offsets");
     AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, T_end, Y_end, off_d,
-                   off_d + ncell, na_fwd, o.h0, hs, ck, st, na, nj, step, K};
+                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     if (int rc = launch_1d(d->f_adjoint, ncell, 64, &aa, sizeof aa, stream, "chem_adjoint", d->stage_lds(64)))
         return rc;

@@ -75,6 +75,7 @@ struct AdjointArgs {
     const long* off_h;
     const long* off_ck;
     const int* nacc_fwd;
+    const int* order;
     const double* h0;
     double* hs;
     double* ck;
