@@ -26,6 +26,7 @@ RODAS4_STAGES = 6
 # The device code of a mechanism is generated from these files; HBM traffic
 # recorded under profiles/ applies only while their hash is unchanged.
 KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
+                  "paper_2508_16105_amd/csrc/device/common.hip",
                   "paper_2508_16105_amd/csrc/device/math.hip",
                   "paper_2508_16105_amd/csrc/codegen.cpp",
                   "paper_2508_16105_amd/csrc/module.cpp"]
