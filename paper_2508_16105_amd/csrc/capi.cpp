@@ -28,9 +28,8 @@ namespace {
 // wave-cooperatively.  At 13 species the lane form spills registers but keeps
 // 64 cells in flight per SIMD against 8, and wins on large fields; the
 // wave-cooperative form has the shorter latency per cell.
-// CHEM_LANE_MAX_SPECIES overrides the choice at load time.  The
-// one-cell-per-lane code is built for at most kMaxLaneSpecies species; it
-// also serves the adjoint of wave-cooperative mechanisms up to that size.
+// CHEM_LANE_MAX_SPECIES overrides the choice at load time (the lane form is
+// built for at most kMaxLaneSpecies species).
 constexpr int kLaneSpecies = 20;
 constexpr int kMaxLaneSpecies = 20;
 
@@ -44,32 +43,6 @@ int lane_max_species()
     return kLaneSpecies;
 }
 
-// The one-cell-per-lane build of a wave-cooperative mechanism (made once).
-int lane_twin(chem_mechanism* m, chem_mechanism** out)
-{
-    if (!m->wide) {
-        *out = m;
-        return 0;
-    }
-    if (m->data.ns() > kMaxLaneSpecies)
-        return set_error(CHEM_E_UNSUPPORTED, "the adjoint is built for at most " + std::to_string(kMaxLaneSpecies) +
-                                                 " species");
-    if (!m->lane_twin) {
-        auto t = std::make_unique<chem_mechanism>();
-        t->data = m->data;
-        t->source = device_source(generate_mechanism_source(t->data), false);
-        std::string err;
-        if (int rc = build_code_object(t->source, t->code, err, &t->cache_file)) return set_error(rc, err);
-        m->lane_twin = t.release();
-    }
-    chem_mechanism* t = m->lane_twin;
-    if (t->params_version != m->params_version || t->params != m->params) {
-        t->params = m->params;
-        t->params_version = m->params_version;
-    }
-    *out = t;
-    return 0;
-}
 }  // namespace
 
 namespace chemmi {
@@ -170,10 +143,6 @@ int chem_load_mechanism(const char* path, chem_mechanism** out)
 void chem_free_mechanism(chem_mechanism* m)
 {
     if (!m) return;
-    if (m->lane_twin) {
-        release_device_state(m->lane_twin);
-        delete m->lane_twin;
-    }
     release_device_state(m);
     delete m;
 }
@@ -360,7 +329,6 @@ int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double
     Options o = resolve_options(opt);
     if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
-    if (int rc = lane_twin(m, &m)) return rc;
     const int ns = m->data.ns();
     double *Te = T_end, *Ye = Y_end;
     void* own = nullptr;

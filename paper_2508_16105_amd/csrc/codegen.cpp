@@ -496,7 +496,9 @@ WideLayout wide_layout(const MechanismData& m)
     w.l_p = w.l_q + nr;
     w.l_j = w.l_p + nr * w.pw;
     w.l_t0 = w.l_j + ns * w.jw;
-    w.lds_cell = w.l_t0 + ns;
+    w.l_w = w.l_t0 + ns;
+    w.lds_cell = w.l_w + n;
+    w.adj_lds_cell = 2 * w.lds_cell + 2 * n;
     return w;
 }
 
@@ -515,8 +517,10 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
       << "constexpr int MAXT = " << w.maxt << ";         // most terms on a reaction side\n"
       << "constexpr int NSLOT = " << w.nslot << ", PW = " << w.pw << ", JW = " << w.jw << ";\n"
       << "constexpr int L_Y = " << w.l_y << ", L_C = " << w.l_c << ", L_G = " << w.l_g << ", L_H = " << w.l_h
-      << ", L_Q = " << w.l_q << ", L_P = " << w.l_p << ", L_J = " << w.l_j << ", L_T0 = " << w.l_t0 << ";\n"
+      << ", L_Q = " << w.l_q << ", L_P = " << w.l_p << ", L_J = " << w.l_j << ", L_T0 = " << w.l_t0
+      << ", L_W = " << w.l_w << ";\n"
       << "constexpr int LDS_CELL = " << w.lds_cell << ";  // doubles of LDS scratch per cell\n"
+      << "constexpr int ADJ_LDS_CELL = " << w.adj_lds_cell << ";  // per cell in the adjoint\n"
       << "constexpr double RU = " << lit(kRu) << ";\n"
       << "constexpr double LN_PATM_R = " << lit(std::log(kPatm / kRu)) << ";\n"
       << "constexpr double LN10 = " << lit(std::log(10.0)) << ";\n";

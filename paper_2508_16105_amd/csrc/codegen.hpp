@@ -19,10 +19,13 @@ struct WideLayout {
     int nslot = 2;         // species partial slots per reaction (2 maxt)
     int pw = 4;            // doubles per reaction in the partials block
     int jw = 1;            // row stride of the concentration Jacobian (odd)
-    int l_y = 0, l_c = 0, l_g = 0, l_h = 0, l_q = 0, l_p = 0, l_j = 0, l_t0 = 0;
+    int l_y = 0, l_c = 0, l_g = 0, l_h = 0, l_q = 0, l_p = 0, l_j = 0, l_t0 = 0, l_w = 0;
     int lds_cell = 0;      // doubles per cell
+    int adj_lds_cell = 0;  // doubles per cell in the adjoint: the scratch for dual numbers,
+                           // then the pivot row and indices (untouched by source evaluations)
     int cells_per_wave() const { return 64 / G; }
     unsigned lds_bytes() const { return (unsigned)(cells_per_wave() * lds_cell * sizeof(double)); }
+    unsigned adj_lds_bytes() const { return (unsigned)(cells_per_wave() * adj_lds_cell * sizeof(double)); }
 };
 
 // The layout for m, or an empty optional-like result (G = 0) if m does not

@@ -643,32 +643,7 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
 
 }  // namespace chem
 
-struct AdjointArgs {
-    const double* par;
-    const double* T0;
-    const double* p;
-    const double* Y0;
-    long ncell;
-    const double* gT;
-    const double* gY;
-    double* gT0;
-    double* gY0;
-    double* gpar;          // [ncell][3 NR]: per-cell parameter gradients (ln A, b, Ea)
-    double* Tend;
-    double* Yend;
-    const long* off_h;     // first step size of each cell in hs
-    const long* off_ck;    // first checkpoint of each cell (in states of N doubles)
-    const int* nacc_fwd;   // accepted steps of the sizing pass
-    const int* order;      // cells by descending accepted steps (lane g takes cell order[g])
-    const double* h0;      // nullable: per-cell first step, else dt
-    double* hs;
-    double* ck;
-    int* status;
-    int* nacc;
-    int* nrej;
-    chem::StepArgs step;
-    int K;                 // accepted steps per checkpoint
-};
+
 
 extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
 {
@@ -735,29 +710,5 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
         g[j] = gA[j];
         g[mech::NR + j] = gb[j];
         g[2 * mech::NR + j] = gE[j];
-    }
-}
-
-// Parameter gradients summed over cells in a fixed order: one workgroup per
-// parameter; thread t adds cells t, t + 256, ... in turn, then a fixed tree.
-extern "C" __global__ void __launch_bounds__(256) chem_reduce_params(const double* __restrict__ gpar, long ncell,
-                                                                    int nparam, double* __restrict__ gA,
-                                                                    double* __restrict__ gb, double* __restrict__ gE)
-{
-    __shared__ double s[256];
-    const int q = blockIdx.x;
-    double v = 0.0;
-    for (long c = threadIdx.x; c < ncell; c += 256) v += gpar[c * nparam + q];
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const int nr = nparam / 3;
-        if (q < nr) gA[q] = s[0];
-        else if (q < 2 * nr) gb[q - nr] = s[0];
-        else gE[q - 2 * nr] = s[0];
     }
 }

@@ -110,6 +110,11 @@ __device__ __forceinline__ double gmax(double x)
     return greduce(x, [](double a, double b) { return fmax(a, b); });
 }
 
+__device__ __forceinline__ chem_math::Dual gsum(chem_math::Dual x)
+{
+    return chem_math::Dual(gsum(x.v), gsum(x.d));
+}
+
 // bits of this group's lanes in a wave-wide ballot, lane 0 of the group at bit 0
 __device__ __forceinline__ unsigned long long gbits(unsigned long long ballot)
 {
@@ -131,27 +136,43 @@ __device__ __forceinline__ void lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ double ipow(double c, int nu) { return nu == 1 ? c : (nu == 2 ? c * c : c * c * c); }
+template <class S>
+__device__ __forceinline__ S ipow(S c, int nu) { return nu == 1 ? c : (nu == 2 ? c * c : c * c * c); }
 
 // d(c^nu)/dc
-__device__ __forceinline__ double dipow(double c, int nu) { return nu == 1 ? 1.0 : (nu == 2 ? 2.0 * c : 3.0 * c * c); }
+template <class S>
+__device__ __forceinline__ S dipow(S c, int nu) { return nu == 1 ? S(1.0) : (nu == 2 ? 2.0 * c : 3.0 * c * c); }
 
-// Rate of progress of the reaction in slot j (and, with JAC, its partials:
-// d q / d C of each species slot, d q / dT at fixed C, and the coefficient of
-// the third-body efficiencies in d q / d C), written to the cell's LDS.
-template <bool JAC>
-__device__ __forceinline__ void reaction(int j, const double* __restrict__ par, double* __restrict__ L, double T,
-                                         double lnT, double iT, double lnPRT, double ctot)
+// add x to an LDS word (only the lane owning the address adds to it)
+__device__ __forceinline__ void lds_add(double* p, double x) { atomicAdd(p, x); }
+__device__ __forceinline__ void lds_add(chem_math::Dual* p, chem_math::Dual x)
 {
+    atomicAdd(&p->v, x.v);
+    atomicAdd(&p->d, x.d);
+}
+
+// Evaluation modes of the source terms: the rates; the rates and the
+// Jacobian row; the parameter products w . df/dtheta (adjoint).
+enum : int { F_ONLY = 0, F_JAC = 1, PARAM_VJP = 2 };
+
+// Rate of progress of the reaction in slot j, written to the cell's LDS; with
+// F_JAC also its partials (d q / d C of each species slot, d q / dT at fixed C,
+// and the coefficient of the third-body efficiencies in d q / d C); with
+// PARAM_VJP the products of w . df/dq_j with d q_j / d(ln A, b, Ea) added to g.
+template <class S, int MODE>
+__device__ __forceinline__ void reaction(int j, const double* __restrict__ par, S* __restrict__ L, S T, S lnT,
+                                         S iT, S lnPRT, S ctot, S irho, S rcpinv, S* __restrict__ g)
+{
+    constexpr bool JAC = MODE == F_JAC;
     const int kind = mech::RX_KIND[j];
     const int oj = mech::RX_ORIG[j];
     const double pb = par[NR + oj], pe = par[2 * NR + oj];
-    double lnk = lnT * pb;
+    S lnk = lnT * pb;
     lnk = fma(-iT, pe, lnk);
     lnk = lnk + par[oj];
     int sp[NSLOT], nu[NSLOT];
-    double c[NSLOT];
-    double lnKc = 0.0, dH = 0.0;
+    S c[NSLOT];
+    S lnKc = 0.0, dH = 0.0, ws = 0.0;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
         sp[s] = mech::RX_SP[j * NSLOT + s];
@@ -160,19 +181,20 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
         if (sp[s] >= 0) {
             const double sgn = s < mech::MAXT ? -(double)nu[s] : (double)nu[s];
             lnKc = fma(sgn, L[mech::L_G + sp[s]], lnKc);
-            if (JAC) dH = fma(sgn, L[mech::L_H + sp[s]], dH);
+            if (MODE != F_ONLY) dH = fma(sgn, L[mech::L_H + sp[s]], dH);
+            if (MODE == PARAM_VJP) ws = fma(sgn * mech::MWTAB[sp[s]], L[mech::L_W + 1 + sp[s]], ws);
             c[s] = L[mech::L_C + sp[s]];
         }
     }
     const int dnu = mech::RX_DNU[j];
     lnKc = fma((double)dnu, lnPRT, lnKc);
     const int er = mech::RX_EFFROW[j];
-    double Mc = ctot;
+    S Mc = ctot;
     if (er >= 0) {
         for (int m = 0; m < NS; ++m) Mc = fma(mech::EFF[er * NS + m] - 1.0, L[mech::L_C + m], Mc);
     }
-    double kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0;
-    double dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;
+    S kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0, Pr = 0.0;
+    S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;
     if (kind < 2) {
         kf = chem_math::exp_tang(lnk);
         kr = chem_math::exp_tang(lnk - lnKc);
@@ -180,34 +202,34 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
         // P_r = k0 [M] / k_inf, one exponential for the ratio
         const double* lo = &mech::RX_LOW[j * 3];
         kinf = chem_math::exp_tang(lnk);
-        const double lnr0 = lo[0] + lo[1] * lnT - lo[2] * iT - lnk;
+        const S lnr0 = lo[0] + lo[1] * lnT - lo[2] * iT - lnk;
         r0 = chem_math::exp_tang(lnr0);
-        const double Pr = r0 * Mc;
+        Pr = r0 * Mc;
         const bool floored = !(Pr >= 1e-300);
-        const double logPr = floored ? -300.0 : log10(Pr);
+        const S logPr = floored ? S(-300.0) : log10(Pr);
         if (kind == 3) {
             const double* tr = &mech::RX_TROE[j * 8];
-            const double e3 = exp(-T * tr[2]);
-            const double e1 = exp(-T * tr[3]);
-            double Fc = tr[0] * e3 + tr[1] * e1;
-            double dFc = tr[5] * e3 + tr[6] * e1;
+            const S e3 = exp(-T * tr[2]);
+            const S e1 = exp(-T * tr[3]);
+            S Fc = tr[0] * e3 + tr[1] * e1;
+            S dFc = tr[5] * e3 + tr[6] * e1;
             if (tr[7] != 0.0) {
-                const double e2 = exp(-tr[4] * iT);
+                const S e2 = exp(-tr[4] * iT);
                 Fc += e2;
                 dFc += tr[4] * iT * iT * e2;
             }
-            const double logFc = log10(Fc);
-            const double tc = -0.4 - 0.67 * logFc;
-            const double tn = 0.75 - 1.27 * logFc;
-            const double tu = logPr + tc;
-            const double tden = tn - 0.14 * tu;
-            const double tx = tu / tden;
-            const double opx2 = 1.0 + tx * tx;
-            const double logF = logFc / opx2;
+            const S logFc = log10(Fc);
+            const S tc = -0.4 - 0.67 * logFc;
+            const S tn = 0.75 - 1.27 * logFc;
+            const S tu = logPr + tc;
+            const S tden = tn - 0.14 * tu;
+            const S tx = tu / tden;
+            const S opx2 = 1.0 + tx * tx;
+            const S logF = logFc / opx2;
             Fb = exp(mech::LN10 * logF);
-            if (JAC) {
-                const double tg = -logFc * 2.0 * tx / (opx2 * opx2);
-                dF_dPr = floored ? 0.0 : tg * tn / (tden * tden);
+            if (MODE != F_ONLY) {
+                const S tg = -logFc * 2.0 * tx / (opx2 * opx2);
+                dF_dPr = floored ? S(0.0) : tg * tn / (tden * tden);
                 dF_dFc = 1.0 / opx2 + tg * (-0.67 * tn + 1.27 * tu) / (tden * tden);
                 dlogFc_dT = dFc / (Fc * mech::LN10);
             }
@@ -217,7 +239,7 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
         iKc = chem_math::exp_tang(-lnKc);
         kr = kf * iKc;
     }
-    double pf = 1.0, pr = 1.0;
+    S pf = 1.0, pr = 1.0;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
         if (sp[s] >= 0) {
@@ -225,20 +247,33 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
             else pr *= ipow(c[s], nu[s]);
         }
     }
-    const double fwd = kf * pf, rev = kr * pr;
-    L[mech::L_Q + j] = kind == 1 ? Mc * (fwd - rev) : fwd - rev;
+    const S fwd = kf * pf, rev = kr * pr;
+    const S q = kind == 1 ? Mc * (fwd - rev) : fwd - rev;
+    if (MODE == PARAM_VJP) {
+        // w . df/dq_j: species rows W_k nu_kj / rho, temperature row
+        // -R T (sum nu H/RT) / (rho c_p); d q / d ln A of the main rate (k_inf
+        // for falloff, through P_r = k0 [M] / k_inf)
+        const S wsum = ws * irho - L[mech::L_W] * (mech::RU * T) * dH * rcpinv;
+        const S qA = kind >= 2 ? q * (Pr * ipr1 - dF_dPr) : q;
+        const S gq = wsum * qA;
+        g[0] += gq;
+        g[1] += gq * lnT;
+        g[2] += gq * (-iT * (1.0 / mech::RU));
+        return;
+    }
+    L[mech::L_Q + j] = q;
     if (!JAC) return;
-    double* P = L + mech::L_P + j * PW;
-    const double fac = kind == 1 ? Mc : 1.0;
-    const double dlnKc = (dH - (double)dnu) * iT;
-    const double dlnkinf = (pb + pe * iT) * iT;
-    double dlnkf = dlnkinf;
-    double dM = kind == 1 ? fwd - rev : 0.0;
+    S* P = L + mech::L_P + j * PW;
+    const S fac = kind == 1 ? Mc : S(1.0);
+    const S dlnKc = (dH - (double)dnu) * iT;
+    const S dlnkinf = (pb + pe * iT) * iT;
+    S dlnkf = dlnkinf;
+    S dM = kind == 1 ? fwd - rev : S(0.0);
     if (kind >= 2) {
         const double* lo = &mech::RX_LOW[j * 3];
-        const double dlnk0 = (lo[1] + lo[2] * iT) * iT;
+        const S dlnk0 = (lo[1] + lo[2] * iT) * iT;
         dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + mech::LN10 * dF_dFc * dlogFc_dT;
-        const double dkdM = kinf * r0 * Fb * (ipr1 * ipr1 + dF_dPr * ipr1);
+        const S dkdM = kinf * r0 * Fb * (ipr1 * ipr1 + dF_dPr * ipr1);
         dM = dkdM * (pf - iKc * pr);
     }
     P[NSLOT] = fac * (dlnkf * fwd - (dlnkf - dlnKc) * rev);
@@ -246,7 +281,7 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
         // derivative of this side's product with respect to the slot's species
-        double d = 0.0;
+        S d = 0.0;
         if (sp[s] >= 0) {
             const int lo = s < mech::MAXT ? 0 : mech::MAXT;
             d = dipow(c[s], nu[s]);
@@ -260,12 +295,15 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
 }
 
 // Source terms f = dy/dt of the group's cell at the state whose component i
-// is yi (lane i), and with JAC row i of the Jacobian in A.  Every lane of the
-// group calls it together.
-template <bool JAC>
-__device__ __forceinline__ double rhs(const double* __restrict__ par, double p, double ip, double yi,
-                                      double* __restrict__ L, double (&A)[N])
+// is yi (lane i); with F_JAC row i of the Jacobian in A; with PARAM_VJP
+// (weights w, component wi in lane i) the products w . df/dtheta of the
+// lane's reaction slots r G + i added to g[r].  Every lane of the group calls
+// it together.  S is double, or a dual number for directional derivatives.
+template <class S, int MODE>
+__device__ __forceinline__ S rhs(const double* __restrict__ par, double p, double ip, S yi, S* __restrict__ L,
+                                 S (&A)[N], S wi, S (&g)[ROUNDS][3])
 {
+    constexpr bool JAC = MODE == F_JAC;
     const int i = gl();
     const bool sp = i >= 1 && i <= NS;
     const int k = sp ? i - 1 : 0;
@@ -273,16 +311,19 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     // evaluation instead of being hoisted out of the substep loop into SGPRs
     const int z = mech::opaque_zero();
     mech::cdbl* MW = (mech::cdbl*)&mech::MWTAB[0] + z;
-    if (i < N) L[mech::L_Y + i] = yi;
+    if (i < N) {
+        L[mech::L_Y + i] = yi;
+        if (MODE == PARAM_VJP) L[mech::L_W + i] = wi;
+    }
     lds_sync();
-    const double T = L[mech::L_Y];
-    const double lnT = log(T);
-    const double iT = 1.0 / T;
-    const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;
-    double cpR = 0.0, HRT = 0.0, Gk = 0.0, dcpR = 0.0;
+    const S T = L[mech::L_Y];
+    const S lnT = log(T);
+    const S iT = 1.0 / T;
+    const S T2 = T * T, T3 = T2 * T, T4 = T2 * T2;
+    S cpR = 0.0, HRT = 0.0, Gk = 0.0, dcpR = 0.0;
     if (sp) {
         const double* c = &mech::THERMO[k][T < mech::TMID[k] ? 0 : 1][0];
-        double a = T4 * c[4];
+        S a = T4 * c[4];
         a = fma(T3, c[3], a);
         a = fma(T2, c[2], a);
         a = fma(T, c[1], a);
@@ -309,32 +350,42 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     }
     const double W = sp ? MW[k] : 0.0;
     const double iW = sp ? MW[NS + k] : 0.0;
-    const double yw = sp ? yi * iW : 0.0;
-    const double sig = gsum(yw);
-    const double Wbar = 1.0 / sig;
-    const double rho = p * Wbar * iT * (1.0 / mech::RU);
-    const double irho = mech::RU * T * sig * ip;
-    const double ctot = p * iT * (1.0 / mech::RU);
+    const S yw = sp ? yi * iW : S(0.0);
+    const S sig = gsum(yw);
+    const S Wbar = 1.0 / sig;
+    const S rho = p * Wbar * iT * (1.0 / mech::RU);
+    const S irho = mech::RU * T * sig * ip;
+    const S ctot = p * iT * (1.0 / mech::RU);
     if (sp) {
         L[mech::L_C + k] = rho * yw;
         L[mech::L_G + k] = Gk;
         L[mech::L_H + k] = HRT;
     }
     lds_sync();
-    const double lnPRT = mech::LN_PATM_R - lnT;
+    const S lnPRT = mech::LN_PATM_R - lnT;
+    if (MODE == PARAM_VJP) {
+        const S rcp = T * sig * ip / gsum(cpR * yw);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int j = r * G + i;
+            if (j < NR) reaction<S, MODE>(j, par, L, T, lnT, iT, lnPRT, ctot, irho, rcp, g[r]);
+        }
+        return S(0.0);
+    }
 #pragma unroll 1
     for (int r = 0; r < ROUNDS; ++r) {
         const int j = r * G + i;
-        if (j < NR) reaction<JAC>(j, par, L, T, lnT, iT, lnPRT, ctot);
+        if (j < NR) reaction<S, MODE>(j, par, L, T, lnT, iT, lnPRT, ctot, irho, irho, g[0]);
     }
     lds_sync();
     // species lists come padded to multiples of 4: four entries' loads in flight
-    const double* __restrict__ Q = L + mech::L_Q;
-    double wdot = 0.0;
+    const S* __restrict__ Q = L + mech::L_Q;
+    S wdot = 0.0;
     if (sp) {
         const int e1 = mech::SP_OFF[k + 1];
         for (int e = mech::SP_OFF[k]; e < e1; e += 4) {
-            double q[4], nu[4];
+            S q[4];
+            double nu[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 nu[u] = (double)mech::SP_NU[e + u];
@@ -344,13 +395,13 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
             for (int u = 0; u < 4; ++u) wdot = nu[u] != 0.0 ? fma(nu[u], q[u], wdot) : wdot;
         }
     }
-    const double cpm = gsum(cpR * yw);
-    const double hw = gsum(HRT * wdot);
-    const double icpm = 1.0 / cpm;
-    const double rcpinv = T * sig * ip * icpm;
-    const double fT = -mech::RU * T * hw * rcpinv;
-    const double fk = W * (irho * wdot);
-    const double fi = sp ? fk : (i == 0 ? fT : 0.0);
+    const S cpm = gsum(cpR * yw);
+    const S hw = gsum(HRT * wdot);
+    const S icpm = 1.0 / cpm;
+    const S rcpinv = T * sig * ip * icpm;
+    const S fT = -mech::RU * T * hw * rcpinv;
+    const S fk = W * (irho * wdot);
+    const S fi = sp ? fk : (i == 0 ? fT : S(0.0));
     if (!JAC) return fi;
 
     // Row k of the concentration Jacobian: Jc_km = d wdot_k / d C_m (fixed T)
@@ -358,18 +409,19 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     // of the lane's reactions go into its own LDS row by atomic adds (one
     // lane per address, applied in program order: reproducible); the
     // third-body part, dense over m, accumulates in registers.
-    double* Jr = L + mech::L_J + k * JW;
+    S* Jr = L + mech::L_J + k * JW;
     if (sp) {
 #pragma unroll
         for (int m = 0; m <= NS; ++m) Jr[m] = 0.0;
     }
     lds_sync();
     if (sp) {
-        const double* __restrict__ Pb = L + mech::L_P;
+        const S* __restrict__ Pb = L + mech::L_P;
         const int e1 = mech::SP_OFF[k + 1];
         for (int e = mech::SP_OFF[k]; e < e1; e += 4) {
             int j[4], ms[4][NSLOT];
-            double nu[4], P[4][NSLOT + 1];
+            double nu[4];
+            S P[4][NSLOT + 1];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 j[u] = mech::SP_RX[e + u];
@@ -384,12 +436,12 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
                 if (nu[u] == 0.0) continue;
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s)
-                    if (ms[u][s] >= 0) atomicAdd(&Jr[ms[u][s]], nu[u] * P[u][s]);
-                atomicAdd(&Jr[NS], nu[u] * P[u][NSLOT]);
+                    if (ms[u][s] >= 0) lds_add(&Jr[ms[u][s]], nu[u] * P[u][s]);
+                lds_add(&Jr[NS], nu[u] * P[u][NSLOT]);
             }
         }
     }
-    double R[NS + 1];
+    S R[NS + 1];
 #pragma unroll
     for (int m = 0; m <= NS; ++m) R[m] = 0.0;
     // the efficiencies by scalar loads at an opaque offset, so they are loaded
@@ -397,8 +449,7 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     mech::cdbl* EF = (mech::cdbl*)&mech::EFF[0] + z;
 #pragma unroll 1
     for (int t = 0; t < mech::NTB; ++t) {
-        const double d = (sp ? mech::NU_TB[k * mech::NTB + t] : 0.0) *
-                         L[mech::L_P + mech::TB_SLOT[t] * PW + NSLOT + 1];
+        const S d = (sp ? mech::NU_TB[k * mech::NTB + t] : 0.0) * L[mech::L_P + mech::TB_SLOT[t] * PW + NSLOT + 1];
         mech::cdbl* eff = EF + t * NS;
 #pragma unroll
         for (int m = 0; m < NS; ++m) R[m] = fma(eff[m], d, R[m]);
@@ -418,30 +469,30 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
     //   J_00 = -R (cpw + T HwT - HS) / (rho cp) - f_T (dcp / cp - 1/T)
     // HJ_m = sum_k H_k/RT Jc_km, HS = sum_k H_k/RT S_k, HwT = sum_k H_k/RT wT_k,
     // cpw = sum_k cp_k/R wdot_k
-    double Sk = 0.0, wT = 0.0;
+    S Sk = 0.0, wT = 0.0;
     if (sp) {
 #pragma unroll
         for (int m = 0; m < NS; ++m) Sk = fma(R[m], L[mech::L_C + m], Sk);
         wT = R[NS];
     }
-    const double HS = gsum(HRT * Sk);
-    const double HwT = gsum(HRT * wT);
-    const double cpw = gsum(cpR * wdot);
-    const double dcpm = gsum(dcpR * yw);
-    const double RT = mech::RU * T;
-    const double icp = icpm * (1.0 / mech::RU);
-    const double dcp = mech::RU * dcpm;
+    const S HS = gsum(HRT * Sk);
+    const S HwT = gsum(HRT * wT);
+    const S cpw = gsum(cpR * wdot);
+    const S dcpm = gsum(dcpR * yw);
+    const S RT = mech::RU * T;
+    const S icp = icpm * (1.0 / mech::RU);
+    const S dcp = mech::RU * dcpm;
     if (sp) {
-        double HJ = 0.0;
+        S HJ = 0.0;
         for (int l = 0; l < NS; ++l) HJ = fma(L[mech::L_H + l], L[mech::L_J + l * JW + k], HJ);
-        const double t = fma(rho, HJ, -Wbar * HS) * (-RT * rcpinv);
-        const double u = fma(cpR, icp * mech::RU, -Wbar);
+        const S t = fma(rho, HJ, -Wbar * HS) * (-RT * rcpinv);
+        const S u = fma(cpR, icp * mech::RU, -Wbar);
         L[mech::L_T0 + k] = fma(-fT, u, t) * iW;
     }
     lds_sync();
     if (sp) {
-        const double g = fma(-W, Sk * irho, fk);
-        const double wg = Wbar * g;
+        const S gk = fma(-W, Sk * irho, fk);
+        const S wg = Wbar * gk;
 #pragma unroll
         for (int m = 0; m < NS; ++m) A[1 + m] = fma(R[m], W, wg) * MW[NS + m];
         A[0] = fma(W * irho, wT - Sk * iT, fk * iT);
@@ -458,14 +509,15 @@ __device__ __forceinline__ double rhs(const double* __restrict__ par, double p, 
 
 // LU with partial pivoting of the group's matrix (row i in lane i), in place:
 // multipliers below the diagonal, U above, reciprocal pivots on the diagonal.
-// piv[k] (in the cell's LDS scratch, after the pivot row): row swapped into k
-// at step k (LINPACK order, the lowest row index among equal magnitudes); bit
-// k of the result: some group of the wave swapped.
-__device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, double* __restrict__ L)
+// PV: LDS scratch of the cell for the pivot row (N doubles) and, after it, the
+// pivot indices: piv[k] is the row swapped into k at step k (LINPACK order,
+// the lowest row index among equal magnitudes).  Bit k of the result: some
+// group of the wave swapped at step k.
+__device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, double* __restrict__ PV)
 {
     const int i = gl_local();
-    double* PR = L + mech::L_J;     // pivot row (the Jacobian rows are consumed by now)
-    int* piv = (int*)(PR + N);      // pivot indices, read by the solves only on a swap
+    double* PR = PV;
+    int* piv = (int*)(PV + N);      // read by the solves only on a swap
     unsigned long long swaps = 0ull;
     ok = true;
 #pragma unroll
@@ -509,11 +561,11 @@ __device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, doubl
 }
 
 // Solve (LU) x = b for the group's vector b (component i in lane i).
-__device__ __forceinline__ double solve(const double (&A)[N], const double* __restrict__ L,
+__device__ __forceinline__ double solve(const double (&A)[N], const double* __restrict__ PV,
                                         unsigned long long swaps, double b)
 {
     const int i = gl_local();
-    const int* piv = (const int*)(L + mech::L_J + N);
+    const int* piv = (const int*)(PV + N);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         if (swaps & (1ull << k)) {
@@ -533,22 +585,24 @@ __device__ __forceinline__ double solve(const double (&A)[N], const double* __re
 }
 
 // One RODAS4 step from y (component yi) with step h; false if the step
-// matrix is singular or a result is not finite.
+// matrix is singular or a result is not finite.  L: the cell's scratch, PV:
+// its pivot scratch.
 __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip, double yi, double h,
-                                         double rtol, double atol, double* __restrict__ L, double& ynew,
-                                         double& errn)
+                                         double rtol, double atol, double* __restrict__ L, double* __restrict__ PV,
+                                         double& ynew, double& errn)
 {
     const int i = gl_local();
     double A[N];
-    const double f0 = rhs<true>(par, p, ip, yi, L, A);
+    double g[ROUNDS][3];
+    const double f0 = rhs<double, F_JAC>(par, p, ip, yi, L, A, 0.0, g);
     const double ghinv = 1.0 / (h * Rodas4::gamma);
     const double hinv = 1.0 / h;
 #pragma unroll
     for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - A[j];
     bool ok;
-    const unsigned long long swaps = lu(A, ok, L);
+    const unsigned long long swaps = lu(A, ok, PV);
     double u[Rodas4::S];
-    u[0] = solve(A, L, swaps, f0);
+    u[0] = solve(A, PV, swaps, f0);
 #pragma unroll
     for (int s = 1; s < Rodas4::S; ++s) u[s] = 0.0;
     double dummy[N];
@@ -565,8 +619,8 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
             }
         }
         if (s == Rodas4::S - 1) ynew = Ys;
-        const double fs = rhs<false>(par, p, ip, Ys, L, dummy);
-        const double us = solve(A, L, swaps, fma(acc, hinv, fs));
+        const double fs = rhs<double, F_ONLY>(par, p, ip, Ys, L, dummy, 0.0, g);
+        const double us = solve(A, PV, swaps, fma(acc, hinv, fs));
 #pragma unroll
         for (int j = 1; j < Rodas4::S; ++j)
             if (j == s) u[j] = us;
@@ -602,20 +656,21 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
     c.done = bad;
 }
 
-// One attempted substep with the controller of the one-cell-per-lane form.
-__device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
-                                             double* __restrict__ L)
+// One attempted substep with the controller of the one-cell-per-lane form;
+// returns the step size if the step was accepted, else 0.
+__device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
+                                               double* __restrict__ L, double* __restrict__ PV)
 {
-    if (c.done) return;
+    if (c.done) return 0.0;
     if (c.nacc + c.nrej >= a.max_substeps) {
         c.status = chem::CELL_MAXSTEPS;
         c.done = true;
-        return;
+        return 0.0;
     }
     if (c.h < a.hmin) {
         c.status = chem::CELL_HMIN;
         c.done = true;
-        return;
+        return 0.0;
     }
     bool last = false;
     double h = c.h;
@@ -624,7 +679,7 @@ __device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__
         last = true;
     }
     double ynew, en;
-    const bool ok = ros_step(par, c.p, c.ip, c.y, h, a.rtol, a.atol, L, ynew, en);
+    const bool ok = ros_step(par, c.p, c.ip, c.y, h, a.rtol, a.atol, L, PV, ynew, en);
     if (ok && en <= 1.0) {
         c.y = ynew;
         c.t = last ? a.dt : c.t + h;
@@ -635,11 +690,12 @@ __device__ __forceinline__ void cell_attempt(Cell& c, const double* __restrict__
         c.rej_last = false;
         ++c.nacc;
         if (last) c.done = true;
-        return;
+        return h;
     }
     ++c.nrej;
     c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
     c.rej_last = true;
+    return 0.0;
 }
 
 __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T, double* __restrict__ Y, long cell,
@@ -657,6 +713,165 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
     }
 }
 
+// ---- discrete adjoint of the frozen-step map (see the one-cell-per-lane form
+// for the algebra); every vector one component per lane ----
+
+// Solve M^T x = b with the factors of lu(): U^T y = b forward, then, for
+// k = N-1 .. 0, y_k -= sum_{i>k} l_ik y_i and swap y_k, y_piv[k].  The row
+// sums a column needs are group sums.
+__device__ __forceinline__ double solve_t(const double (&A)[N], const double* __restrict__ PV,
+                                          unsigned long long swaps, double b)
+{
+    const int i = gl_local();
+    const int* piv = (const int*)(PV + N);
+    double y = b;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double s = gsum(i < k ? A[k] * y : 0.0);
+        if (i == k) y = (y - s) * A[k];
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        const double s = gsum(i > k && i < N ? A[k] * y : 0.0);
+        if (i == k) y -= s;
+        if (swaps & (1ull << k)) {
+            const int pk = piv[k];
+            y = gather(y, (i == k) ? pk : (i == pk ? k : i));
+        }
+    }
+    return y;
+}
+
+// Component i of J^T w for the group's rows of J (row i in lane i).
+__device__ __forceinline__ double colsum(const double (&J)[N], double w)
+{
+    const int i = gl_local();
+    double out = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double s = gsum(J[k] * w);
+        out = (i == k) ? s : out;
+    }
+    return out;
+}
+
+// Component i of D_u[J^T w] from dual rows of J (tangent along u).
+__device__ __forceinline__ double colsum_tangent(const chem_math::Dual (&J)[N], double w)
+{
+    const int i = gl_local();
+    double out = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double s = gsum(J[k].d * w);
+        out = (i == k) ? s : out;
+    }
+    return out;
+}
+
+// value of a stage-indexed register array at a run-time stage s (selects, so
+// the array stays in registers)
+__device__ __forceinline__ double pick(const double (&v)[Rodas4::S], int s)
+{
+    double r = v[0];
+#pragma unroll
+    for (int q = 1; q < Rodas4::S; ++q) r = (q == s) ? v[q] : r;
+    return r;
+}
+
+__device__ __forceinline__ void place(double (&v)[Rodas4::S], int s, double x)
+{
+#pragma unroll
+    for (int q = 0; q < Rodas4::S; ++q) v[q] = (q == s) ? x : v[q];
+}
+
+// The adjoint of one frozen RODAS4 step from y (component yi) with step h:
+// lam (the cotangent of y_new, component in lane i) becomes the cotangent of
+// y; the parameter products of the lane's reaction slots are added to g.
+// L: the cell's scratch (room for dual numbers), PV: its pivot scratch.  The
+// stage loops stay rolled (one copy of each source-term evaluation).
+__device__ __noinline__ void step_adjoint(const double* __restrict__ par, double p, double ip, double yi, double h,
+                                          double& lam, double (&g)[ROUNDS][3], double* __restrict__ L,
+                                          double* __restrict__ PV)
+{
+    using chem_math::Dual;
+    const int i = gl_local();
+    double J0[N], A[N], dummy[N];
+    const double f0 = rhs<double, F_JAC>(par, p, ip, yi, L, J0, 0.0, g);
+    const double ghinv = 1.0 / (h * Rodas4::gamma);
+    const double hinv = 1.0 / h;
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - J0[j];
+    bool ok;
+    const unsigned long long swaps = lu(A, ok, PV);
+    double u[Rodas4::S], Ys[Rodas4::S];
+#pragma unroll
+    for (int s = 0; s < Rodas4::S; ++s) u[s] = Ys[s] = 0.0;
+    Ys[0] = yi;
+    u[0] = solve(A, PV, swaps, f0);
+#pragma unroll 1
+    for (int s = 1; s < Rodas4::S; ++s) {
+        double Y = yi, acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < Rodas4::S - 1; ++j) {
+            if (j < s) {
+                Y = fma(RA[s][j], u[j], Y);
+                acc = fma(RC[s][j], u[j], acc);
+            }
+        }
+        place(Ys, s, Y);
+        const double fs = rhs<double, F_ONLY>(par, p, ip, Y, L, dummy, 0.0, g);
+        place(u, s, solve(A, PV, swaps, fma(acc, hinv, fs)));
+    }
+    // reverse over the stages
+    const double mw[Rodas4::S] = {RA[5][0], RA[5][1], RA[5][2], RA[5][3], 1.0, 1.0};
+    double ub[Rodas4::S], w[Rodas4::S];
+    double yb = lam;
+#pragma unroll
+    for (int s = 0; s < Rodas4::S; ++s) {
+        ub[s] = mw[s] * lam;
+        w[s] = 0.0;
+    }
+#pragma unroll 1
+    for (int s = Rodas4::S - 1; s >= 0; --s) {
+        const double ws = solve_t(A, PV, swaps, pick(ub, s));
+        place(w, s, ws);
+        const double Yss = pick(Ys, s);
+        double Js[N];
+        if (s == 0) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) Js[j] = J0[j];
+        } else {
+            rhs<double, F_JAC>(par, p, ip, Yss, L, Js, 0.0, g);
+        }
+        const double Yb = colsum(Js, ws);
+        yb += Yb;
+        rhs<double, PARAM_VJP>(par, p, ip, Yss, L, dummy, ws, g);
+#pragma unroll
+        for (int j = 0; j < Rodas4::S - 1; ++j)
+            if (j < s) ub[j] = fma(RA[s][j], Yb, fma(RC[s][j] * hinv, ws, ub[j]));
+    }
+    // second-order terms at y: J(y) inside M, one dual evaluation per stage direction
+    Dual* Ld = (Dual*)L;
+#pragma unroll 1
+    for (int s = 0; s < Rodas4::S; ++s) {
+        const double us = pick(u, s), ws = pick(w, s);
+        Dual Jd[N];
+        Dual gd[ROUNDS][3];
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) gd[r][0] = gd[r][1] = gd[r][2] = 0.0;
+        rhs<Dual, F_JAC>(par, p, ip, Dual(yi, us), Ld, Jd, Dual(0.0), gd);
+        yb += colsum_tangent(Jd, ws);
+        rhs<Dual, PARAM_VJP>(par, p, ip, Dual(yi, us), Ld, Jd, Dual(ws), gd);
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            g[r][0] += gd[r][0].d;
+            g[r][1] += gd[r][1].d;
+            g[r][2] += gd[r][2].d;
+        }
+    }
+    lam = yb;
+}
+
 }  // namespace chemw
 
 // ---- plain form: one group of G lanes per cell, cells in index order ----
@@ -671,7 +886,7 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_plain(chem::IntegrateAr
     double* L = lds + grp * mech::LDS_CELL;
     Cell c;
     cell_begin(c, a.T[cell], a.p[cell], a.Y + cell * NS, a.h0 ? a.h0[cell] : a.step.dt);
-    while (!c.done) cell_attempt(c, a.par, a.step, L);
+    while (!c.done) cell_attempt(c, a.par, a.step, L, L + mech::L_J);
     cell_store(c, a.T, a.Y, cell, a.status, a.nacc, a.nrej);
 }
 
@@ -689,15 +904,16 @@ extern "C" __global__ void __launch_bounds__(64) chem_eval(EvalArgs a)
     const double p = a.p[cell];
     const double yi = i == 0 ? a.T[cell] : (i <= NS ? a.Y[cell * NS + i - 1] : 0.0);
     double A[N];
+    double g[ROUNDS][3];
     double f;
     if (a.J) {
-        f = rhs<true>(a.par, p, 1.0 / p, yi, L, A);
+        f = rhs<double, F_JAC>(a.par, p, 1.0 / p, yi, L, A, 0.0, g);
         if (i < N) {
 #pragma unroll
             for (int j = 0; j < N; ++j) a.J[(cell * N + i) * N + j] = A[j];
         }
     } else {
-        f = rhs<false>(a.par, p, 1.0 / p, yi, L, A);
+        f = rhs<double, F_ONLY>(a.par, p, 1.0 / p, yi, L, A, 0.0, g);
     }
     if (i < N) a.f[cell * N + i] = f;
 }
@@ -740,12 +956,103 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_persistent(const Persis
         }
         if (__all(exhausted)) break;
         if (have) {
-            cell_attempt(c, par, step, L);
+            cell_attempt(c, par, step, L, L + mech::L_J);
             if (c.done) {
                 const FieldDesc& fd = blk->fields[f];
                 cell_store(c, fd.T, fd.Y, local, fd.status, fd.nacc, fd.nrej);
                 have = false;
             }
+        }
+    }
+}
+
+// ---- discrete adjoint: one group per cell, cells in descending cost order ----
+// The forward solve is rerun, storing every accepted step size and the state
+// every K accepted steps; then the reverse sweep recomputes each segment from
+// its checkpoint and applies the step adjoints backwards.  Per-cell parameter
+// gradients go to gpar for the fixed-order reduction.
+extern "C" __global__ void __launch_bounds__(64) chem_adjoint(AdjointArgs a)
+{
+    using namespace chemw;
+    chem_math::exp_table_init(mech::EXP2_J64);
+    extern __shared__ double lds[];
+    const int grp = (int)threadIdx.x / G;
+    const long slot = (long)blockIdx.x * CPW + grp;
+    if (slot >= a.ncell) return;
+    const long cell = a.order[slot];
+    double* L = lds + grp * mech::ADJ_LDS_CELL;
+    double* PV = L + 2 * mech::LDS_CELL;
+    const int i = gl();
+    Cell c;
+    cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, a.h0 ? a.h0[cell] : a.step.dt);
+    double* hs = a.hs + a.off_h[cell];
+    double* ck = a.ck + a.off_ck[cell] * N;
+    const int cap = a.nacc_fwd[cell];
+    int stored = -1;
+    while (!c.done) {
+        if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
+            if (i < N) ck[(c.nacc / a.K) * N + i] = c.y;
+            stored = c.nacc;
+        }
+        const double hacc = cell_attempt(c, a.par, a.step, L, PV);
+        if (hacc > 0.0) {
+            if (c.nacc > cap) {
+                c.status = chem::CELL_NONFINITE;
+                c.done = true;
+                break;
+            }
+            if (i == 0) hs[c.nacc - 1] = hacc;
+        }
+    }
+    cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
+    if (c.status == chem::CELL_BADINPUT) {
+        if (i == 0) a.Tend[cell] = a.T0[cell];
+        else if (i <= NS) a.Yend[cell * NS + i - 1] = a.Y0[cell * NS + i - 1];
+    }
+    double* gp = a.gpar + cell * 3 * NR;
+    if (c.status != chem::CELL_OK) {
+        if (i == 0) a.gT0[cell] = __builtin_nan("");
+        else if (i <= NS) a.gY0[cell * NS + i - 1] = __builtin_nan("");
+        for (int j = i; j < 3 * NR; j += G) gp[j] = 0.0;
+        return;
+    }
+    double lam = i == 0 ? a.gT[cell] : (i <= NS ? a.gY[cell * NS + i - 1] : 0.0);
+    double g[ROUNDS][3];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) g[r][0] = g[r][1] = g[r][2] = 0.0;
+    const int na = c.nacc;
+    const double p = c.p, ip = c.ip;
+    for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
+        const int first = seg * a.K;
+        const int last = min(na, first + a.K) - 1;
+        double ys[16];                        // the segment's states (K <= 16), component i
+        ys[0] = i < N ? ck[seg * N + i] : 0.0;
+        for (int s = first; s < last; ++s) {
+            double yn, en;
+            double yc = ys[0];
+#pragma unroll
+            for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
+            ros_step(a.par, p, ip, yc, hs[s], a.step.rtol, a.step.atol, L, PV, yn, en);
+#pragma unroll
+            for (int q = 1; q < 16; ++q) ys[q] = (q == s - first + 1) ? yn : ys[q];
+        }
+        for (int s = last; s >= first; --s) {
+            double yc = ys[0];
+#pragma unroll
+            for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
+            step_adjoint(a.par, p, ip, yc, hs[s], lam, g, L, PV);
+        }
+    }
+    if (i == 0) a.gT0[cell] = lam;
+    else if (i <= NS) a.gY0[cell * NS + i - 1] = lam;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int j = r * G + i;
+        if (j < NR) {
+            const int oj = mech::RX_ORIG[j];
+            gp[oj] = g[r][0];
+            gp[NR + oj] = g[r][1];
+            gp[2 * NR + oj] = g[r][2];
         }
     }
 }

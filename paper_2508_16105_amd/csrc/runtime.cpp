@@ -85,14 +85,14 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_reduce_stats", &d.f_stats);
         rc = rc ? rc : load_function(d.module, "chem_persistent", &d.f_persistent);
         rc = rc ? rc : load_function(d.module, "chem_reset_heads", &d.f_reset);
+        rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
+        rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
         if (!m->wide) {   // one-cell-per-lane module only
             rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
             rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
             rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
             rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
             rc = rc ? rc : load_function(d.module, "chem_order_scatter", &d.f_oscatter);
-            rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
-            rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
         }
         if (rc) return rc;
         HIPCHECK(hipMalloc((void**)&d.par, sizeof(double) * std::max<size_t>(m->params.size(), 1)), "hipMalloc par");
@@ -545,8 +545,9 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     const StepArgs step = step_args(dt, rtol, atol, o);
     if (o.h0) {
         IntegrateArgs ia{d->par, Tw, p, Yw, (long)ncell, o.h0, st, na_fwd, nj, step};
-        if (int rc = launch_1d(d->f_plain, ncell, 64, &ia, sizeof ia, stream, "chem_plain", d->stage_lds(64)))
-            return rc;
+        const int64_t lanes = m->wide ? ncell * m->layout.G : ncell;
+        const unsigned shmem = m->wide ? m->layout.lds_bytes() : d->stage_lds(64);
+        if (int rc = launch_1d(d->f_plain, lanes, 64, &ia, sizeof ia, stream, "chem_plain", shmem)) return rc;
     } else {   // the persistent form takes the same steps, bitwise, sooner
         FieldView fv{Tw, p, Yw, ncell, st, na_fwd, nj, nullptr, nullptr};
         Options po = o;
@@ -591,8 +592,10 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, T_end, Y_end, off_d,
                    off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
-    if (int rc = launch_1d(d->f_adjoint, ncell, 64, &aa, sizeof aa, stream, "chem_adjoint", d->stage_lds(64)))
-        return rc;
+    // one lane per cell, or one group of G lanes per cell (with room for dual numbers)
+    const int64_t alanes = m->wide ? ncell * m->layout.G : ncell;
+    const unsigned ashmem = m->wide ? m->layout.adj_lds_bytes() : d->stage_lds(64);
+    if (int rc = launch_1d(d->f_adjoint, alanes, 64, &aa, sizeof aa, stream, "chem_adjoint", ashmem)) return rc;
     HIPCHECK(hipEventRecord(d->ev1, stream), "event");
     struct {
         const double* g;

@@ -195,9 +195,6 @@ struct chem_mechanism {
     std::string cache_file;
     std::mutex mu;
     std::map<int, chemmi::DeviceState> devices;
-    // the one-cell-per-lane build of a mechanism held in the wave-cooperative
-    // form, made on first use by the calls only that form provides (the adjoint)
-    chem_mechanism* lane_twin = nullptr;
 };
 
 namespace chemmi {

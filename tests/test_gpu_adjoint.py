@@ -133,33 +133,69 @@ def test_adjoint_m13_falloff_and_third_body(chem, mechs, dev):
     _assert_grad_parity(gT0, gY0, ga, gb, ge, ref, spread, "m13")
 
 
-def test_adjoint_of_a_wave_cooperative_mechanism(chem, mechs, dev):
-    """A mechanism held in the wave-cooperative form takes its adjoint from a
-    one-cell-per-lane build made on first use: same gradients as the lane
-    form's own adjoint, bitwise, also after a parameter change."""
+def _load_wide(chem, name):
     import os
-    gm, _ = mechs["m13"]
     old = os.environ.get("CHEM_LANE_MAX_SPECIES")
     os.environ["CHEM_LANE_MAX_SPECIES"] = "0"
     try:
-        gw = chem.Mechanism(mech_path("m13"))
+        return chem.Mechanism(mech_path(name))
     finally:
         if old is None:
             del os.environ["CHEM_LANE_MAX_SPECIES"]
         else:
             os.environ["CHEM_LANE_MAX_SPECIES"] = old
-    T, p, Y = uniform_cells(mech_text("m13"), 40, 67)
-    gT, gY = _loss_weights("m13", len(T), True, seed=16)
-    for scale in (0.0, 0.1):
-        lnA, b, Ea = gm.get_params()
+
+
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_wide_adjoint_matches_oracle_and_lane_form(chem, mechs, dev, name):
+    """The wave-cooperative adjoint (16-lane groups here) against the oracle
+    and the one-cell-per-lane adjoint of the same mechanism; after a parameter
+    change the two forms still agree (a stale parameter buffer would not)."""
+    gm, om = mechs[name]
+    gw = _load_wide(chem, name)
+    T, p, Y = uniform_cells(mech_text(name), 40, 67)
+    gT, gY = _loss_weights(name, len(T), True, seed=16)
+    w = _run(chem, gw, T, p, Y, 1e-8, gT, gY, dev)
+    ref, spread = _oracle_adjoint(om, T, p, Y, 1e-8, gT, gY)
+    _assert_grad_parity(*w[:5], ref, spread, f"wide {name}")
+    a = _run(chem, gm, T, p, Y, 1e-8, gT, gY, dev)
+    _assert_grad_parity(*w[:5], a[:5], spread, f"wide vs lane {name}")
+    lnA, b, Ea = gm.get_params()
+    try:
         for m in (gm, gw):
-            m.set_params(lnA + scale, b, Ea)
-        a = _run(chem, gm, T, p, Y, 1e-8, gT, gY, dev)
-        w = _run(chem, gw, T, p, Y, 1e-8, gT, gY, dev)
-        for x, y in zip(a[:7], w[:7]):
-            assert np.array_equal(x, y)
+            m.set_params(lnA + 0.1, b, Ea)
+        w2 = _run(chem, gw, T, p, Y, 1e-8, gT, gY, dev)
+        a2 = _run(chem, gm, T, p, Y, 1e-8, gT, gY, dev)
+        assert not np.array_equal(w2[0], w[0])
+        for x, y in zip(w2[:5], a2[:5]):
+            scale = np.abs(y).max(axis=-1, keepdims=True) if y.ndim == 2 else np.abs(y).max()
+            assert np.all(np.abs(x - y) <= 1e-3 * scale + 1e-300)
+    finally:
         for m in (gm, gw):
             m.set_params(lnA, b, Ea)
+
+
+def test_wide_adjoint_m32_sample(chem, oracle_lib, dev):
+    """The 32-species mechanism (one 64-lane wave per cell): cells of every
+    region of the 2048 x 2048 field against the oracle; checkpoint interval
+    and repetition bitwise neutral."""
+    w = WORKLOADS["big4m"]
+    gm = chem.Mechanism(mech_path("m32"))
+    om = oracle_lib.Mechanism(mech_path("m32"))
+    Tf, pf, Yf, reg = rde_field(mech_text("m32"), 512, 512, w["seed"])
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([rng.choice(np.where(reg == r)[0], 8, replace=False) for r in (0, 1, 2)])
+    T, p, Y = Tf[idx], pf[idx], Yf[idx]
+    gT, gY = _loss_weights("m32", len(T), True, seed=17)
+    a = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev)
+    assert a[7]["failed"] == 0
+    _assert_grad_parity(*a[:5], *_oracle_adjoint(om, T, p, Y, w["dt"], gT, gY), "m32")
+    for k in (1, 16):
+        b = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev, checkpoint_every=k)
+        for x, y in zip(a[:7], b[:7]):
+            assert np.array_equal(x, y)
+    Ti, Yi, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), w["dt"], RTOL, ATOL)
+    assert np.array_equal(a[5], Ti.cpu().numpy()) and np.array_equal(a[6], Yi.cpu().numpy())
 
 
 def test_adjoint_forward_result_equals_integrate(chem, mechs, dev):
