@@ -194,20 +194,22 @@ def big_leg(chem, torch, dev, steps):
     return out
 
 
-def adjoint_leg(chem, torch, dev, steps, cpu_cells):
+def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
     """The discrete adjoint on the 512 x 512 adjoint field (262,144 cells, dt
-    1e-8 s): L = sum over cells of T_end / 1000 K + Y_H2O,end; gradients with
-    respect to T0, Y0 and every reaction's ln A, b, Ea.  Times whole calls
-    (sizing pass, arena set-up, adjoint kernel, parameter reduction) against
-    the forward integration of the same field in both forms."""
+    1e-8 s, 9 species), or on the 2048 x 2048 32-species field (wave-
+    cooperative form): L = sum over cells of T_end / 1000 K + Y_H2O,end;
+    gradients with respect to T0, Y0 and every reaction's ln A, b, Ea.  Times
+    whole calls (sizing pass, arena set-up, adjoint kernel, parameter
+    reduction) against the forward integration of the same field in both
+    forms."""
     from workloads import WORKLOADS, mech_path, mech_text
     from workloads.states import parse_species, rde_field
-    w = WORKLOADS["adj256k"]
+    w = WORKLOADS[workload]
     mech = chem.Mechanism(mech_path(w["mech"]))
     T, p, Y, _ = rde_field(mech_text(w["mech"]), w["width"], w["height"], w["seed"])
     n = len(T)
     species = parse_species(mech_text(w["mech"]))[0]
-    gT = np.full(n, 1.0 / w["t_ref"])
+    gT = np.full(n, 1.0 / w.get("t_ref", 1000.0))
     gY = np.zeros((n, len(species)))
     gY[:, species.index("H2O")] = 1.0
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -230,7 +232,7 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells):
         kms.append(out[7]["kernel_ms"])
     adj_ms = 1e3 * (time.perf_counter() - t0) / steps
     st = out[7]
-    res = {"workload": "adj256k", "cells": n,
+    res = {"workload": workload, "cells": n,
            "mechanism": f"{w['mech']} ({mech.ns} species, {mech.nr} reactions)",
            "dt": w["dt"], "params": 3 * mech.nr,
            "ms_per_call": adj_ms, "adjoint_kernel_ms": float(np.mean(kms)),
@@ -271,6 +273,7 @@ def main():
     ap.add_argument("--amr-only", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true")
     ap.add_argument("--adjoint-cpu-cells", type=int, default=192)
+    ap.add_argument("--adjoint-workload", default="adj256k")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -302,7 +305,8 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps),
-                                                 0 if args.no_cpu else args.adjoint_cpu_cells)}))
+                                                 0 if args.no_cpu else args.adjoint_cpu_cells,
+                                                 args.adjoint_workload)}))
         return
 
     w = WORKLOADS[args.workload]
@@ -416,6 +420,8 @@ def main():
         line["big4m"] = big_leg(chem, torch, dev, 2)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else args.adjoint_cpu_cells)
+        if not args.no_big:
+            line["adjoint_big4m"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else 16, "big4m")
     print(json.dumps(line))
 
 
