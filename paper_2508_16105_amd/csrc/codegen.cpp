@@ -485,6 +485,16 @@ WideLayout wide_layout(const MechanismData& m)
         w.G = 0;
         return w;
     }
+    for (const auto& r : m.reactions) {   // the packed reaction table's field widths
+        for (const auto* side : {&r.reac, &r.prod})
+            for (const auto& t : *side)
+                if (t.nu > 3) w.G = 0;
+        if (r.dnu < -4 || r.dnu > 3) w.G = 0;
+    }
+    if (nr > 2046 || w.G == 0) {
+        w.G = 0;
+        return w;
+    }
     w.nslot = 2 * w.maxt;
     w.pw = w.nslot + 2;
     w.jw = (ns + 1) % 2 ? ns + 1 : ns + 2;
@@ -574,6 +584,32 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
                                  tr && r.has_T2 ? 1.0 : 0.0});
         if (effrow[s] >= 0)
             for (int k = 0; k < ns; ++k) eff.push_back(r.eff[k]);
+    }
+    // packed per slot, for one load per reaction round: species slots (8 bits
+    // each: species index + 1 in the low 6 bits, coefficient in the top 2;
+    // 0 = unused) in two words, then kind | (dnu + 4) << 2 | (effrow + 1) << 5 |
+    // orig << 16
+    {
+        std::vector<int> pack;
+        for (int s = 0; s < nr; ++s) {
+            const auto& r = m.reactions[order[s]];
+            unsigned long long slots = 0;
+            for (int t = 0; t < 2 * w.maxt; ++t) {
+                const bool isr = t < w.maxt;
+                const auto& side = isr ? r.reac : r.prod;
+                const int q = isr ? t : t - w.maxt;
+                unsigned v = 0;
+                if (q < (int)side.size()) v = (unsigned)(side[q].sp + 1) | ((unsigned)side[q].nu << 6);
+                slots |= (unsigned long long)v << (8 * t);
+            }
+            pack.push_back((int)(unsigned)(slots & 0xffffffffull));
+            pack.push_back((int)(unsigned)(slots >> 32));
+            pack.push_back((int)((unsigned)r.kind | ((unsigned)(r.dnu + 4) << 2) | ((unsigned)(effrow[s] + 1) << 5) |
+                                 ((unsigned)order[s] << 16)));
+        }
+        o << "// per slot: species slots (two words, 8 bits each: index + 1 | nu << 6), then\n"
+             "// kind | (dnu + 4) << 2 | (EFF row + 1) << 5 | original index << 16\n";
+        ints("RX_PACK", pack);
     }
     o << "// reactions in evaluation order (slot s): original index, kind (0 elementary,\n"
          "// 1 third-body, 2 Lindemann, 3 Troe), sum nu'' - sum nu', species and\n"

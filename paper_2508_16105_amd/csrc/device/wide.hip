@@ -160,12 +160,16 @@ enum : int { F_ONLY = 0, F_JAC = 1, PARAM_VJP = 2 };
 // and the coefficient of the third-body efficiencies in d q / d C); with
 // PARAM_VJP the products of w . df/dq_j with d q_j / d(ln A, b, Ea) added to g.
 template <class S, int MODE>
-__device__ __forceinline__ void reaction(int j, const double* __restrict__ par, S* __restrict__ L, S T, S lnT,
-                                         S iT, S lnPRT, S ctot, S irho, S rcpinv, S* __restrict__ g)
+__device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const double* __restrict__ par,
+                                         S* __restrict__ L, S T, S lnT, S iT, S lnPRT, S ctot, S irho, S rcpinv,
+                                         S* __restrict__ g)
 {
     constexpr bool JAC = MODE == F_JAC;
-    const int kind = mech::RX_KIND[j];
-    const int oj = mech::RX_ORIG[j];
+    // the slot's packed table entry (loaded by the caller ahead of time)
+    const int kind = (int)(pk[2] & 3u);
+    const int dnu = (int)((pk[2] >> 2) & 7u) - 4;
+    const int er = (int)((pk[2] >> 5) & 2047u) - 1;
+    const int oj = (int)(pk[2] >> 16);
     const double pb = par[NR + oj], pe = par[2 * NR + oj];
     S lnk = lnT * pb;
     lnk = fma(-iT, pe, lnk);
@@ -175,8 +179,9 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
     S lnKc = 0.0, dH = 0.0, ws = 0.0;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
-        sp[s] = mech::RX_SP[j * NSLOT + s];
-        nu[s] = mech::RX_NU[j * NSLOT + s];
+        const unsigned v = (pk[s / 4] >> (8 * (s % 4))) & 255u;
+        sp[s] = (int)(v & 63u) - 1;
+        nu[s] = (int)(v >> 6);
         c[s] = 1.0;
         if (sp[s] >= 0) {
             const double sgn = s < mech::MAXT ? -(double)nu[s] : (double)nu[s];
@@ -186,9 +191,7 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
             c[s] = L[mech::L_C + sp[s]];
         }
     }
-    const int dnu = mech::RX_DNU[j];
     lnKc = fma((double)dnu, lnPRT, lnKc);
-    const int er = mech::RX_EFFROW[j];
     S Mc = ctot;
     if (er >= 0) {
         for (int m = 0; m < NS; ++m) Mc = fma(mech::EFF[er * NS + m] - 1.0, L[mech::L_C + m], Mc);
@@ -209,12 +212,12 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
         const S logPr = floored ? S(-300.0) : log10(Pr);
         if (kind == 3) {
             const double* tr = &mech::RX_TROE[j * 8];
-            const S e3 = exp(-T * tr[2]);
-            const S e1 = exp(-T * tr[3]);
+            const S e3 = chem_math::exp_tang(-T * tr[2]);
+            const S e1 = chem_math::exp_tang(-T * tr[3]);
             S Fc = tr[0] * e3 + tr[1] * e1;
             S dFc = tr[5] * e3 + tr[6] * e1;
             if (tr[7] != 0.0) {
-                const S e2 = exp(-tr[4] * iT);
+                const S e2 = chem_math::exp_tang(-tr[4] * iT);
                 Fc += e2;
                 dFc += tr[4] * iT * iT * e2;
             }
@@ -226,7 +229,7 @@ __device__ __forceinline__ void reaction(int j, const double* __restrict__ par, 
             const S tx = tu / tden;
             const S opx2 = 1.0 + tx * tx;
             const S logF = logFc / opx2;
-            Fb = exp(mech::LN10 * logF);
+            Fb = chem_math::exp_tang(mech::LN10 * logF);
             if (MODE != F_ONLY) {
                 const S tg = -logFc * 2.0 * tx / (opx2 * opx2);
                 dF_dPr = floored ? S(0.0) : tg * tn / (tden * tden);
@@ -311,6 +314,15 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
     // evaluation instead of being hoisted out of the substep loop into SGPRs
     const int z = mech::opaque_zero();
     mech::cdbl* MW = (mech::cdbl*)&mech::MWTAB[0] + z;
+    // the packed table entries of the lane's reaction slots, loaded now so the
+    // loads overlap the thermo phase
+    unsigned pk[ROUNDS][3];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int j = r * G + i;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) pk[r][q] = j < NR ? (unsigned)mech::RX_PACK[3 * j + q] : 0u;
+    }
     if (i < N) {
         L[mech::L_Y + i] = yi;
         if (MODE == PARAM_VJP) L[mech::L_W + i] = wi;
@@ -368,14 +380,19 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
             const int j = r * G + i;
-            if (j < NR) reaction<S, MODE>(j, par, L, T, lnT, iT, lnPRT, ctot, irho, rcp, g[r]);
+            if (j < NR) reaction<S, MODE>(j, pk[r], par, L, T, lnT, iT, lnPRT, ctot, irho, rcp, g[r]);
         }
         return S(0.0);
     }
 #pragma unroll 1
     for (int r = 0; r < ROUNDS; ++r) {
         const int j = r * G + i;
-        if (j < NR) reaction<S, MODE>(j, par, L, T, lnT, iT, lnPRT, ctot, irho, irho, g[0]);
+        unsigned pr[3] = {pk[0][0], pk[0][1], pk[0][2]};
+#pragma unroll
+        for (int q = 1; q < ROUNDS; ++q)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) pr[t] = (q == r) ? pk[q][t] : pr[t];
+        if (j < NR) reaction<S, MODE>(j, pr, par, L, T, lnT, iT, lnPRT, ctot, irho, irho, g[0]);
     }
     lds_sync();
     // species lists come padded to multiples of 4: four entries' loads in flight
