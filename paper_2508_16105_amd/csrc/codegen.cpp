@@ -212,10 +212,13 @@ struct Emitter {
         return s;
     }
 
-    // mode 0: source terms; 1: source terms and Jacobian; 2: parameter products
+    // mode 0: source terms; 1: source terms and Jacobian; 2: parameter
+    // products; 3: production rates, the Jacobian-transpose product J^T w and
+    // the parameter products
     void reaction(int j, int mode)
     {
-        const bool jac = mode == 1, vjp = mode == 2;
+        const bool jtv = mode == 3;
+        const bool jac = mode == 1 || jtv, vjp = mode == 2 || jtv;
         const auto& r = m.reactions[j];
         o << "  { // reaction " << j << "\n";
         // ln k = ln A + b ln T - (Ea/R) / T, one scalar operand per instruction
@@ -288,7 +291,7 @@ struct Emitter {
         std::vector<int> nu(ns, 0);
         for (auto& t : r.reac) nu[t.sp] -= t.nu;
         for (auto& t : r.prod) nu[t.sp] += t.nu;
-        if (vjp) {
+        if (vjp && !jtv) {
             // w . df/dq_j: species rows W_k nu_kj / rho, temperature row -R T dH_j/RT / (rho cp)
             std::string ws, sh;
             for (int k = 0; k < ns; ++k)
@@ -344,6 +347,36 @@ struct Emitter {
             if (falloff) o << "    const S dMterm = dkdM*(pf - iKc*pr);\n";
             for (int mm = 0; mm < ns; ++mm)
                 if (!dq[mm].empty()) o << "    const S dq" << mm << " = " << dq[mm] << ";\n";
+            if (jtv) {
+                // weights of this reaction's rate in w . f (species rows) and in the
+                // heat release: wY = sum_k nu_k W_k w_{1+k}, hs = sum_k nu_k H_k/RT;
+                // the columns of J^T w collect wY dq_m and hs dq_m; s = sum_m dq_m C_m
+                std::string ws, sh, sj;
+                for (int k = 0; k < ns; ++k)
+                    if (nu[k]) ws += " + " + lit(nu[k]) + "*(MW[" + std::to_string(k) + "]*w[" + std::to_string(1 + k) + "])";
+                for (int k = 0; k < ns; ++k)
+                    if (nu[k]) sh += " + " + lit(nu[k]) + "*HRT[" + std::to_string(k) + "]";
+                for (int mm = 0; mm < ns; ++mm)
+                    if (!dq[mm].empty()) sj += " + dq" + std::to_string(mm) + "*C[" + std::to_string(mm) + "]";
+                o << "    const S wY = 0.0" << ws << ";\n"
+                     "    const S hs = 0.0" << sh << ";\n"
+                     "    const S sj = 0.0" << sj << ";\n";
+                for (int mm = 0; mm < ns; ++mm)
+                    if (!dq[mm].empty())
+                        o << "    colA[" << mm << "] = fma(wY, dq" << mm << ", colA[" << mm << "]); colH[" << mm
+                          << "] = fma(hs, dq" << mm << ", colH[" << mm << "]);\n";
+                o << "    SwY = fma(wY, sj, SwY); HSa = fma(hs, sj, HSa);\n"
+                     "    wYT = fma(wY, dqT, wYT); HwT = fma(hs, dqT, HwT);\n";
+                // parameter products, as in param_vjp
+                o << "    const S wsum = wY * irho - w[0] * (" << lit(kRu) << " * T) * hs * rcpinv;\n";
+                if (falloff) o << "    const S qA = q * (Pr * ipr1 - dF_dPr);\n";
+                else o << "    const S qA = q;\n";
+                o << "    const S g = wsum * qA;\n"
+                     "    gA[" << j << "] += g;\n"
+                     "    gb[" << j << "] += g * lnT;\n"
+                     "    gE[" << j << "] += g * (-iT * " << lit(1.0 / kRu) << ");\n  }\n";
+                return;
+            }
             for (int k = 0; k < ns; ++k) {
                 if (!nu[k]) continue;
                 for (int mm = 0; mm < ns; ++mm)
@@ -460,6 +493,42 @@ struct Emitter {
         cp_sum(false);
         o << "  const S rcpinv = T * sig * ip / cpm;\n";
         for (int j = 0; j < nr; ++j) reaction(j, 2);
+        o << "}\n\n";
+        // v = J(y)^T w and the parameter products in one pass, without forming J:
+        // every entry of J is assembled from per-reaction partials, so J^T w
+        // needs only per-reaction weights and two column sums (see chain_rule):
+        //   v_{1+m} = (colA_m + Wbar (w.f_Y - SwY/rho)) / W_m + w_0 J_{0,1+m}
+        //   v_0     = (wYT - SwY/T)/rho + (w.f_Y)/T + w_0 J_00
+        // with colA_m = sum_j wY_j dq_j/dC_m, colH_m = sum_j hs_j dq_j/dC_m (= HJ_m),
+        // SwY = sum_j wY_j s_j, HS = sum_j hs_j s_j, wYT = sum_j wY_j dq_j/dT,
+        // HwT = sum_j hs_j dq_j/dT, s_j = sum_m dq_j/dC_m C_m.
+        o << "template <class S>\n__device__ __forceinline__ void jtv_param(const double* __restrict__ par, double p, "
+             "double ip, const S (&y)[N], const double (&w)[N], S (&v)[N], S* __restrict__ gA, S* __restrict__ gb, "
+             "S* __restrict__ gE)\n{\n";
+        prologue(true);
+        cp_sum(true);
+        o << "  const S icpm = 1.0 / cpm;\n"
+             "  const S rcpinv = T * sig * ip * icpm;\n"
+             "  S colA[NS], colH[NS];\n"
+             "#pragma unroll\n  for (int k = 0; k < NS; ++k) { colA[k] = 0.0; colH[k] = 0.0; }\n"
+             "  S SwY = 0.0, HSa = 0.0, wYT = 0.0, HwT = 0.0;\n";
+        for (int j = 0; j < nr; ++j) reaction(j, 3);
+        o << "  S hw = 0.0, Wf = 0.0, cpw = 0.0;\n";
+        for (int k = 0; k < ns; ++k)
+            o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw); cpw = fma(cpR[" << k << "], wd[" << k
+              << "], cpw); Wf = fma(w[" << 1 + k << "], MW[" << k << "] * (irho * wd[" << k << "]), Wf);\n";
+        o << "  const S fT = -" << lit(kRu) << " * T * hw * rcpinv;\n"
+             "  const S RT = " << lit(kRu) << " * T;\n"
+             "  const S icp = icpm * " << lit(1.0 / kRu) << ";\n"
+             "  const S SwYg = Wf - irho * SwY;\n"
+             "  const S wg = Wbar * SwYg;\n";
+        for (int mm = 0; mm < ns; ++mm)
+            o << "  { S t = fma(rho, colH[" << mm << "], -Wbar*HSa) * (-RT * rcpinv);\n"
+                 "    S u = fma(cpR[" << mm << "], icp * " << lit(kRu) << ", -Wbar);\n"
+                 "    const S J0m = fma(-fT, u, t) * MW[" << ns + mm << "];\n"
+                 "    v[" << 1 + mm << "] = fma(colA[" << mm << "] + wg, MW[" << ns + mm << "], w[0] * J0m); }\n";
+        o << "  const S J00 = -" << lit(kRu) << " * (cpw + T*HwT - HSa) * rcpinv - fT * (dcp * icp - iT);\n"
+             "  v[0] = fma(irho, wYT - SwY * iT, fma(iT, Wf, w[0] * J00));\n";
         o << "}\n\n}  // namespace mech\n";
         return o.str();
     }

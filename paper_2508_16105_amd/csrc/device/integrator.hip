@@ -565,12 +565,14 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
                                           double* __restrict__ gE)
 {
     using chem_math::Dual;
-    double J0[N][N], M[N][N], f[N];
-    mech::rhs_jac(par, p, ip, y, f, J0);
+    double M[N][N], f[N];
+    mech::rhs_jac(par, p, ip, y, f, M);
     const double ghinv = 1.0 / (h * Rodas4::gamma);
     const double hinv = 1.0 / h;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) M[i][j] = (i == j ? ghinv : 0.0) - J0[i][j];
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < N; ++j) M[i][j] = -M[i][j];
+        M[i][i] += ghinv;
+    }
     int piv[N];
     bool ok;
     const unsigned swaps = lu_factor(M, piv, ok);
@@ -592,7 +594,8 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
         for (int k = 0; k < N; ++k) u[s][k] = fma(acc[k], hinv, fs[k]);
         lu_solve(M, piv, swaps, u[s]);
     }
-    // reverse over the stages
+    // reverse over the stages: Ybar_s = J(Y_s)^T w_s and the parameter products
+    // in one pass of the generated Jacobian-transpose product
     const double mw[Rodas4::S] = {RA[5][0], RA[5][1], RA[5][2], RA[5][3], 1.0, 1.0};
     double ub[Rodas4::S][N], w[Rodas4::S][N], yb[N];
     for (int k = 0; k < N; ++k) {
@@ -602,36 +605,21 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
     for (int s = Rodas4::S - 1; s >= 0; --s) {
         for (int k = 0; k < N; ++k) w[s][k] = ub[s][k];
         lu_solve_t(M, piv, swaps, w[s]);
-        double Js[N][N], fs[N], Yb[N];
-        if (s == 0) {
-            for (int i = 0; i < N; ++i)
-                for (int j = 0; j < N; ++j) Js[i][j] = J0[i][j];
-        } else {
-            mech::rhs_jac(par, p, ip, Ys[s], fs, Js);
-        }
-        for (int k = 0; k < N; ++k) {
-            double v = 0.0;
-            for (int i = 0; i < N; ++i) v = fma(Js[i][k], w[s][i], v);
-            Yb[k] = v;
-            yb[k] += v;
-        }
-        mech::param_vjp(par, p, ip, Ys[s], w[s], gA, gb, gE);
+        double Yb[N];
+        mech::jtv_param(par, p, ip, Ys[s], w[s], Yb, gA, gb, gE);
+        for (int k = 0; k < N; ++k) yb[k] += Yb[k];
         for (int j = 0; j < s; ++j)
             for (int k = 0; k < N; ++k) ub[j][k] = fma(RA[s][j], Yb[k], fma(RC[s][j] * hinv, w[s][k], ub[j][k]));
     }
-    // second-order terms at y, one dual evaluation per stage direction
+    // second-order terms at y (J(y) inside M): D_{u_s}[J(y)^T w_s] and the
+    // parameter products' derivative, one dual evaluation per stage direction
     for (int s = 0; s < Rodas4::S; ++s) {
-        Dual yd[N], fd[N], Jd[N][N];
+        Dual yd[N], vd[N];
         for (int k = 0; k < N; ++k) yd[k] = Dual(y[k], u[s][k]);
-        mech::rhs_jac(par, p, ip, yd, fd, Jd);
-        for (int k = 0; k < N; ++k) {
-            double v = 0.0;
-            for (int i = 0; i < N; ++i) v = fma(Jd[i][k].d, w[s][i], v);
-            yb[k] += v;
-        }
         Dual gAd[mech::NR], gbd[mech::NR], gEd[mech::NR];
         for (int j = 0; j < mech::NR; ++j) { gAd[j] = 0.0; gbd[j] = 0.0; gEd[j] = 0.0; }
-        mech::param_vjp(par, p, ip, yd, w[s], gAd, gbd, gEd);
+        mech::jtv_param(par, p, ip, yd, w[s], vd, gAd, gbd, gEd);
+        for (int k = 0; k < N; ++k) yb[k] += vd[k].d;
         for (int j = 0; j < mech::NR; ++j) {
             gA[j] += gAd[j].d;
             gb[j] += gbd[j].d;
