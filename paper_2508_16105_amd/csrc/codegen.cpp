@@ -74,9 +74,6 @@ struct Emitter {
     void thermo_table()
     {
         // constant-address-space view: loads through it are scalar (uniform)
-        o << "__constant__ double EXP2_J64[64] = {";
-        for (int j = 0; j < 64; ++j)
-            o << lit((double)std::exp2((long double)j / 64.0L)) << (j < 63 ? ", " : "};\n");
         o << "typedef const __attribute__((address_space(4))) double cdbl;\n"
              "// a zero the compiler cannot see through, known to be wave-uniform\n"
              "__device__ __forceinline__ int opaque_zero()\n{\n"
@@ -234,14 +231,14 @@ struct Emitter {
         const bool falloff = r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe;
         if (r.kind != RxnKind::Elementary) o << "    const S Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
-            o << "    const S kf = chem_math::exp_tang(lnk);\n"
-                 "    const S kr = chem_math::exp_tang(lnk - lnKc);\n";
+            o << "    const S kf = chem_math::exp_poly(lnk);\n"
+                 "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
-            o << "    const S kinf = chem_math::exp_tang(lnk);\n"
+            o << "    const S kinf = chem_math::exp_poly(lnk);\n"
                  "    const S lnr0 = " << lit(r.lnA0) << " + " << lit(r.b0) << "*lnT - "
               << lit(r.EaR0) << "*iT - lnk;\n"
-                 "    const S r0 = chem_math::exp_tang(lnr0);\n"
+                 "    const S r0 = chem_math::exp_poly(lnr0);\n"
                  "    const S Pr = r0 * Mc;\n"
                  "    const bool floored = !(Pr >= 1e-300);\n"
                  "    const S logPr = floored ? -300.0 : log10(Pr);\n";
@@ -278,7 +275,7 @@ struct Emitter {
             }
             o << "    const S ipr1 = 1.0 / (1.0 + Pr);\n"
                  "    const S kf = kinf * Pr * ipr1 * Fb;\n"
-                 "    const S iKc = chem_math::exp_tang(-lnKc);\n"
+                 "    const S iKc = chem_math::exp_poly(-lnKc);\n"
                  "    const S kr = kf * iKc;\n";
         }
         o << "    const S pf = " << side_product(r.reac) << ";\n"

@@ -69,13 +69,24 @@ __device__ __forceinline__ unsigned lu_factor(double (&A)[N][N], int (&piv)[N], 
     return swaps;
 }
 
+// The pivot index read inside the (rare) swap branch is opaque to the
+// optimiser: otherwise the row compares of every step are hoisted out of the
+// branch, shared by all solves of a Rosenbrock step and kept live in scalar
+// registers, which spill.  Back substitution runs by columns, so each unknown
+// is one multiply after the previous one rather than a chain of N - i FMAs.
+__device__ __forceinline__ int opaque_index(int p)
+{
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
 __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
                                          double (&b)[N])
 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         if (swaps & (1u << k)) {
-            const int p = piv[k];
+            const int p = opaque_index(piv[k]);
 #pragma unroll
             for (int i = k + 1; i < N; ++i) {
                 const bool s = (p == i);
@@ -89,10 +100,9 @@ __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&pi
     }
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        double v = b[i];
+        b[i] *= A[i][i];
 #pragma unroll
-        for (int j = i + 1; j < N; ++j) v = fma(-A[i][j], b[j], v);
-        b[i] = v * A[i][i];
+        for (int r = 0; r < i; ++r) b[r] = fma(-A[r][i], b[i], b[r]);
     }
 }
 
@@ -247,7 +257,6 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
 extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateArgs a)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     extern __shared__ double lds[];
@@ -262,7 +271,6 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateAr
 extern "C" __global__ void __launch_bounds__(64, 1) chem_eval(EvalArgs a)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     double y[N], f[N];
@@ -301,7 +309,6 @@ struct FixedStepArgs {
 extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArgs a)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= a.ncell) return;
     extern __shared__ double lds[];
@@ -336,7 +343,6 @@ extern "C" __global__ void __launch_bounds__(256) chem_order_key(const PersistBl
                                                                 const double* __restrict__ par)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     __shared__ unsigned h[kCostBuckets];
     for (int b = threadIdx.x; b < kCostBuckets; b += blockDim.x) h[b] = 0u;
     __syncthreads();
@@ -421,7 +427,6 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
                                                 const double* __restrict__ par)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
     const long total = blk->total;
@@ -547,7 +552,7 @@ __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&
         for (int i = k + 1; i < N; ++i) v = fma(-A[i][k], b[i], v);
         b[k] = v;
         if (swaps & (1u << k)) {
-            const int p = piv[k];
+            const int p = opaque_index(piv[k]);
 #pragma unroll
             for (int i = k + 1; i < N; ++i) {
                 const bool s = (p == i);
@@ -636,7 +641,6 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
 extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
 {
     using namespace chem;
-    chem_math::exp_table_init(mech::EXP2_J64);
     const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= a.ncell) return;
     // cells of similar cost share a wave, so no lane waits long for the slowest

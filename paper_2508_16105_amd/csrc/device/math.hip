@@ -1,49 +1,43 @@
 // math.hip -- device math used by the generated source terms.
 //
-// exp(x) by Tang's table-driven method (P. T. P. Tang, "Table-driven
-// implementation of the exponential function in IEEE floating-point
-// arithmetic", ACM TOMS 15(2), 1989), with 64 table entries:
-//     x = (64 m + j) ln2/64 + r,  |r| <= ln2/128,
-//     exp(x) = 2^m * 2^(j/64) * exp(r),
-// exp(r) - 1 from its degree-5 Taylor polynomial (truncation below 4e-17 on
-// that interval), 2^(j/64) from a table held in LDS.  The reduction
-// r = x - n ln2/64 uses a two-part ln2/64 through fused multiply-adds.  No
-// special-case branches: NaN propagates, arguments beyond the double range
-// give 0 or inf through ldexp, +-inf give NaN (a failed step for the caller).
-// The table values (2^(j/64) rounded to double) come with the generated code
-// as EXP2_J64.
+// exp(x) without tables or branches (Cody & Waite argument reduction followed
+// by a polynomial; W. J. Cody and W. Waite, "Software Manual for the
+// Elementary Functions", 1980):
+//     x = n ln2 + r,  n = rint(x / ln2),  |r| <= ln2/2,
+//     exp(x) = 2^n * P(r),
+// with ln2 split in two parts so r = x - n ln2 is exact to working precision
+// through two fused multiply-adds, and P the degree-11 polynomial that
+// interpolates exp at the 12 Chebyshev nodes of [-ln2/2, ln2/2] (computed in
+// 40-digit arithmetic and rounded to double; interpolation error 3e-18,
+// 1.5 ulp overall with Horner evaluation in double; printed by
+// exp_poly_coeffs.py in the package directory).  No lookup table, so no LDS read
+// whose latency a single wave per SIMD would have to wait out.  NaN
+// propagates, arguments beyond the double range give 0 or inf through ldexp,
+// +-inf give NaN (a failed step for the caller).
 
 namespace chem_math {
 
-__shared__ double exp2_j64[64];
-
-// Copy the table into LDS.  Every thread of the workgroup must call this
-// (it contains a barrier) before the first exp_tang.
-__device__ __forceinline__ void exp_table_init(const double* __restrict__ src)
+__device__ __forceinline__ double exp_poly(double x)
 {
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) exp2_j64[i] = src[i];
-    __syncthreads();
-}
-
-__device__ __forceinline__ double exp_tang(double x)
-{
-    constexpr double kInvL = 92.33248261689366;            // 64 / ln 2
-    constexpr double kL1 = 0.010830424696249145;           // ln2/64, leading part
-    constexpr double kL2 = 3.623510646634843e-19;          // ln2/64 - kL1
-    const double nd = __builtin_rint(x * kInvL);
+    constexpr double kLog2e = 1.4426950408889634;           // 1 / ln 2
+    constexpr double kLn2Hi = 0.6931471805599453;           // ln 2 rounded to double
+    constexpr double kLn2Lo = 2.3190468138462996e-17;       // ln 2 - kLn2Hi
+    const double nd = __builtin_rint(x * kLog2e);
     const int n = (int)nd;
-    double r = fma(-nd, kL1, x);
-    r = fma(-nd, kL2, r);
-    // p = exp(r) - 1; scalar constants enter as multiplicands or through a
-    // separate add (an FMA with a scalar addend costs two extra moves)
-    double q = r * (1.0 / 120.0);
-    q = q + (1.0 / 24.0);
-    q = q * r;
-    q = q + (1.0 / 6.0);
-    q = fma(r, q, 0.5);
-    const double p = fma(r * r, q, r);
-    const double s = exp2_j64[n & 63];
-    return ldexp(fma(s, p, s), n >> 6);
+    double r = fma(-nd, kLn2Hi, x);
+    r = fma(-nd, kLn2Lo, r);
+    double q = fma(2.5110037605963777e-08, r, 2.763263963904103e-07);
+    q = fma(q, r, 2.755724091857897e-06);
+    q = fma(q, r, 2.4801485482328494e-05);
+    q = fma(q, r, 0.00019841269890047113);
+    q = fma(q, r, 0.0013888888952314775);
+    q = fma(q, r, 0.008333333333319601);
+    q = fma(q, r, 0.0416666666664881);
+    q = fma(q, r, 0.1666666666666668);
+    q = fma(q, r, 0.5000000000000019);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return ldexp(q, n);
 }
 
 }  // namespace chem_math
@@ -99,9 +93,9 @@ __device__ __forceinline__ Dual fma(Dual a, Dual b, double c) { return {::fma(a.
 __device__ __forceinline__ Dual fma(Dual a, double b, double c) { return {::fma(a.v, b, c), a.d * b}; }
 __device__ __forceinline__ Dual fma(double a, Dual b, double c) { return {::fma(a, b.v, c), a * b.d}; }
 __device__ __forceinline__ Dual fma(double a, double b, Dual c) { return {::fma(a, b, c.v), c.d}; }
-__device__ __forceinline__ Dual exp_tang(Dual x)
+__device__ __forceinline__ Dual exp_poly(Dual x)
 {
-    const double e = exp_tang(x.v);
+    const double e = exp_poly(x.v);
     return {e, e * x.d};
 }
 __device__ __forceinline__ Dual exp(Dual x)

@@ -199,25 +199,25 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     S kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0, Pr = 0.0;
     S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;
     if (kind < 2) {
-        kf = chem_math::exp_tang(lnk);
-        kr = chem_math::exp_tang(lnk - lnKc);
+        kf = chem_math::exp_poly(lnk);
+        kr = chem_math::exp_poly(lnk - lnKc);
     } else {
         // P_r = k0 [M] / k_inf, one exponential for the ratio
         const double* lo = &mech::RX_LOW[j * 3];
-        kinf = chem_math::exp_tang(lnk);
+        kinf = chem_math::exp_poly(lnk);
         const S lnr0 = lo[0] + lo[1] * lnT - lo[2] * iT - lnk;
-        r0 = chem_math::exp_tang(lnr0);
+        r0 = chem_math::exp_poly(lnr0);
         Pr = r0 * Mc;
         const bool floored = !(Pr >= 1e-300);
         const S logPr = floored ? S(-300.0) : log10(Pr);
         if (kind == 3) {
             const double* tr = &mech::RX_TROE[j * 8];
-            const S e3 = chem_math::exp_tang(-T * tr[2]);
-            const S e1 = chem_math::exp_tang(-T * tr[3]);
+            const S e3 = chem_math::exp_poly(-T * tr[2]);
+            const S e1 = chem_math::exp_poly(-T * tr[3]);
             S Fc = tr[0] * e3 + tr[1] * e1;
             S dFc = tr[5] * e3 + tr[6] * e1;
             if (tr[7] != 0.0) {
-                const S e2 = chem_math::exp_tang(-tr[4] * iT);
+                const S e2 = chem_math::exp_poly(-tr[4] * iT);
                 Fc += e2;
                 dFc += tr[4] * iT * iT * e2;
             }
@@ -229,7 +229,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
             const S tx = tu / tden;
             const S opx2 = 1.0 + tx * tx;
             const S logF = logFc / opx2;
-            Fb = chem_math::exp_tang(mech::LN10 * logF);
+            Fb = chem_math::exp_poly(mech::LN10 * logF);
             if (MODE != F_ONLY) {
                 const S tg = -logFc * 2.0 * tx / (opx2 * opx2);
                 dF_dPr = floored ? S(0.0) : tg * tn / (tden * tden);
@@ -239,7 +239,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
         }
         ipr1 = 1.0 / (1.0 + Pr);
         kf = kinf * Pr * ipr1 * Fb;
-        iKc = chem_math::exp_tang(-lnKc);
+        iKc = chem_math::exp_poly(-lnKc);
         kr = kf * iKc;
     }
     S pf = 1.0, pr = 1.0;
@@ -895,7 +895,6 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
 extern "C" __global__ void __launch_bounds__(64, 2) chem_plain(chem::IntegrateArgs a)
 {
     using namespace chemw;
-    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int grp = (int)threadIdx.x / G;
     const long cell = (long)blockIdx.x * CPW + grp;
@@ -911,7 +910,6 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_plain(chem::IntegrateAr
 extern "C" __global__ void __launch_bounds__(64) chem_eval(EvalArgs a)
 {
     using namespace chemw;
-    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int grp = (int)threadIdx.x / G;
     const long cell = (long)blockIdx.x * CPW + grp;
@@ -945,7 +943,6 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_persistent(const Persis
                                                                  const double* __restrict__ par)
 {
     using namespace chemw;
-    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int grp = (int)threadIdx.x / G;
     double* L = lds + grp * mech::LDS_CELL;
@@ -991,7 +988,6 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_persistent(const Persis
 extern "C" __global__ void __launch_bounds__(64) chem_adjoint(AdjointArgs a)
 {
     using namespace chemw;
-    chem_math::exp_table_init(mech::EXP2_J64);
     extern __shared__ double lds[];
     const int grp = (int)threadIdx.x / G;
     const long slot = (long)blockIdx.x * CPW + grp;
