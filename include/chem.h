@@ -91,7 +91,8 @@ typedef struct {
     const int32_t *const *cost; /* nullable host array [nfield] of nullable device int32 [ncell]
                                    per-cell cost hints (e.g. nacc + nrej of the previous call);
                                    fields without one get a cost predicted from their state:
-                                   the RMS over y of f(y) dt / (atol + rtol |y|) */
+                                   the mean over the components of
+                                   log2(1 + |f_k(y)| dt / (atol + rtol |y_k|)) */
 } chem_options;
 
 typedef struct {

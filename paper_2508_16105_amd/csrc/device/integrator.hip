@@ -332,7 +332,12 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArg
 // sort over 256 cost buckets): the cost of a cell is either given by the
 // caller (e.g. its substep count in the previous call, the measured load the
 // paper balances on) or predicted from its state by one source-term
-// evaluation (the RMS of f dt / (atol + rtol |y|)).  Positions are dealt to
+// evaluation: the mean over the components of log2(1 + |f_k| dt / (atol +
+// rtol |y_k|)), i.e. by how many factors of two each component would move,
+// in tolerance units, over dt.  A log-average weighs every component; an RMS
+// is set by the fastest-changing trace species alone and ranks the costs of
+// reacting cells far worse (rank correlation 0.38 against 0.69 on the RDE
+// field's reacting cells).  Positions are dealt to
 // nq queues (one per XCD) interleaved, so every queue sees the same cost mix.
 // Each wave pulls cells from the queue of its XCD (workgroups are dealt to
 // the XCDs round-robin), moves on to the next queue when its own is empty,
@@ -364,11 +369,8 @@ extern "C" __global__ void __launch_bounds__(256) chem_order_key(const PersistBl
                 mech::rhs(par, p, 1.0 / p, y, f);
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const double e = f[k] * st.dt / (st.atol + st.rtol * fabs(y[k]));
-                    s = fma(e, e, s);
-                }
-                key = 4.0 * log2(1.0 + sqrt(s * (1.0 / N)));
+                for (int k = 0; k < N; ++k) s += log2(1.0 + fabs(f[k]) * st.dt / (st.atol + st.rtol * fabs(y[k])));
+                key = 6.0 * s * (1.0 / N);
             }
             const int b = (key >= 0.0) ? (key < kCostBuckets - 1 ? (int)key : kCostBuckets - 1)
                                        : kCostBuckets - 1;    // NaN: schedule early
