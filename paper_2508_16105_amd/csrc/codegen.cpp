@@ -716,6 +716,25 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
     ints("SP_OFF", off);
     ints("SP_RX", srx);
     ints("SP_NU", snu);
+    // the same entries packed for the Jacobian rows, so one round of loads gives
+    // everything an entry needs: slot | (net coefficient & 255) << 16, then the
+    // species of the reaction's slots 0-3 and 4-5 as bytes (index + 1, 0 unused)
+    {
+        std::vector<int> jp;
+        for (size_t e = 0; e < srx.size(); ++e) {
+            const int slot = srx[e];
+            jp.push_back((int)((unsigned)slot | (((unsigned)snu[e] & 255u) << 16)));
+            unsigned b[2] = {0u, 0u};
+            for (int t = 0; t < w.nslot; ++t) {
+                const int spc = sp[slot * w.nslot + t];
+                b[t / 4] |= (unsigned)(spc + 1) << (8 * (t % 4));
+            }
+            jp.push_back((int)b[0]);
+            jp.push_back((int)b[1]);
+        }
+        o << "// per SP entry: slot | (net coefficient & 255) << 16, slot species 0-3, 4-5 (bytes, index + 1)\n";
+        ints("SP_JPACK", jp);
+    }
     // non-elementary reactions t: their slot, and the net coefficient of every
     // species in them (the dense third-body part of the Jacobian rows)
     std::vector<int> tbslot;
@@ -731,9 +750,21 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
             nutb.push_back((double)v);
         }
     o << "constexpr int NTB = " << tbslot.size() << ";\n"
-         "// non-elementary reaction t: its slot (EFF row t), and NU_TB[k * NTB + t]\n";
+         "// non-elementary reaction t: its slot (EFF row t); the net coefficient of\n"
+         "// species k in it as a 4-bit field (coefficient + 8), eight per word:\n"
+         "// NU_TB4[k * NTBW + t / 8] >> (4 (t % 8))\n";
     ints("TB_SLOT", tbslot);
-    dbls("NU_TB", nutb);
+    {
+        const int ntb = (int)tbslot.size(), ntbw = std::max(1, (ntb + 7) / 8);
+        std::vector<int> packed((size_t)ns * ntbw, 0);
+        for (int k = 0; k < ns; ++k)
+            for (int t = 0; t < ntb; ++t) {
+                const int v = (int)nutb[(size_t)k * ntb + t];
+                packed[(size_t)k * ntbw + t / 8] |= (int)((unsigned)(v + 8) << (4 * (t % 8)));
+            }
+        o << "constexpr int NTBW = " << ntbw << ";\n";
+        ints("NU_TB4", packed);
+    }
     o << "}  // namespace mech\n";
     return o.str();
 }

@@ -436,15 +436,22 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
         const S* __restrict__ Pb = L + mech::L_P;
         const int e1 = mech::SP_OFF[k + 1];
         for (int e = mech::SP_OFF[k]; e < e1; e += 4) {
+            // one round of independent table loads per four entries (slot,
+            // coefficient and slot species packed per entry), then the partials
+            unsigned w[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) w[u][q] = (unsigned)mech::SP_JPACK[3 * (e + u) + q];
             int j[4], ms[4][NSLOT];
             double nu[4];
             S P[4][NSLOT + 1];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                j[u] = mech::SP_RX[e + u];
-                nu[u] = (double)mech::SP_NU[e + u];
+                j[u] = (int)(w[u][0] & 0xffffu);
+                nu[u] = (double)(signed char)(w[u][0] >> 16);
 #pragma unroll
-                for (int s = 0; s < NSLOT; ++s) ms[u][s] = mech::RX_SP[j[u] * NSLOT + s];
+                for (int s = 0; s < NSLOT; ++s) ms[u][s] = (int)((w[u][1 + s / 4] >> (8 * (s % 4))) & 255u) - 1;
 #pragma unroll
                 for (int s = 0; s <= NSLOT; ++s) P[u][s] = Pb[j[u] * PW + s];
             }
@@ -464,12 +471,21 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
     // the efficiencies by scalar loads at an opaque offset, so they are loaded
     // here, one reaction at a time, not hoisted out of the substep loop
     mech::cdbl* EF = (mech::cdbl*)&mech::EFF[0] + z;
-#pragma unroll 1
-    for (int t = 0; t < mech::NTB; ++t) {
-        const S d = (sp ? mech::NU_TB[k * mech::NTB + t] : 0.0) * L[mech::L_P + mech::TB_SLOT[t] * PW + NSLOT + 1];
-        mech::cdbl* eff = EF + t * NS;
+    // the lane's coefficients in all of them: one load per eight reactions,
+    // ahead of the loop (4-bit fields, coefficient + 8)
+    unsigned tbw[mech::NTBW];
 #pragma unroll
-        for (int m = 0; m < NS; ++m) R[m] = fma(eff[m], d, R[m]);
+    for (int q = 0; q < mech::NTBW; ++q) tbw[q] = sp ? (unsigned)mech::NU_TB4[k * mech::NTBW + q] : 0x88888888u;
+#pragma unroll
+    for (int q = 0; q < mech::NTBW; ++q) {
+#pragma unroll 1
+        for (int t = 8 * q; t < mech::NTB && t < 8 * q + 8; ++t) {
+            const double nut = (double)((int)((tbw[q] >> (4 * (t - 8 * q))) & 15u) - 8);
+            const S d = nut * L[mech::L_P + mech::TB_SLOT[t] * PW + NSLOT + 1];
+            mech::cdbl* eff = EF + t * NS;
+#pragma unroll
+            for (int m = 0; m < NS; ++m) R[m] = fma(eff[m], d, R[m]);
+        }
     }
     lds_sync();
     if (sp) {
@@ -554,16 +570,23 @@ __device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, doubl
 #pragma unroll
             for (int j = k; j < N; ++j) A[j] = gather(A[j], src);
         }
-        // the pivot row through LDS: one lane writes it, every lane reads it
-        if (i == k) {
-#pragma unroll
-            for (int j = k; j < N; ++j) PR[j] = A[j];
-        }
-        lds_sync();
+        // the pivot row: with one cell per wave read straight from the pivot
+        // lane into scalar registers; otherwise through LDS (one lane writes
+        // it, every lane of the group reads it)
         double prow[N];
+        if constexpr (G == 64) {
 #pragma unroll
-        for (int j = k; j < N; ++j) prow[j] = PR[j];
-        lds_sync();
+            for (int j = k; j < N; ++j) prow[j] = bcast(A[j], k);
+        } else {
+            if (i == k) {
+#pragma unroll
+                for (int j = k; j < N; ++j) PR[j] = A[j];
+            }
+            lds_sync();
+#pragma unroll
+            for (int j = k; j < N; ++j) prow[j] = PR[j];
+            lds_sync();
+        }
         const double rp = 1.0 / prow[k];
         if (i == k) {
             A[k] = rp;
