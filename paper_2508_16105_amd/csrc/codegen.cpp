@@ -627,21 +627,15 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
         for (size_t i = 0; i < v.size(); ++i) o << lit(v[i]) << (i + 1 < v.size() ? ", " : "");
         o << "};\n";
     };
-    std::vector<int> orig, kind, dnu, sp, nu;
+    // per slot: original index; species of the MAXT reactant then MAXT product
+    // slots (-1: unused)
+    std::vector<int> orig, sp;
     std::vector<double> low, troe, eff;
     for (int s = 0; s < nr; ++s) {
         const auto& r = m.reactions[order[s]];
         orig.push_back(order[s]);
-        kind.push_back((int)r.kind);
-        dnu.push_back(r.dnu);
-        for (int t = 0; t < w.maxt; ++t) {
-            sp.push_back(t < (int)r.reac.size() ? r.reac[t].sp : -1);
-            nu.push_back(t < (int)r.reac.size() ? r.reac[t].nu : 0);
-        }
-        for (int t = 0; t < w.maxt; ++t) {
-            sp.push_back(t < (int)r.prod.size() ? r.prod[t].sp : -1);
-            nu.push_back(t < (int)r.prod.size() ? r.prod[t].nu : 0);
-        }
+        for (int t = 0; t < w.maxt; ++t) sp.push_back(t < (int)r.reac.size() ? r.reac[t].sp : -1);
+        for (int t = 0; t < w.maxt; ++t) sp.push_back(t < (int)r.prod.size() ? r.prod[t].sp : -1);
         low.insert(low.end(), {r.lnA0, r.b0, r.EaR0});
         const bool tr = r.kind == RxnKind::Troe;
         troe.insert(troe.end(), {tr ? 1.0 - r.alpha : 0.0, tr ? r.alpha : 0.0, tr ? 1.0 / r.T3 : 0.0,
@@ -677,20 +671,14 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
              "// kind | (dnu + 4) << 2 | (EFF row + 1) << 5 | original index << 16\n";
         ints("RX_PACK", pack);
     }
-    o << "// reactions in evaluation order (slot s): original index, kind (0 elementary,\n"
-         "// 1 third-body, 2 Lindemann, 3 Troe), sum nu'' - sum nu', species and\n"
-         "// coefficients of the MAXT reactant then MAXT product slots (-1: unused)\n";
+    o << "// reactions in evaluation order (slot s): original index (kind, species\n"
+         "// slots and coefficients are in RX_PACK)\n";
     ints("RX_ORIG", orig);
-    ints("RX_KIND", kind);
-    ints("RX_DNU", dnu);
-    ints("RX_SP", sp);
-    ints("RX_NU", nu);
     o << "// low-pressure limit (ln A0 SI, b0, Ea0/R); Troe: 1-alpha, alpha, 1/T***,\n"
          "// 1/T*, T**, -(1-alpha)/T***, -alpha/T*, [T** given]\n";
     dbls("RX_LOW", low);
     dbls("RX_TROE", troe);
     o << "// third-body efficiencies, one dense row per non-elementary reaction\n";
-    ints("RX_EFFROW", effrow);
     dbls("EFF", eff);
     // species -> reactions that change it (slot, net coefficient)
     std::vector<int> off(1, 0), srx, snu;
