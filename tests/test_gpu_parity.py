@@ -63,6 +63,37 @@ def test_source_terms_and_jacobian_match_oracle(chem, mechs, dev, name):
         assert np.all(np.abs(J[i] - Jo) <= 1e-10 * (np.abs(Jo) + sc)), (name, i)
 
 
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_source_terms_at_the_thermo_range_ends(chem, mechs, dev, name):
+    """States at the ends of the NASA-7 range (200-230 K, 4500-6000 K) and
+    from 0.1 to 100 atm, where the rate exponentials reach their largest
+    arguments: source terms and Jacobian against the oracle (finite results
+    agree to the same bar; a non-finite oracle result is non-finite here)."""
+    gm, om = mechs[name]
+    _, _, Y = uniform_cells(mech_text(name), 64, 24)
+    rng = np.random.default_rng(25)
+    T = np.concatenate([rng.uniform(200.0, 230.0, 32), rng.uniform(4500.0, 6000.0, 32)])
+    p = 101325.0 * np.exp(rng.uniform(np.log(0.1), np.log(100.0), 64))
+    f, J = chem.eval_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev))
+    f, J = f.cpu().numpy(), J.cpu().numpy()
+    checked = 0
+    for i in range(len(T)):
+        y = np.concatenate([[T[i]], Y[i]])
+        fo = om.rhs(p[i], y)
+        if not np.all(np.isfinite(fo)):
+            assert not np.all(np.isfinite(f[i])), i
+            continue
+        assert np.all(np.abs(f[i] - fo) <= 1e-11 * np.abs(fo).max() + 1e-300), (i, T[i], f[i], fo)
+        Jo = om.jac_cs(p[i], y)
+        Ja = om.jac(p[i], y)
+        sc = np.abs(Jo).max(axis=1, keepdims=True) * np.maximum(np.abs(y), 1e-3)[None, :] \
+            / np.maximum(np.abs(y), 1e-3).max()
+        tol = 1e-10 * (np.abs(Jo) + sc) + 4.0 * np.abs(Ja - Jo)
+        assert np.all(np.abs(J[i] - Jo) <= tol), (name, i, T[i])
+        checked += 1
+    assert checked >= 48
+
+
 def test_fixed_step_matches_oracle(chem, mechs, dev):
     gm, om = mechs["m9"]
     T, p, Y = uniform_cells(mech_text("m9"), 128, 22)
