@@ -209,13 +209,12 @@ struct Emitter {
         return s;
     }
 
-    // mode 0: source terms; 1: source terms and Jacobian; 2: parameter
-    // products; 3: production rates, the Jacobian-transpose product J^T w and
-    // the parameter products
+    // mode 0: source terms; 1: source terms and Jacobian; 3: production rates,
+    // the Jacobian-transpose product J^T w and the parameter products
     void reaction(int j, int mode)
     {
         const bool jtv = mode == 3;
-        const bool jac = mode == 1 || jtv, vjp = mode == 2 || jtv;
+        const bool jac = mode == 1 || jtv;
         const auto& r = m.reactions[j];
         o << "  { // reaction " << j << "\n";
         // ln k = ln A + b ln T - (Ea/R) / T, one scalar operand per instruction
@@ -246,13 +245,13 @@ struct Emitter {
                 o << "    const S e3 = exp(-T * " << lit(1.0 / r.T3) << ");\n"
                      "    const S e1 = exp(-T * " << lit(1.0 / r.T1) << ");\n";
                 o << "    S Fc = " << lit(1.0 - r.alpha) << "*e3 + " << lit(r.alpha) << "*e1;\n";
-                if (jac || vjp)
+                if (jac)
                     o << "    S dFc = " << lit(-(1.0 - r.alpha) / r.T3) << "*e3 + "
                       << lit(-r.alpha / r.T1) << "*e1;\n";
                 if (r.has_T2) {
                     o << "    const S e2 = exp(" << lit(-r.T2) << " * iT);\n"
                          "    Fc += e2;\n";
-                    if (jac || vjp) o << "    dFc += " << lit(r.T2) << "*iT*iT*e2;\n";
+                    if (jac) o << "    dFc += " << lit(r.T2) << "*iT*iT*e2;\n";
                 }
                 o << "    const S logFc = log10(Fc);\n"
                      "    const S tc = -0.4 - 0.67*logFc;\n"
@@ -263,7 +262,7 @@ struct Emitter {
                      "    const S opx2 = 1.0 + tx*tx;\n"
                      "    const S logF = logFc / opx2;\n"
                      "    const S Fb = exp(" << lit(std::log(10.0)) << " * logF);\n";
-                if (jac || vjp) {
+                if (jac) {
                     o << "    const S tg = -logFc * 2.0 * tx / (opx2*opx2);\n"
                          "    const S dF_dPr = floored ? 0.0 : tg * tn / (tden*tden);\n"
                          "    const S dF_dFc = 1.0/opx2 + tg * (-0.67*tn + 1.27*tu) / (tden*tden);\n"
@@ -271,7 +270,7 @@ struct Emitter {
                 }
             } else {
                 o << "    const S Fb = 1.0;\n";
-                if (jac || vjp) o << "    const S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
+                if (jac) o << "    const S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
             }
             o << "    const S ipr1 = 1.0 / (1.0 + Pr);\n"
                  "    const S kf = kinf * Pr * ipr1 * Fb;\n"
@@ -288,24 +287,6 @@ struct Emitter {
         std::vector<int> nu(ns, 0);
         for (auto& t : r.reac) nu[t.sp] -= t.nu;
         for (auto& t : r.prod) nu[t.sp] += t.nu;
-        if (vjp && !jtv) {
-            // w . df/dq_j: species rows W_k nu_kj / rho, temperature row -R T dH_j/RT / (rho cp)
-            std::string ws, sh;
-            for (int k = 0; k < ns; ++k)
-                if (nu[k]) ws += " + " + lit(nu[k]) + "*(MW[" + std::to_string(k) + "]*w[" + std::to_string(1 + k) + "])";
-            for (int k = 0; k < ns; ++k)
-                if (nu[k]) sh += " + " + lit(nu[k]) + "*HRT[" + std::to_string(k) + "]";
-            o << "    const S wsum = (0.0" << ws << ") * irho - w[0] * (" << lit(kRu) << " * T) * (0.0" << sh
-              << ") * rcpinv;\n";
-            // d q / d ln A of the main rate (k_inf for falloff: P_r = k0 [M] / k_inf)
-            if (falloff) o << "    const S qA = q * (Pr * ipr1 - dF_dPr);\n";
-            else o << "    const S qA = q;\n";
-            o << "    const S g = wsum * qA;\n"
-                 "    gA[" << j << "] += g;\n"
-                 "    gb[" << j << "] += g * lnT;\n"
-                 "    gE[" << j << "] += g * (-iT * " << lit(1.0 / kRu) << ");\n  }\n";
-            return;
-        }
         for (int k = 0; k < ns; ++k)
             if (nu[k]) o << "    wd[" << k << "] = fma(" << lit(nu[k]) << ", q, wd[" << k << "]);\n";
         if (jac) {
@@ -364,14 +345,14 @@ struct Emitter {
                           << "] = fma(hs, dq" << mm << ", colH[" << mm << "]);\n";
                 o << "    SwY = fma(wY, sj, SwY); HSa = fma(hs, sj, HSa);\n"
                      "    wYT = fma(wY, dqT, wYT); HwT = fma(hs, dqT, HwT);\n";
-                // parameter products, as in param_vjp
+                // parameter products w . df/dq_j times d q_j / d(ln A, b, Ea)
                 o << "    const S wsum = wY * irho - w[0] * (" << lit(kRu) << " * T) * hs * rcpinv;\n";
                 if (falloff) o << "    const S qA = q * (Pr * ipr1 - dF_dPr);\n";
                 else o << "    const S qA = q;\n";
                 o << "    const S g = wsum * qA;\n"
-                     "    gA[" << j << "] += g;\n"
-                     "    gb[" << j << "] += g * lnT;\n"
-                     "    gE[" << j << "] += g * (-iT * " << lit(1.0 / kRu) << ");\n  }\n";
+                     "    chem_math::param_acc(gA[" << j << "], g);\n"
+                     "    chem_math::param_acc(gb[" << j << "], g * lnT);\n"
+                     "    chem_math::param_acc(gE[" << j << "], g * (-iT * " << lit(1.0 / kRu) << "));\n  }\n";
                 return;
             }
             for (int k = 0; k < ns; ++k) {
@@ -482,15 +463,6 @@ struct Emitter {
         rhs_tail();
         chain_rule();
         o << "}\n\n";
-        // parameter products: g += (df/dtheta)^T w for theta = (ln A, b, Ea [J/mol]) of each reaction
-        o << "template <class S>\n__device__ __forceinline__ void param_vjp(const double* __restrict__ par, double p, "
-             "double ip, const S (&y)[N], const double (&w)[N], S* __restrict__ gA, S* __restrict__ gb, "
-             "S* __restrict__ gE)\n{\n";
-        prologue(false);
-        cp_sum(false);
-        o << "  const S rcpinv = T * sig * ip / cpm;\n";
-        for (int j = 0; j < nr; ++j) reaction(j, 2);
-        o << "}\n\n";
         // v = J(y)^T w and the parameter products in one pass, without forming J:
         // every entry of J is assembled from per-reaction partials, so J^T w
         // needs only per-reaction weights and two column sums (see chain_rule):
@@ -499,9 +471,11 @@ struct Emitter {
         // with colA_m = sum_j wY_j dq_j/dC_m, colH_m = sum_j hs_j dq_j/dC_m (= HJ_m),
         // SwY = sum_j wY_j s_j, HS = sum_j hs_j s_j, wYT = sum_j wY_j dq_j/dT,
         // HwT = sum_j hs_j dq_j/dT, s_j = sum_m dq_j/dC_m C_m.
+        // (the parameter products go to double accumulators; for a dual S only
+        // their tangent is added, see chem_math::param_acc)
         o << "template <class S>\n__device__ __forceinline__ void jtv_param(const double* __restrict__ par, double p, "
-             "double ip, const S (&y)[N], const double (&w)[N], S (&v)[N], S* __restrict__ gA, S* __restrict__ gb, "
-             "S* __restrict__ gE)\n{\n";
+             "double ip, const S (&y)[N], const double (&w)[N], S (&v)[N], double* __restrict__ gA, "
+             "double* __restrict__ gb, double* __restrict__ gE)\n{\n";
         prologue(true);
         cp_sum(true);
         o << "  const S icpm = 1.0 / cpm;\n"

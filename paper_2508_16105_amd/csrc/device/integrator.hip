@@ -620,18 +620,12 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
     }
     // second-order terms at y (J(y) inside M): D_{u_s}[J(y)^T w_s] and the
     // parameter products' derivative, one dual evaluation per stage direction
+    // (the parameter products add only their tangent, see param_acc)
     for (int s = 0; s < Rodas4::S; ++s) {
         Dual yd[N], vd[N];
         for (int k = 0; k < N; ++k) yd[k] = Dual(y[k], u[s][k]);
-        Dual gAd[mech::NR], gbd[mech::NR], gEd[mech::NR];
-        for (int j = 0; j < mech::NR; ++j) { gAd[j] = 0.0; gbd[j] = 0.0; gEd[j] = 0.0; }
-        mech::jtv_param(par, p, ip, yd, w[s], vd, gAd, gbd, gEd);
+        mech::jtv_param(par, p, ip, yd, w[s], vd, gA, gb, gE);
         for (int k = 0; k < N; ++k) yb[k] += vd[k].d;
-        for (int j = 0; j < mech::NR; ++j) {
-            gA[j] += gAd[j].d;
-            gb[j] += gbd[j].d;
-            gE[j] += gEd[j].d;
-        }
     }
     for (int k = 0; k < N; ++k) lam[k] = yb[k];
 }

@@ -106,4 +106,9 @@ __device__ __forceinline__ Dual exp(Dual x)
 __device__ __forceinline__ Dual log(Dual x) { return {::log(x.v), x.d / x.v}; }
 __device__ __forceinline__ Dual log10(Dual x) { return {::log10(x.v), x.d / (x.v * 2.302585092994045684)}; }
 
+// Accumulate a parameter product: the value itself, or for a dual number its
+// derivative along the evaluation's direction (the second-order term).
+__device__ __forceinline__ void param_acc(double& a, double g) { a += g; }
+__device__ __forceinline__ void param_acc(double& a, const Dual& g) { a += g.d; }
+
 }  // namespace chem_math
