@@ -64,10 +64,13 @@ class Mechanism:
         self.ns, self.nr = ns.value, nr.value
         self.n = self.ns + 1
 
-    def __del__(self):
+    def __del__(self, _libmod=_lib):
+        # the module is bound as a default: at interpreter exit the global name
+        # may already be gone, and then the library is left to the process end
         h = getattr(self, "h", None)
-        if h and _lib._lib is not None:
-            _lib._lib.chem_free_mechanism(h)
+        lib = getattr(_libmod, "_lib", None)
+        if h and lib is not None:
+            lib.chem_free_mechanism(h)
             self.h = None
 
     def get_params(self):

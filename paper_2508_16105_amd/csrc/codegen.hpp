@@ -7,7 +7,7 @@
 
 namespace chemmi {
 
-// HIP source of namespace mech { NS, NR, N, rhs(), rhs_jac(), param_vjp() } for
+// HIP source of namespace mech { NS, NR, N, rhs(), rhs_jac(), jtv_param() } for
 // m: straight-line code for the one-cell-per-lane kernels.
 std::string generate_mechanism_source(const MechanismData& m);
 
