@@ -143,9 +143,10 @@ def test_m13_third_body_and_troe_integration(chem, mechs, dev):
     _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, "m13 uniform")
 
 
-def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev):
-    gm, _ = mechs["m9"]
-    T, p, Y, reg = rde_field(mech_text("m9"), 256, 256, 101)
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev, name):
+    gm, _ = mechs[name]
+    T, p, Y, reg = rde_field(mech_text(name), 256, 256, 101)
     Tp, Yp, sp, stp, nap, nrp = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL,
                                                return_counts=True)
     cost = (nap + nrp).contiguous()
@@ -159,13 +160,14 @@ def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev):
         assert sq["accepted"] == sp["accepted"] and sq["cells"] == sp["cells"]
 
 
-def test_batched_fields_match_per_field_plain(chem, mechs, dev, oracle_lib):
-    gm, om = mechs["m9"]
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_batched_fields_match_per_field_plain(chem, mechs, dev, oracle_lib, name):
+    gm, om = mechs[name]
     sizes = [1000, 33, 70001, 1, 4097, 64]
     fields = []
     for i, n in enumerate(sizes):
         from workloads.states import rde_field_n
-        T, p, Y, _ = rde_field_n(mech_text("m9"), n, 500 + i)
+        T, p, Y, _ = rde_field_n(mech_text(name), n, 500 + i)
         fields.append((T, p, Y))
     Ts = [_g(f[0], dev) for f in fields]
     ps = [_g(f[1], dev) for f in fields]
@@ -180,7 +182,7 @@ def test_batched_fields_match_per_field_plain(chem, mechs, dev, oracle_lib):
     for (T, p, Y), Tb, Yb in zip(fields, Ts, Ys):
         idx = rng.choice(len(T), size=min(len(T), 200), replace=False)
         To, Yo, _, _, _ = om.integrate(T[idx], p[idx], Y[idx], DT, RTOL, ATOL)
-        _assert_state_parity(Tb.cpu().numpy()[idx], Yb.cpu().numpy()[idx], To, Yo, "batched")
+        _assert_state_parity(Tb.cpu().numpy()[idx], Yb.cpu().numpy()[idx], To, Yo, f"batched {name}")
 
 
 def test_full_size_rde1m_sampled(chem, mechs, dev):
