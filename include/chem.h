@@ -29,7 +29,9 @@
  *     synchronises the stream before return.
  *   - ncell = 0 is a valid no-op.
  *   - A mechanism handle may be used from several host threads; calls on it
- *     are serialised internally.
+ *     are serialised internally, and the device work of each call is ordered
+ *     after that of the previous call on the handle even when the two use
+ *     different streams (they share the handle's device workspace).
  */
 #ifndef CHEM_H
 #define CHEM_H

@@ -169,6 +169,16 @@ int chem_get_params(const chem_mechanism* m, double* lnA, double* b, double* Ea)
     return CHEM_OK;
 }
 
+namespace {
+// Records the end of a call's work on its stream when the call returns (under
+// the handle's lock), so the next call is ordered after it.
+struct DoneMark {
+    chem_mechanism* m;
+    hipStream_t stream;
+    ~DoneMark() { chemmi::mark_done(m, stream); }
+};
+}  // namespace
+
 int chem_set_params(chem_mechanism* m, const double* lnA, const double* b, const double* Ea)
 {
     if (!m || !lnA || !b || !Ea) return set_error(CHEM_E_INVAL, "null argument");
@@ -196,6 +206,7 @@ int chem_eval_source(const chem_mechanism* mc, int64_t ncell, const double* T, c
     if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {f, "f"}})) return rc;
     if (J && !is_device_ptr(J)) return set_error(CHEM_E_INVAL, "J is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
     DeviceState* d;
     if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
     EvalArgs a{d->par, T, p, Y, (long)ncell, f, J};
@@ -219,6 +230,7 @@ int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, co
                                     {errnorm, "errnorm"}, {ok, "ok"}}))
         return rc;
     std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
     DeviceState* d;
     if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
     FixedStepArgs a{d->par, T, p, Y, (long)ncell, h, ynew, errnorm, rtol, atol, ok};
@@ -244,6 +256,7 @@ int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const dou
     Options o = resolve_options(opt);
     if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
     if (o.form == CHEM_FORM_PERSISTENT) {
         const int32_t* cost = o.cost ? o.cost[0] : nullptr;
         if (cost && !is_device_ptr(cost)) return set_error(CHEM_E_INVAL, "cost[0] is not a device pointer");
@@ -285,6 +298,7 @@ int chem_integrate_batched(const chem_mechanism* mc, int nfield, double* const* 
     }
     if (o.h0) return set_error(CHEM_E_INVAL, "h0 is per field; not supported by the batched call");
     std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
     if (o.form == CHEM_FORM_PLAIN) {
         chem_stats total{};
         for (auto& fv : fields) {
@@ -331,6 +345,7 @@ int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double
     Options o = resolve_options(opt);
     if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
     const int ns = m->data.ns();
     double *Te = T_end, *Ye = Y_end;
     void* own = nullptr;

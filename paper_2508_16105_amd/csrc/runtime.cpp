@@ -101,8 +101,11 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         HIPCHECK(hipMalloc((void**)&d.hist, sizeof(unsigned) * 2 * kCostBuckets), "hipMalloc hist");
         HIPCHECK(hipEventCreate(&d.ev0), "hipEventCreate");
         HIPCHECK(hipEventCreate(&d.ev1), "hipEventCreate");
+        HIPCHECK(hipEventCreateWithFlags(&d.done, hipEventDisableTiming), "hipEventCreate");
         d.par_version = 0;
     }
+    // the previous call's work may still run on another stream
+    if (d.done_recorded) HIPCHECK(hipStreamWaitEvent(stream, d.done, 0), "order after the previous call");
     if (d.par_version != m->params_version) {
         // stream-ordered after earlier work that read the old parameters
         HIPCHECK(hipMemcpyAsync(d.par, m->params.data(), sizeof(double) * m->params.size(),
@@ -113,6 +116,15 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
     }
     *out = &d;
     return 0;
+}
+
+void mark_done(chem_mechanism* m, hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    auto it = m->devices.find(dev);
+    if (it == m->devices.end() || !it->second.done) return;
+    if (hipEventRecord(it->second.done, stream) == hipSuccess) it->second.done_recorded = true;
 }
 
 void release_device_state(chem_mechanism* m)
@@ -129,6 +141,7 @@ void release_device_state(chem_mechanism* m)
             if (p) (void)hipFree(p);
         if (d.ev0) (void)hipEventDestroy(d.ev0);
         if (d.ev1) (void)hipEventDestroy(d.ev1);
+        if (d.done) (void)hipEventDestroy(d.done);
         if (d.module) (void)hipModuleUnload(d.module);
     }
     m->devices.clear();

@@ -176,6 +176,10 @@ struct DeviceState {
     std::map<LaunchConfig, hipGraphExec_t> graphs;
     std::map<int64_t, LaunchConfig> tuned;  // by log2 bucket of the total cell count
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // recorded after every API call's work: the next call's stream waits on
+    // it, so the shared workspace is reused in order even across streams
+    hipEvent_t done = nullptr;
+    bool done_recorded = false;
     size_t lds_per_block = 65536;
     int n = 0;                           // state size ns + 1
     // LDS for the RODAS4 stage vectors u_1..u_5 of every lane of a workgroup
@@ -205,6 +209,8 @@ bool is_device_ptr(const void* p);
 
 // Device state for the current device (module loaded, parameters current).
 int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out);
+// Record the end of an API call's work on `stream` (see DeviceState::done).
+void mark_done(chem_mechanism* m, hipStream_t stream);
 void release_device_state(chem_mechanism* m);
 
 int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,

@@ -160,6 +160,27 @@ def test_persistent_is_bitwise_equal_to_plain(chem, mechs, dev, name):
         assert sq["accepted"] == sp["accepted"] and sq["cells"] == sp["cells"]
 
 
+def test_calls_on_two_streams_are_ordered(chem, mechs, dev):
+    """Two asynchronous persistent calls on one handle from two streams share
+    the handle's device workspace; the second is ordered after the first, so
+    both equal the same calls made one after the other."""
+    gm, _ = mechs["m9"]
+    fields = [rde_field(mech_text("m9"), 256, 256, seed)[:3] for seed in (101, 202)]
+    ref = [chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL,
+                          form=chem.FORM_PERSISTENT)[:2] for T, p, Y in fields]
+    ins = [[_g(x, dev) for x in f] for f in fields]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = []
+    for (T, p, Y), s in zip(ins, streams):
+        with torch.cuda.stream(s):
+            outs.append(chem.integrate(gm, T, p, Y, DT, RTOL, ATOL, form=chem.FORM_PERSISTENT,
+                                       stats=False)[:2])
+    torch.cuda.synchronize()
+    for (Tr, Yr), (To, Yo) in zip(ref, outs):
+        assert torch.equal(Tr, To) and torch.equal(Yr, Yo)
+
+
 @pytest.mark.parametrize("name", ["m9", "m13"])
 def test_batched_fields_match_per_field_plain(chem, mechs, dev, oracle_lib, name):
     gm, om = mechs[name]
