@@ -14,7 +14,8 @@ import numpy as np
 
 HERE = pathlib.Path(__file__).resolve().parent
 LIB = HERE / "liboracle.so"
-SOURCES = [HERE / "oracle.c", HERE / "chem_generic.inc", HERE / "oracle.h"]
+SOURCES = [HERE / "oracle.c", HERE / "chem_generic.inc", HERE / "oracle.h", HERE / "oracle_internal.h",
+           HERE / "count.cpp"]
 
 RODAS4 = 0
 ROS4 = 1
@@ -29,13 +30,19 @@ class Opts(C.Structure):
 
 
 def build(force: bool = True) -> pathlib.Path:
-    """Compile liboracle.so with gcc (plain C11 + OpenMP)."""
+    """Compile liboracle.so: oracle.c with gcc (plain C11 + OpenMP) and the
+    counted instantiation count.cpp with g++, linked into one library."""
     if not force and LIB.exists() and all(LIB.stat().st_mtime >= s.stat().st_mtime for s in SOURCES):
         return LIB
+    import tempfile
     tmp = LIB.with_suffix(".so.tmp")
-    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                    "-fcx-limited-range", "-Wall", "-o", str(tmp), str(HERE / "oracle.c"), "-lm"],
-                   check=True)
+    with tempfile.TemporaryDirectory() as d:
+        co, cc = os.path.join(d, "oracle.o"), os.path.join(d, "count.o")
+        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-fcx-limited-range", "-Wall",
+                        "-c", str(HERE / "oracle.c"), "-o", co], check=True)
+        subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+                        "-c", str(HERE / "count.cpp"), "-o", cc], check=True)
+        subprocess.run(["g++", "-shared", "-fopenmp", "-o", str(tmp), co, cc, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
@@ -71,6 +78,8 @@ def lib():
         L.om_replay.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_double, _dp, C.c_int, _dp, _dp]
         L.om_replay_dir.argtypes = [C.c_void_p, C.c_int, C.c_double, _dp, C.c_int, _dp,
                                     C.c_void_p, C.c_void_p, _dp]
+        L.om_count_step.argtypes = [C.c_void_p, C.c_double, _dp, C.c_double,
+                                    np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
         L.om_adjoint.argtypes = [C.c_void_p, C.c_int, C.c_long, _dp, _dp, _dp, C.c_double,
                                  C.c_double, C.c_double, C.POINTER(Opts), _dp, _dp, _dp, _dp,
                                  _dp, _dp, _dp, C.c_int]
@@ -146,6 +155,18 @@ class Mechanism:
         if rc:
             raise RuntimeError("singular step matrix")
         return yn, e
+
+    def count_step(self, p, y, h):
+        """Counted mode: the arithmetic of one RODAS4 step attempt from y with
+        step h (the mechanism's own parameters), as a dict of add (including
+        subtractions), mul, div, exp and log counts, plus flop = add + mul + div."""
+        out = np.zeros(5, dtype=np.int64)
+        rc = lib().om_count_step(self.h, float(p), np.ascontiguousarray(y, dtype=float), float(h), out)
+        if rc:
+            raise RuntimeError("singular step matrix")
+        d = dict(zip(("add", "mul", "div", "exp", "log"), (int(v) for v in out)))
+        d["flop"] = d["add"] + d["mul"] + d["div"]
+        return d
 
     def integrate(self, T, p, Y, dt, rtol, atol, method=RODAS4, max_substeps=100000,
                   hmin_rel=1e-20, par=None, nthreads=0):

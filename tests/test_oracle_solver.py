@@ -278,3 +278,35 @@ def test_cell_status_codes(oracle_lib):
     assert st[hot] == oracle_lib.CELL_MAXSTEPS and na[hot] + nj[hot] == 1
     Te, Ye, na, nj, st = m.integrate(T[:2], p[:2], Y[:2], 1e-8, 1e-8, 1e-12, hmin_rel=0.5)
     assert st[hot] == oracle_lib.CELL_HMIN
+
+
+def _flops_per_substep_formula(ns, nr, s=6):
+    """The method's algorithmic work per substep attempt used for the roofline:
+    Jacobian 50 nr + 4 n^2, LU (2/3) n^3, per stage a source evaluation
+    40 ns + 30 nr, two triangular solves 2 n^2 and the stage combinations 2 s n."""
+    n = ns + 1
+    return (50 * nr + 4 * n * n) + (2.0 / 3.0) * n**3 + s * (40 * ns + 30 * nr + 2 * n * n + 2 * s * n)
+
+
+@pytest.mark.parametrize("name", ["m9", "m13", "m32"])
+def test_counted_mode(oracle_lib, name):
+    """The oracle's counted instantiation of one RODAS4 step attempt: for m9
+    the source terms are evaluated exactly six times (two exponentials per
+    reaction each time) and the counts do not depend on the state; for every
+    mechanism a plain implementation's flop count is at or above the method's
+    minimal per-substep work (the roofline's figure) and within 3x of it."""
+    om = oracle_lib.Mechanism(mech_path(name))
+    T, p, Y = uniform_cells(mech_text(name), 3, 17)
+    counts = []
+    for i in range(3):
+        y = np.concatenate([[T[i]], Y[i]])
+        c = om.count_step(p[i], y, 1e-9)
+        counts.append(c)
+    nr = om.nr
+    if name == "m9":
+        assert counts[0] == counts[1] == counts[2]
+    f = _flops_per_substep_formula(om.ns, nr)
+    for c in counts:
+        assert f <= c["flop"] <= 3.0 * f, (name, c, f)
+    if name == "m9":
+        assert counts[0]["exp"] == 6 * 2 * nr
