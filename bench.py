@@ -412,6 +412,23 @@ def main():
     }
     if "plain" in results and "persistent" in results:
         line["persistent_over_plain"] = results["plain"]["ms_per_step"] / results["persistent"]["ms_per_step"]
+    if "persistent" in results:
+        # the operator-split coupling: the same persistent step returning the
+        # mean reaction rates wdot and heat release qdot (chem_integrate_source)
+        def source_step():
+            Tw.copy_(T0)
+            Yw.copy_(Y0)
+            return chem.integrate_source(mech, Tw, pg, Yw, w["dt"], w["rtol"], w["atol"],
+                                         form=chem.FORM_PERSISTENT, inplace=True, stats=False)
+        source_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            source_step()
+        torch.cuda.synchronize()
+        sms = 1e3 * (time.perf_counter() - t0) / args.steps
+        line["source_mode"] = {"form": "persistent", "ms_per_step": sms,
+                               "over_integrate": sms / results["persistent"]["ms_per_step"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
     if not args.no_amr:   # the 13-species per-field plain launches (~80 s) only with --amr-only

@@ -156,6 +156,24 @@ int chem_integrate(const chem_mechanism *m, int64_t ncell, double *T, const doub
                    chem_stats *stats, int32_t *cell_status, int32_t *nacc, int32_t *nrej,
                    void *stream);
 
+/* Integrate every cell over [0, dt] as chem_integrate does and return the
+   reaction terms a flow solver adds to its species and energy equations
+   (Appendix A, eqs. (21) and (20)) for an operator-split step: the mean rates
+   over the step,
+     wdot[cell * ns + k] = rho0 (Y_k(dt) - Y_k(0)) / dt      [kg/(m^3 s)]
+     qdot[cell]          = -sum_k h_k(298.15 K) wdot_k         [W/m^3]
+   where rho0 = p Wbar / (R T) of the initial state and h_k(298.15 K) the
+   species' enthalpy from its NASA-7 data (J/kg; zero for the elements'
+   reference species), i.e. the chemical heat release.  Device: T, Y in/out
+   (advanced as by chem_integrate); p in; wdot[ncell * ns], qdot[ncell] out;
+   cell_status[ncell] nullable out.  A failed cell gets NaN in wdot and qdot.
+   opt (form, tolerances of the integration, ...) and stats as for
+   chem_integrate. */
+int chem_integrate_source(const chem_mechanism *m, int64_t ncell, double *T, const double *p,
+                          double *Y, double dt, double rtol, double atol, double *wdot,
+                          double *qdot, const chem_options *opt, chem_stats *stats,
+                          int32_t *cell_status, void *stream);
+
 /* Integrate nfield independent fields (e.g. the cell sets of different mesh
    refinement levels) of sizes ncell[f] in one launch.  T, p, Y are host
    arrays of nfield device pointers.  With CHEM_FORM_PERSISTENT (the default

@@ -15,7 +15,7 @@ import ctypes as C
 from . import _lib
 from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN, ORDER_COST, ORDER_NATURAL
 
-__all__ = ["Mechanism", "integrate", "integrate_batched", "integrate_adjoint", "eval_source",
+__all__ = ["Mechanism", "integrate", "integrate_source", "integrate_batched", "integrate_adjoint", "eval_source",
            "step_fixed", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
            "FORM_PERSISTENT", "ORDER_COST", "ORDER_NATURAL", "version"]
 
@@ -121,6 +121,32 @@ def integrate(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stat
     _lib.check(rc, allow=(-6,) if allow_failed else ())
     out = (T, Y, s.as_dict() if s is not None else None)
     return out + (st, nacc, nrej) if return_counts else out
+
+
+def integrate_source(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stats=True,
+                     inplace=False, return_status=False, stream=None, allow_failed=False, **opts):
+    """Integrate as `integrate` does and return the operator-split reaction
+    terms of the step (chem_integrate_source): (T_end, Y_end, wdot [ncell, ns]
+    in kg/(m^3 s), qdot [ncell] in W/m^3, stats dict or None[, status])."""
+    torch = _torch()
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    if not inplace:
+        T, Y = T.clone(), Y.clone()
+    wdot = torch.empty((n, mech.ns), dtype=torch.float64, device=T.device)
+    qdot = torch.empty(n, dtype=torch.float64, device=T.device)
+    st = torch.empty(n, dtype=torch.int32, device=T.device) if return_status else None
+    s = _lib.Stats() if stats else None
+    if opts.get("cost") is not None and not isinstance(opts["cost"], (list, tuple)):
+        opts["cost"] = [opts["cost"]]
+    o = _options(form=form, **opts)
+    rc = _lib.lib().chem_integrate_source(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt), float(rtol),
+                                          float(atol), _ptr(wdot), _ptr(qdot), C.byref(o),
+                                          C.byref(s) if s is not None else None, _ptr(st), _stream(stream))
+    _lib.check(rc, allow=(-6,) if allow_failed else ())
+    out = (T, Y, wdot, qdot, s.as_dict() if s is not None else None)
+    return out + (st,) if return_status else out
 
 
 def integrate_batched(mech: Mechanism, Ts, ps, Ys, dt, rtol, atol, *, form=FORM_PERSISTENT,

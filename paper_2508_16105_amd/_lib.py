@@ -16,7 +16,8 @@ ORDER_COST, ORDER_NATURAL = 1, 2
 
 EXPORTS = ["chem_load_mechanism", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
            "chem_set_params", "chem_eval_source", "chem_step_fixed", "chem_integrate",
-           "chem_integrate_batched", "chem_integrate_adjoint", "chem_last_error", "chem_version"]
+           "chem_integrate_source", "chem_integrate_batched", "chem_integrate_adjoint",
+           "chem_last_error", "chem_version"]
 
 
 class Options(C.Structure):
@@ -61,6 +62,8 @@ def lib():
         L.chem_step_fixed.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
         L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, C.POINTER(Options),
                                      C.POINTER(Stats), vp, vp, vp, vp]
+        L.chem_integrate_source.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, C.POINTER(Options),
+                                            C.POINTER(Stats), vp, vp]
         L.chem_integrate_batched.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, dbl,
                                              C.POINTER(Options), C.POINTER(Stats), vp]
         L.chem_integrate_adjoint.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp,

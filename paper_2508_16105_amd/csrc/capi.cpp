@@ -267,6 +267,27 @@ int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const dou
                      (hipStream_t)stream);
 }
 
+int chem_integrate_source(const chem_mechanism* mc, int64_t ncell, double* T, const double* p, double* Y,
+                          double dt, double rtol, double atol, double* wdot, double* qdot,
+                          const chem_options* opt, chem_stats* stats, int32_t* cell_status, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {wdot, "wdot"}, {qdot, "qdot"}})) return rc;
+    if (cell_status && !is_device_ptr(cell_status)) return set_error(CHEM_E_INVAL, "cell_status is not a device pointer");
+    Options o = resolve_options(opt);
+    if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
+    if (o.form == CHEM_FORM_PERSISTENT && o.cost && o.cost[0] && !is_device_ptr(o.cost[0]))
+        return set_error(CHEM_E_INVAL, "cost[0] is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
+    return run_source(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, wdot, qdot, (hipStream_t)stream);
+}
+
 int chem_integrate_batched(const chem_mechanism* mc, int nfield, double* const* T,
                            const double* const* p, double* const* Y, const int64_t* ncell, double dt,
                            double rtol, double atol, const chem_options* opt, chem_stats* stats,

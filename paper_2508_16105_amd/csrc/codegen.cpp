@@ -85,6 +85,17 @@ struct Emitter {
                 const double W = m.species[k].W;
                 o << lit(t == 0 ? W : (t == 1 ? 1.0 / W : kRu / W)) << ((t == 2 && k == ns - 1) ? "};\n" : ", ");
             }
+        // species enthalpy at 298.15 K (J/kg, the NASA-7 set the kernels choose
+        // there): the chemical enthalpy whose release the coupled energy equation sees
+        o << "__constant__ double HF298[NS] = {";
+        for (int k = 0; k < ns; ++k) {
+            const auto& sp = m.species[k];
+            const double T = 298.15;
+            const double* a = T < sp.tmid ? sp.lo : sp.hi;
+            const double hrt = a[0] + a[1] * T / 2 + a[2] * T * T / 3 + a[3] * T * T * T / 4 +
+                               a[4] * T * T * T * T / 5 + a[5] / T;
+            o << lit(kRu * T * hrt / sp.W) << (k + 1 < ns ? ", " : "};\n");
+        }
         o << "__constant__ double THERMO[NS][2][20] = {\n";
         for (int k = 0; k < ns; ++k) {
             o << "  {";
@@ -443,7 +454,8 @@ struct Emitter {
           << "namespace mech {\n"
           << "constexpr int NS = " << ns << ";\n"
           << "constexpr int NR = " << nr << ";\n"
-          << "constexpr int N = NS + 1;\n\n";
+          << "constexpr int N = NS + 1;\n"
+          << "constexpr double RU = " << lit(kRu) << ";\n\n";
         // source terms only
         thermo_table();
         o << "template <class S>\n__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, "

@@ -202,3 +202,50 @@ extern "C" __global__ void __launch_bounds__(256) chem_reduce_params(const doubl
         else gE[q - 2 * nr] = s[0];
     }
 }
+
+
+// ---- operator-split source terms (the coupling to the flow equations) ----
+// The flow solver's species and energy equations (Appendix A, eqs. (20)-(21))
+// take the reaction terms of the split chemistry step as the mean rates over
+// the step: wdot_k = rho0 (Y_k(dt) - Y_k(0)) / dt and qdot = -sum_k h_k(298.15 K)
+// wdot_k, with rho0 the density of the initial state.  Around an integration:
+// chem_source_begin keeps Y(0) in wdot and rho0 in qdot; chem_source_end turns
+// them into the rates (NaN for a cell whose integration failed).
+struct SourceArgs {
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double dt;
+    const int* status;
+    double* wdot;   // [ncell][NS]
+    double* qdot;   // [ncell]
+};
+
+extern "C" __global__ void __launch_bounds__(256) chem_source_begin(SourceArgs a)
+{
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    double sig = 0.0;
+    for (int k = 0; k < mech::NS; ++k) {
+        const double y = a.Y[c * mech::NS + k];
+        sig = fma(y, mech::MWTAB[mech::NS + k], sig);
+        a.wdot[c * mech::NS + k] = y;
+    }
+    a.qdot[c] = a.p[c] / (mech::RU * a.T[c] * sig);
+}
+
+extern "C" __global__ void __launch_bounds__(256) chem_source_end(SourceArgs a)
+{
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.ncell) return;
+    const bool ok = a.status[c] == chem::CELL_OK;
+    const double r = a.qdot[c] / a.dt;
+    double q = 0.0;
+    for (int k = 0; k < mech::NS; ++k) {
+        const double w = r * (a.Y[c * mech::NS + k] - a.wdot[c * mech::NS + k]);
+        a.wdot[c * mech::NS + k] = ok ? w : __builtin_nan("");
+        q = fma(-mech::HF298[k], w, q);
+    }
+    a.qdot[c] = ok ? q : __builtin_nan("");
+}

@@ -87,6 +87,8 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_reset_heads", &d.f_reset);
         rc = rc ? rc : load_function(d.module, "chem_adjoint", &d.f_adjoint);
         rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
+        rc = rc ? rc : load_function(d.module, "chem_source_begin", &d.f_src_begin);
+        rc = rc ? rc : load_function(d.module, "chem_source_end", &d.f_src_end);
         if (!m->wide) {   // one-cell-per-lane module only
             rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
             rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
@@ -525,6 +527,33 @@ struct Scratch {
 };
 
 }  // namespace
+
+int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+               double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
+               double* wdot, double* qdot, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    // the status buffer of the integration (the caller's, else the workspace's
+    // first ncell entries, sized now so the integration does not move it)
+    if (int rc = grow(&d->cells_i32, &d->cells_cap, 3 * (size_t)ncell, "workspace")) return rc;
+    int32_t* st = status ? status : d->cells_i32;
+    struct {
+        const double* T; const double* p; const double* Y; long ncell; double dt; const int* status;
+        double* wdot; double* qdot;
+    } a{T, p, Y, (long)ncell, dt, st, wdot, qdot};
+    if (int rc = launch_1d(d->f_src_begin, ncell, 256, &a, sizeof a, stream, "chem_source_begin")) return rc;
+    int rc;
+    if (o.form == CHEM_FORM_PERSISTENT) {
+        FieldView fv{T, p, Y, ncell, st, nullptr, nullptr, o.h0, o.cost ? o.cost[0] : nullptr};
+        rc = run_persistent(m, &fv, 1, dt, rtol, atol, o, stats, stream);
+    } else {
+        rc = run_plain(m, ncell, T, p, Y, dt, rtol, atol, o, stats, st, nullptr, nullptr, stream);
+    }
+    if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+    if (int rc2 = launch_1d(d->f_src_end, ncell, 256, &a, sizeof a, stream, "chem_source_end")) return rc2;
+    return rc;
+}
 
 int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double* p, const double* Y0,
                 double dt, double rtol, double atol, const double* gT, const double* gY, double* gT0,

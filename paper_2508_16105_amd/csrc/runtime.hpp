@@ -156,7 +156,7 @@ struct DeviceState {
     hipFunction_t f_plain = nullptr, f_eval = nullptr, f_fixed = nullptr, f_zero = nullptr,
                   f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr,
                   f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr, f_adjoint = nullptr,
-                  f_rparams = nullptr;
+                  f_rparams = nullptr, f_src_begin = nullptr, f_src_end = nullptr;
     double* par = nullptr;               // 3 * nr device doubles
     uint64_t par_version = 0;
     unsigned long long* stats = nullptr; // 4 counters
@@ -222,6 +222,13 @@ int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, doub
 
 int run_persistent(chem_mechanism* m, const FieldView* fields, int nfield, double dt, double rtol,
                    double atol, const Options& o, chem_stats* stats, hipStream_t stream);
+
+// Integration with the operator-split source terms (see chem_integrate_source):
+// the initial density and state are kept in wdot/qdot, the cells integrated in
+// the form o asks for, and the mean rates over the step written back.
+int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+               double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
+               double* wdot, double* qdot, hipStream_t stream);
 
 // Discrete adjoint (see chem_integrate_adjoint); the arrays are as there, with
 // T_end/Y_end non-null.

@@ -288,3 +288,59 @@ def test_h0_option(chem, mechs, dev):
     # a different step sequence: agreement at the tolerance level, not bitwise
     assert np.all(np.abs(Tg.cpu().numpy() - To) <= 1e-6 * To)
     assert np.all(np.abs(Yg.cpu().numpy() - Yo) <= 1e-7)
+
+
+RU = 8.314462618
+
+
+def _source_terms(om, T, p, Y, Tend, Yend, dt):
+    """The operator-split reaction terms of a step from its two end states
+    (eqs. (20)-(21)): wdot = rho0 (Y_end - Y_0)/dt, qdot = -sum h_k(298.15 K) wdot_k."""
+    W = om.weights()
+    rho0 = p / (RU * T * (Y / W).sum(axis=1))
+    wdot = rho0[:, None] * (Yend - Y) / dt
+    _, hrt, _ = om.thermo(298.15)
+    hf = RU * 298.15 * hrt / W
+    return wdot, -(wdot * hf).sum(axis=1), rho0
+
+
+@pytest.mark.parametrize("name,form", [("m9", "plain"), ("m9", "persistent"), ("m13", "plain")])
+def test_source_mode_matches_integrate_and_oracle(chem, mechs, dev, name, form):
+    """chem_integrate_source: the state it leaves equals chem_integrate's
+    (bitwise); its rates equal those formed from its own end state (to
+    round-off, which pins rho0, the difference and h(298.15 K)); and against
+    the oracle's end state they agree to the parity bar carried through the
+    formulas (|dY| <= 1e-8 gives |d wdot| <= rho0 1e-8 / dt)."""
+    gm, om = mechs[name]
+    f = chem.FORM_PERSISTENT if form == "persistent" else chem.FORM_PLAIN
+    T, p, Y, reg = rde_field(mech_text(name), 64, 64, 105)
+    Tg, Yg, wg, qg, stats, st = chem.integrate_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL,
+                                                       form=f, return_status=True)
+    Ti, Yi, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT, RTOL, ATOL, form=f)
+    assert torch.equal(Tg, Ti) and torch.equal(Yg, Yi)
+    assert stats["failed"] == 0 and np.all(st.cpu().numpy() == 0)
+    wg, qg = wg.cpu().numpy(), qg.cpu().numpy()
+    ws, qs, rho0 = _source_terms(om, T, p, Y, Tg.cpu().numpy(), Yg.cpu().numpy(), DT)
+    _, hrt, _ = om.thermo(298.15)
+    hf = RU * 298.15 * hrt / om.weights()
+    assert np.all(np.abs(wg - ws) <= 1e-12 * np.abs(ws) + 1e-300)
+    assert np.all(np.abs(qg - qs) <= 1e-12 * np.abs(ws * hf).sum(axis=1) + 1e-300)
+    To, Yo, _, _, sto = om.integrate(T, p, Y, DT, RTOL, ATOL)
+    assert np.all(sto == 0)
+    wo, qo, _ = _source_terms(om, T, p, Y, To, Yo, DT)
+    bar = rho0 * 1e-8 / DT
+    assert np.all(np.abs(wg - wo) <= 1.01 * bar[:, None])
+    assert np.all(np.abs(qg - qo) <= 1.01 * bar * np.abs(hf).sum())
+
+
+def test_source_mode_failed_cells_are_nan(chem, mechs, dev):
+    gm, _ = mechs["m9"]
+    T, p, Y = uniform_cells(mech_text("m9"), 8, 26)
+    T[3] = -5.0
+    _, _, wg, qg, stats, st = chem.integrate_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL,
+                                                    return_status=True, allow_failed=True)
+    st, wg, qg = st.cpu().numpy(), wg.cpu().numpy(), qg.cpu().numpy()
+    assert st[3] == 4 and stats["failed"] == 1
+    assert np.all(np.isnan(wg[3])) and np.isnan(qg[3])
+    ok = [i for i in range(8) if i != 3]
+    assert np.all(np.isfinite(wg[ok])) and np.all(np.isfinite(qg[ok]))

@@ -178,3 +178,23 @@ def test_wide_bad_cells_and_limits(chem, mechs, dev):
     with pytest.raises(chem.ChemError) as e:
         chem.step_fixed(gm, _g(T2, dev), _g(p2, dev), _g(Y2, dev), 1e-9)
     assert e.value.code == -8
+
+
+def test_wide_source_mode(chem, mechs, dev):
+    """chem_integrate_source in the wave-cooperative form (32 species): the
+    same end state as chem_integrate, and rates formed from it to round-off."""
+    gm, om = mechs["m32"]
+    T, p, Y, _ = rde_field_n(mech_text("m32"), 3000, 930)
+    Tg, Yg, wg, qg, stats = chem.integrate_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL,
+                                                  form=chem.FORM_PERSISTENT)
+    Ti, Yi, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL,
+                               form=chem.FORM_PERSISTENT)
+    assert torch.equal(Tg, Ti) and torch.equal(Yg, Yi) and stats["failed"] == 0
+    W = om.weights()
+    rho0 = p / (8.314462618 * T * (Y / W).sum(axis=1))
+    ws = rho0[:, None] * (Yg.cpu().numpy() - Y) / 5e-9
+    _, hrt, _ = om.thermo(298.15)
+    hf = 8.314462618 * 298.15 * hrt / W
+    wg, qg = wg.cpu().numpy(), qg.cpu().numpy()
+    assert np.all(np.abs(wg - ws) <= 1e-12 * np.abs(ws) + 1e-300)
+    assert np.all(np.abs(qg + (ws * hf).sum(axis=1)) <= 1e-12 * np.abs(ws * hf).sum(axis=1) + 1e-300)
