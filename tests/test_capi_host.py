@@ -78,4 +78,14 @@ def test_params_roundtrip_and_argument_errors(L):
                             None, None) == 0
     assert L.chem_integrate(None, 10, None, None, None, 1e-8, 1e-8, 1e-12, None, None, None, None,
                             None, None) == -1
+    # the coupled step: the same checks, and host pointers refused before any launch
+    host = np.zeros(10)
+    assert L.chem_integrate_source(h, 10, None, None, None, -1.0, 1e-8, 1e-12, None, None, None, None,
+                                   None, None) == -1
+    assert L.chem_integrate_source(h, 0, None, None, None, 1e-8, 1e-8, 1e-12, None, None, None, None,
+                                   None, None) == 0
+    assert L.chem_integrate_source(h, 10, host.ctypes.data, host.ctypes.data, host.ctypes.data, 1e-8, 1e-8,
+                                   1e-12, host.ctypes.data, host.ctypes.data, None, None, None, None) == -1
+    assert L.chem_integrate_source(None, 10, None, None, None, 1e-8, 1e-8, 1e-12, None, None, None, None,
+                                   None, None) == -1
     L.chem_free_mechanism(h)
