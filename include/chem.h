@@ -106,10 +106,12 @@ typedef struct {
     double kernel_ms;           /* device time of the integration launches */
 } chem_stats;
 
-/* Read and validate a `chemmi-mech 1` file (format: NASA-7 species thermo and
-   reversible reactions; the "reactions and thermo data" of Sec. 2.1), check the
-   element balance of every reaction exactly, convert A from cm-mol-s to SI by
-   (1e-6)^(order-1) and Ea from kJ/mol, and build the device code for it
+/* Read and validate a `chemmi-mech 1` file (format: NASA-7 species thermo;
+   elementary, third-body, Lindemann, Troe, SRI and pressure-tabulated (PLOG)
+   reactions, reversible at k_f / K_c or irreversible; the "reactions and
+   thermo data" of Sec. 2.1), check the element balance of every reaction
+   exactly, convert A from cm-mol-s to SI by (1e-6)^(order-1) and Ea from
+   kJ/mol, and build the device code for it
    (generated mechanism-specific source compiled for gfx950 with hipRTC, with an
    on-disk cache in $CHEM_KERNEL_CACHE or a kcache/ folder beside the library).
    *out is owned by the caller until chem_free_mechanism.  Errors:

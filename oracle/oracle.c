@@ -225,11 +225,22 @@ int om_load(const char *path, omech **out, char *err, int errlen)
             else if (!strcmp(kind, "thirdbody")) { r->type = OMR_THIRDBODY; need = 7; }
             else if (!strcmp(kind, "lindemann")) { r->type = OMR_LINDEMANN; need = 10; }
             else if (!strcmp(kind, "troe")) { r->type = OMR_TROE; need = 14; }
+            else if (!strcmp(kind, "sri")) { r->type = OMR_SRI; need = 15; }
+            else if (!strcmp(kind, "plog")) { r->type = OMR_PLOG; need = 7; }
             else FAIL(OM_E_PARSE, "line %d: unknown reaction kind %s", lineno, kind);
-            int neff = (nt > need && !strncmp(tok[nt - 1], "eff=", 4)) ? 1 : 0;
-            if (nt != need + neff) FAIL(OM_E_PARSE, "line %d: wrong field count", lineno);
-            if (r->type == OMR_ELEMENTARY && neff)
-                FAIL(OM_E_PARSE, "line %d: efficiencies on an elementary reaction", lineno);
+            if (nt < need) FAIL(OM_E_PARSE, "line %d: wrong field count", lineno);
+            /* optional trailing flags: eff=..., plog=..., irrev */
+            char *efft = NULL, *plogt = NULL;
+            for (int i = need; i < nt; ++i) {
+                if (!strncmp(tok[i], "eff=", 4) && !efft) efft = tok[i] + 4;
+                else if (!strncmp(tok[i], "plog=", 5) && !plogt) plogt = tok[i] + 5;
+                else if (!strcmp(tok[i], "irrev") && !r->irrev) r->irrev = 1;
+                else FAIL(OM_E_PARSE, "line %d: unknown field %s", lineno, tok[i]);
+            }
+            if (efft && (r->type == OMR_ELEMENTARY || r->type == OMR_PLOG))
+                FAIL(OM_E_PARSE, "line %d: efficiencies without a third body", lineno);
+            if ((r->type == OMR_PLOG) != (plogt != NULL))
+                FAIL(OM_E_PARSE, "line %d: plog table and plog kind go together", lineno);
             if (parse_side(m, tok[2], r->rsp, r->rnu, &r->nre) ||
                 parse_side(m, tok[3], r->psp, r->pnu, &r->np))
                 FAIL(OM_E_PARSE, "line %d: bad reaction side", lineno);
@@ -239,12 +250,14 @@ int om_load(const char *path, omech **out, char *err, int errlen)
             for (int i = 0; i < r->np; ++i) r->dnu += r->pnu[i];
             double A = atof(tok[4]);
             if (!(A > 0.0)) FAIL(OM_E_INVALID, "line %d: A must be positive", lineno);
-            int ordA = order + (r->type == OMR_THIRDBODY ? 1 : 0);
-            r->lnA = log(A) + (ordA - 1) * log(1e-6);           /* cm^3/mol -> m^3/mol */
+            /* cm^3/mol -> m^3/mol per concentration factor beyond the first; the
+               main rate of a plog reaction is a plain factor on its table */
+            int ordA = r->type == OMR_PLOG ? 1 : order + (r->type == OMR_THIRDBODY ? 1 : 0);
+            r->lnA = log(A) + (ordA - 1) * log(1e-6);
             r->b = atof(tok[5]);
             r->Ea = atof(tok[6]) * 1e3;                           /* kJ/mol -> J/mol */
             for (int k = 0; k < OM_NSMAX; ++k) r->eff[k] = 1.0;
-            if (r->type == OMR_LINDEMANN || r->type == OMR_TROE) {
+            if (r->type == OMR_LINDEMANN || r->type == OMR_TROE || r->type == OMR_SRI) {
                 double A0 = atof(tok[7]);
                 if (!(A0 > 0.0)) FAIL(OM_E_INVALID, "line %d: A0 must be positive", lineno);
                 r->lnA0 = log(A0) + order * log(1e-6);           /* order + 1 - 1 */
@@ -260,8 +273,29 @@ int om_load(const char *path, omech **out, char *err, int errlen)
                 if (!(r->T3 > 0.0 && r->T1 > 0.0))
                     FAIL(OM_E_INVALID, "line %d: Troe T3, T1 must be positive", lineno);
             }
-            if (neff) {
-                for (char *t = strtok(tok[nt - 1] + 4, ","); t; t = strtok(NULL, ",")) {
+            if (r->type == OMR_SRI) {
+                for (int i = 0; i < 5; ++i) r->sri[i] = atof(tok[10 + i]);
+                if (!(r->sri[0] >= 0.0 && r->sri[2] > 0.0 && r->sri[3] > 0.0))
+                    FAIL(OM_E_INVALID, "line %d: SRI needs a >= 0, c > 0, d > 0", lineno);
+            }
+            if (plogt) {
+                for (char *t = strtok(plogt, ","); t; t = strtok(NULL, ",")) {
+                    double v[4];
+                    if (r->nplog >= OM_PLOGMAX) FAIL(OM_E_SIZE, "line %d: too many plog pressures", lineno);
+                    if (sscanf(t, "%lf:%lf:%lf:%lf", &v[0], &v[1], &v[2], &v[3]) != 4)
+                        FAIL(OM_E_PARSE, "line %d: bad plog entry", lineno);
+                    if (!(v[0] > 0.0 && v[1] > 0.0)) FAIL(OM_E_INVALID, "line %d: plog p, A must be positive", lineno);
+                    if (r->nplog && !(v[0] > r->plog_p[r->nplog - 1]))
+                        FAIL(OM_E_INVALID, "line %d: plog pressures must increase", lineno);
+                    r->plog_p[r->nplog] = v[0];
+                    r->plog_lnA[r->nplog] = log(v[1]) + (order - 1) * log(1e-6);
+                    r->plog_b[r->nplog] = v[2];
+                    r->plog_Ea[r->nplog] = v[3] * 1e3;
+                    r->nplog++;
+                }
+            }
+            if (efft) {
+                for (char *t = strtok(efft, ","); t; t = strtok(NULL, ",")) {
                     char *c = strchr(t, ':');
                     if (!c) FAIL(OM_E_PARSE, "line %d: bad efficiency", lineno);
                     *c = 0;

@@ -16,7 +16,9 @@
 #define OM_MAXSIDE 4
 #define OM_NEMAX 16
 
-enum { OMR_ELEMENTARY = 0, OMR_THIRDBODY = 1, OMR_LINDEMANN = 2, OMR_TROE = 3 };
+#define OM_PLOGMAX 16
+
+enum { OMR_ELEMENTARY = 0, OMR_THIRDBODY = 1, OMR_LINDEMANN = 2, OMR_TROE = 3, OMR_SRI = 4, OMR_PLOG = 5 };
 
 typedef struct {
     int type;
@@ -27,6 +29,10 @@ typedef struct {
     double lnA0, b0, Ea0;              /* low-pressure limit */
     double alpha, T3, T1, T2;
     int has_T2;
+    double sri[5];                     /* SRI a, b (K), c (K), d, e */
+    int nplog;                         /* PLOG: pressures (Pa), increasing, and their rates */
+    double plog_p[OM_PLOGMAX], plog_lnA[OM_PLOGMAX], plog_b[OM_PLOGMAX], plog_Ea[OM_PLOGMAX];
+    int irrev;                         /* no reverse reaction */
     double eff[OM_NSMAX];
 } omrxn;
 

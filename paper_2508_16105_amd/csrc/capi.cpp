@@ -133,7 +133,7 @@ int chem_load_mechanism(const char* path, chem_mechanism** out)
         if (m->layout.G == 0)
             return set_error(CHEM_E_UNSUPPORTED, "mechanism outside the wave-cooperative tables (over 3 terms or a "
                                                      "coefficient over 3 on a reaction side, |dnu| over 4, or over "
-                                                     "2046 reactions)");
+                                                     "511 third-body or falloff reactions, or over 511 PLOG reactions)");
         m->wide = true;
         m->source = device_source(generate_wide_source(m->data, m->layout), true);
     }

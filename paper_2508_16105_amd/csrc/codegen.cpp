@@ -210,6 +210,38 @@ struct Emitter {
         o << "  const S lnPRT = " << lit(std::log(kPatm / kRu)) << " - lnT;\n"
              "  S wd[NS];\n"
              "#pragma unroll\n  for (int k = 0; k < NS; ++k) wd[k] = 0.0;\n";
+        for (const auto& r : m.reactions)
+            if (r.kind == RxnKind::Plog) {
+                o << "  const double lnp = log(p);\n";
+                break;
+            }
+    }
+
+    // PLOG: the Arrhenius set at this pressure, linear in ln p between the
+    // tabulated pressures and the end sets outside them (pla, plb, ple).
+    void plog_set(const ReactionData& r)
+    {
+        const auto& e = r.plog;
+        const size_t n = e.size();
+        auto set = [&](size_t i) {
+            return "pla = " + lit(e[i].lnA) + "; plb = " + lit(e[i].b) + "; ple = " + lit(e[i].EaR) + ";";
+        };
+        o << "    double pla, plb, ple;\n";
+        if (n == 1) {
+            o << "    " << set(0) << "\n";
+            return;
+        }
+        o << "    if (!(lnp > " << lit(e[0].lnp) << ")) { " << set(0) << " }\n";
+        for (size_t i = 0; i + 1 < n; ++i) {
+            o << "    else if (lnp < " << lit(e[i + 1].lnp) << ") {\n"
+                 "      const double w = (lnp - " << lit(e[i].lnp) << ") * " << lit(1.0 / (e[i + 1].lnp - e[i].lnp))
+              << ";\n"
+                 "      pla = fma(w, " << lit(e[i + 1].lnA - e[i].lnA) << ", " << lit(e[i].lnA) << ");\n"
+                 "      plb = fma(w, " << lit(e[i + 1].b - e[i].b) << ", " << lit(e[i].b) << ");\n"
+                 "      ple = fma(w, " << lit(e[i + 1].EaR - e[i].EaR) << ", " << lit(e[i].EaR) << ");\n"
+                 "    }\n";
+        }
+        o << "    else { " << set(n - 1) << " }\n";
     }
 
     std::string third_body_sum(const ReactionData& r)
@@ -232,17 +264,22 @@ struct Emitter {
         o << "    S lnk = lnT * P[" << nr + j << "];\n"
              "    lnk = fma(-iT, P[" << 2 * nr + j << "], lnk);\n"
              "    lnk = lnk + P[" << j << "];\n";
+        const bool plog = r.kind == RxnKind::Plog, rev_on = r.reversible;
+        if (plog) {
+            plog_set(r);
+            o << "    lnk = lnk + (lnT * plb - iT * ple + pla);\n";
+        }
         // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
         std::string lnkc;
         for (auto& t : r.prod) lnkc += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
         for (auto& t : r.reac) lnkc += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
         if (r.dnu != 0) lnkc += " + " + lit(r.dnu) + "*lnPRT";
         o << "    const S lnKc = 0.0" << lnkc << ";\n";
-        const bool falloff = r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe;
-        if (r.kind != RxnKind::Elementary) o << "    const S Mc = " << third_body_sum(r) << ";\n";
+        const bool falloff = is_falloff(r.kind);
+        if (r.kind != RxnKind::Elementary && !plog) o << "    const S Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
-            o << "    const S kf = chem_math::exp_poly(lnk);\n"
-                 "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
+            o << "    const S kf = chem_math::exp_poly(lnk);\n";
+            if (rev_on) o << "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
             o << "    const S kinf = chem_math::exp_poly(lnk);\n"
@@ -279,21 +316,41 @@ struct Emitter {
                          "    const S dF_dFc = 1.0/opx2 + tg * (-0.67*tn + 1.27*tu) / (tden*tden);\n"
                          "    const S dlogFc_dT = dFc / (Fc * " << lit(std::log(10.0)) << ");\n";
                 }
+            } else if (r.kind == RxnKind::Sri) {
+                // F = d [a exp(-b/T) + exp(-T/c)]^X T^e with X = 1 / (1 + log10(P_r)^2)
+                const double* c = r.sri;
+                o << "    const S sea = " << (c[0] != 0.0 ? lit(c[0]) + " * chem_math::exp_poly(" + lit(-c[1]) + " * iT)"
+                                                         : std::string("0.0")) << ";\n"
+                     "    const S sec = chem_math::exp_poly(-T * " << lit(1.0 / c[2]) << ");\n"
+                     "    const S sY = sea + sec;\n"
+                     "    const S lnsY = log(sY);\n"
+                     "    const S sX = 1.0 / (1.0 + logPr * logPr);\n"
+                     "    const S Fb = chem_math::exp_poly(sX * lnsY + " << lit(c[4]) << " * lnT + " << lit(std::log(c[3]))
+                  << ");\n";
+                if (jac)
+                    o << "    const S dF_dPr = floored ? 0.0 : lnsY * " << lit(-2.0 / std::log(10.0))
+                      << " * logPr * sX * sX;\n"
+                         "    const S dF_dFc = 0.0, dlogFc_dT = 0.0;\n"
+                         "    const S dlnF_T = sX * (sea * " << lit(c[1]) << " * iT * iT - sec * " << lit(1.0 / c[2])
+                      << ") / sY + " << lit(c[4]) << " * iT;\n";
             } else {
                 o << "    const S Fb = 1.0;\n";
                 if (jac) o << "    const S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
             }
             o << "    const S ipr1 = 1.0 / (1.0 + Pr);\n"
-                 "    const S kf = kinf * Pr * ipr1 * Fb;\n"
-                 "    const S iKc = chem_math::exp_poly(-lnKc);\n"
-                 "    const S kr = kf * iKc;\n";
+                 "    const S kf = kinf * Pr * ipr1 * Fb;\n";
+            if (rev_on)
+                o << "    const S iKc = chem_math::exp_poly(-lnKc);\n"
+                     "    const S kr = kf * iKc;\n";
         }
         o << "    const S pf = " << side_product(r.reac) << ";\n"
-             "    const S pr = " << side_product(r.prod) << ";\n"
-             "    const S fwd = kf * pf;\n"
-             "    const S rev = kr * pr;\n";
-        if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * (fwd - rev);\n";
-        else o << "    const S q = fwd - rev;\n";
+             "    const S fwd = kf * pf;\n";
+        if (rev_on)
+            o << "    const S pr = " << side_product(r.prod) << ";\n"
+                 "    const S rev = kr * pr;\n";
+        const std::string net = rev_on ? "(fwd - rev)" : "fwd";
+        if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * " << net << ";\n";
+        else o << "    const S q = " << (rev_on ? "fwd - rev" : "fwd") << ";\n";
         // production rates
         std::vector<int> nu(ns, 0);
         for (auto& t : r.reac) nu[t.sp] -= t.nu;
@@ -305,35 +362,40 @@ struct Emitter {
             std::string sh;
             for (auto& t : r.prod) sh += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
             for (auto& t : r.reac) sh += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
-            o << "    const S dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
-            o << "    const S dlnkinf = (P[" << nr + j << "] + P[" << 2 * nr + j << "]*iT) * iT;\n";
+            if (rev_on) o << "    const S dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
+            if (plog)
+                o << "    const S dlnkinf = (P[" << nr + j << "] + plb + (P[" << 2 * nr + j << "] + ple)*iT) * iT;\n";
+            else
+                o << "    const S dlnkinf = (P[" << nr + j << "] + P[" << 2 * nr + j << "]*iT) * iT;\n";
             if (!falloff) {
                 o << "    const S dlnkf = dlnkinf;\n";
             } else {
                 o << "    const S dlnk0 = (" << lit(r.b0) << " + " << lit(r.EaR0) << "*iT) * iT;\n"
-                     "    const S dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + "
-                  << lit(std::log(10.0)) << " * dF_dFc * dlogFc_dT;\n"
-                     "    const S dkdM = kinf * r0 * Fb * (ipr1*ipr1 + dF_dPr*ipr1);\n";
+                     "    const S dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + ";
+                if (r.kind == RxnKind::Sri) o << "dlnF_T;\n";
+                else o << lit(std::log(10.0)) << " * dF_dFc * dlogFc_dT;\n";
+                o << "    const S dkdM = kinf * r0 * Fb * (ipr1*ipr1 + dF_dPr*ipr1);\n";
             }
             std::string fac = r.kind == RxnKind::ThirdBody ? "Mc * " : "";
-            o << "    const S dqT = " << fac << "(dlnkf * fwd - (dlnkf - dlnKc) * rev);\n";
+            if (rev_on) o << "    const S dqT = " << fac << "(dlnkf * fwd - (dlnkf - dlnKc) * rev);\n";
+            else o << "    const S dqT = " << fac << "(dlnkf * fwd);\n";
             // d q / d C_m (dense over the species that enter)
             std::vector<std::string> dq(ns);
             for (int mm = 0; mm < ns; ++mm) {
                 std::string t;
                 std::string a = side_product(r.reac, mm);
-                std::string b = side_product(r.prod, mm);
+                std::string b = rev_on ? side_product(r.prod, mm) : std::string();
                 if (!a.empty()) t += "kf*(" + a + ")";
                 if (!b.empty()) t += (t.empty() ? "-" : " - ") + std::string("kr*(") + b + ")";
                 if (!t.empty() && r.kind == RxnKind::ThirdBody) t = "Mc*(" + t + ")";
                 if (r.kind == RxnKind::ThirdBody && r.eff[mm] != 0.0)
-                    t += (t.empty() ? "" : " + ") + lit(r.eff[mm]) + "*(fwd - rev)";
+                    t += (t.empty() ? "" : " + ") + lit(r.eff[mm]) + "*" + net;
                 if (falloff && r.eff[mm] != 0.0)
                     t += (t.empty() ? "" : " + ") + lit(r.eff[mm]) + "*dMterm";
                 dq[mm] = t;
             }
             // k_r = k_f / K_c, so both directions scale with d k_f / d[M]
-            if (falloff) o << "    const S dMterm = dkdM*(pf - iKc*pr);\n";
+            if (falloff) o << "    const S dMterm = dkdM*" << (rev_on ? "(pf - iKc*pr)" : "pf") << ";\n";
             for (int mm = 0; mm < ns; ++mm)
                 if (!dq[mm].empty()) o << "    const S dq" << mm << " = " << dq[mm] << ";\n";
             if (jtv) {
@@ -543,7 +605,12 @@ WideLayout wide_layout(const MechanismData& m)
                 if (t.nu > 3) w.G = 0;
         if (r.dnu < -4 || r.dnu > 3) w.G = 0;
     }
-    if (nr > 2046 || w.G == 0) {
+    int n_eff = 0, n_plog = 0;
+    for (const auto& r : m.reactions) {
+        if (r.kind == RxnKind::Plog) ++n_plog;
+        else if (r.kind != RxnKind::Elementary) ++n_eff;
+    }
+    if (n_eff > 511 || n_plog > 511 || nr > 65535 || w.G == 0) {
         w.G = 0;
         return w;
     }
@@ -592,15 +659,19 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
     // reactions in evaluation order: grouped by kind so a round of lanes mostly
     // takes one branch
     std::vector<int> order;
-    for (int kind = 0; kind < 4; ++kind)
+    for (int kind = 0; kind < 6; ++kind)
         for (int j = 0; j < nr; ++j)
             if ((int)m.reactions[j].kind == kind) order.push_back(j);
     std::vector<int> slot_of(nr);
     for (int s = 0; s < nr; ++s) slot_of[order[s]] = s;
+    // per slot: its EFF row (third body and falloff) or its PLOG table (PLOG)
     std::vector<int> effrow(nr, -1);
-    int neff = 0;
-    for (int s = 0; s < nr; ++s)
-        if (m.reactions[order[s]].kind != RxnKind::Elementary) effrow[s] = neff++;
+    int neff = 0, nplog = 0;
+    for (int s = 0; s < nr; ++s) {
+        const RxnKind k = m.reactions[order[s]].kind;
+        if (k == RxnKind::Plog) effrow[s] = nplog++;
+        else if (k != RxnKind::Elementary) effrow[s] = neff++;
+    }
     auto ints = [&](const char* name, const std::vector<int>& v) {
         o << "__constant__ int " << name << "[" << std::max<size_t>(v.size(), 1) << "] = {";
         if (v.empty()) o << "0";
@@ -616,7 +687,8 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
     // per slot: original index; species of the MAXT reactant then MAXT product
     // slots (-1: unused)
     std::vector<int> orig, sp;
-    std::vector<double> low, troe, eff;
+    std::vector<double> low, troe, eff, plog;
+    std::vector<int> plog_off(1, 0);
     for (int s = 0; s < nr; ++s) {
         const auto& r = m.reactions[order[s]];
         orig.push_back(order[s]);
@@ -624,17 +696,25 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
         for (int t = 0; t < w.maxt; ++t) sp.push_back(t < (int)r.prod.size() ? r.prod[t].sp : -1);
         low.insert(low.end(), {r.lnA0, r.b0, r.EaR0});
         const bool tr = r.kind == RxnKind::Troe;
-        troe.insert(troe.end(), {tr ? 1.0 - r.alpha : 0.0, tr ? r.alpha : 0.0, tr ? 1.0 / r.T3 : 0.0,
-                                 tr ? 1.0 / r.T1 : 0.0, tr && r.has_T2 ? r.T2 : 0.0,
-                                 tr ? -(1.0 - r.alpha) / r.T3 : 0.0, tr ? -r.alpha / r.T1 : 0.0,
-                                 tr && r.has_T2 ? 1.0 : 0.0});
-        if (effrow[s] >= 0)
+        if (r.kind == RxnKind::Sri)
+            troe.insert(troe.end(), {r.sri[0], -r.sri[1], 1.0 / r.sri[2], r.sri[1], std::log(r.sri[3]), r.sri[4],
+                                     0.0, 0.0});
+        else
+            troe.insert(troe.end(), {tr ? 1.0 - r.alpha : 0.0, tr ? r.alpha : 0.0, tr ? 1.0 / r.T3 : 0.0,
+                                     tr ? 1.0 / r.T1 : 0.0, tr && r.has_T2 ? r.T2 : 0.0,
+                                     tr ? -(1.0 - r.alpha) / r.T3 : 0.0, tr ? -r.alpha / r.T1 : 0.0,
+                                     tr && r.has_T2 ? 1.0 : 0.0});
+        if (r.kind == RxnKind::Plog) {
+            for (const auto& e : r.plog) plog.insert(plog.end(), {e.lnp, e.lnA, e.b, e.EaR});
+            plog_off.push_back((int)(plog.size() / 4));
+        } else if (effrow[s] >= 0) {
             for (int k = 0; k < ns; ++k) eff.push_back(r.eff[k]);
+        }
     }
     // packed per slot, for one load per reaction round: species slots (8 bits
     // each: species index + 1 in the low 6 bits, coefficient in the top 2;
-    // 0 = unused) in two words, then kind | (dnu + 4) << 2 | (effrow + 1) << 5 |
-    // orig << 16
+    // 0 = unused) in two words, then kind | irreversible << 3 | (dnu + 4) << 4 |
+    // (EFF row or PLOG table + 1) << 7 | orig << 16
     {
         std::vector<int> pack;
         for (int s = 0; s < nr; ++s) {
@@ -650,20 +730,24 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
             }
             pack.push_back((int)(unsigned)(slots & 0xffffffffull));
             pack.push_back((int)(unsigned)(slots >> 32));
-            pack.push_back((int)((unsigned)r.kind | ((unsigned)(r.dnu + 4) << 2) | ((unsigned)(effrow[s] + 1) << 5) |
-                                 ((unsigned)order[s] << 16)));
+            pack.push_back((int)((unsigned)r.kind | ((r.reversible ? 0u : 1u) << 3) | ((unsigned)(r.dnu + 4) << 4) |
+                                 ((unsigned)(effrow[s] + 1) << 7) | ((unsigned)order[s] << 16)));
         }
         o << "// per slot: species slots (two words, 8 bits each: index + 1 | nu << 6), then\n"
-             "// kind | (dnu + 4) << 2 | (EFF row + 1) << 5 | original index << 16\n";
+             "// kind | irreversible << 3 | (dnu + 4) << 4 | (EFF row or PLOG table + 1) << 7 |\n"
+             "// original index << 16\n";
         ints("RX_PACK", pack);
     }
     o << "// reactions in evaluation order (slot s): original index (kind, species\n"
          "// slots and coefficients are in RX_PACK)\n";
     ints("RX_ORIG", orig);
     o << "// low-pressure limit (ln A0 SI, b0, Ea0/R); Troe: 1-alpha, alpha, 1/T***,\n"
-         "// 1/T*, T**, -(1-alpha)/T***, -alpha/T*, [T** given]\n";
+         "// 1/T*, T**, -(1-alpha)/T***, -alpha/T*, [T** given]; SRI: a, -b, 1/c, b, ln d, e\n";
     dbls("RX_LOW", low);
     dbls("RX_TROE", troe);
+    o << "// PLOG tables: entries RX_PLOG_OFF[t] .. RX_PLOG_OFF[t+1] of (ln p, ln A SI, b, Ea/R)\n";
+    ints("RX_PLOG_OFF", plog_off);
+    dbls("RX_PLOG", plog);
     o << "// third-body efficiencies, one dense row per non-elementary reaction\n";
     dbls("EFF", eff);
     // species -> reactions that change it (slot, net coefficient)
@@ -709,12 +793,13 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
         o << "// per SP entry: slot | (net coefficient & 255) << 16, slot species 0-3, 4-5 (bytes, index + 1)\n";
         ints("SP_JPACK", jp);
     }
-    // non-elementary reactions t: their slot, and the net coefficient of every
-    // species in them (the dense third-body part of the Jacobian rows)
+    // third-body and falloff reactions t (EFF row t): their slot, and the net
+    // coefficient of every species in them (the dense third-body part of the
+    // Jacobian rows)
     std::vector<int> tbslot;
     std::vector<double> nutb;
     for (int s = 0; s < nr; ++s)
-        if (effrow[s] >= 0) tbslot.push_back(s);
+        if (effrow[s] >= 0 && m.reactions[order[s]].kind != RxnKind::Plog) tbslot.push_back(s);
     for (int k = 0; k < ns; ++k)
         for (int s : tbslot) {
             const auto& r = m.reactions[order[s]];
@@ -724,7 +809,9 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
             nutb.push_back((double)v);
         }
     o << "constexpr int NTB = " << tbslot.size() << ";\n"
-         "// non-elementary reaction t: its slot (EFF row t); the net coefficient of\n"
+         "static_assert(NTB == 0 || sizeof(EFF) == sizeof(double) * NTB * NS, \"one EFF row per third-body "
+         "reaction\");\n"
+         "// third-body or falloff reaction t: its slot (EFF row t); the net coefficient of\n"
          "// species k in it as a 4-bit field (coefficient + 8), eight per word:\n"
          "// NU_TB4[k * NTBW + t / 8] >> (4 (t % 8))\n";
     ints("TB_SLOT", tbslot);

@@ -162,18 +162,42 @@ enum : int { F_ONLY = 0, F_JAC = 1, PARAM_VJP = 2 };
 template <class S, int MODE>
 __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const double* __restrict__ par,
                                          S* __restrict__ L, S T, S lnT, S iT, S lnPRT, S ctot, S irho, S rcpinv,
-                                         S* __restrict__ g)
+                                         double p, S* __restrict__ g)
 {
     constexpr bool JAC = MODE == F_JAC;
     // the slot's packed table entry (loaded by the caller ahead of time)
-    const int kind = (int)(pk[2] & 3u);
-    const int dnu = (int)((pk[2] >> 2) & 7u) - 4;
-    const int er = (int)((pk[2] >> 5) & 2047u) - 1;
+    // kind: 0 elementary, 1 third body, 2 Lindemann, 3 Troe, 4 SRI, 5 PLOG
+    const int kind = (int)(pk[2] & 7u);
+    const bool irrev = (pk[2] >> 3) & 1u;
+    const int dnu = (int)((pk[2] >> 4) & 7u) - 4;
+    const int er = (int)((pk[2] >> 7) & 511u) - 1;   // EFF row, or PLOG table for kind 5
     const int oj = (int)(pk[2] >> 16);
-    const double pb = par[NR + oj], pe = par[2 * NR + oj];
+    double pb = par[NR + oj], pe = par[2 * NR + oj];
     S lnk = lnT * pb;
     lnk = fma(-iT, pe, lnk);
     lnk = lnk + par[oj];
+    if (kind == 5) {
+        // the Arrhenius set at this pressure: linear in ln p between the
+        // tabulated pressures, the end sets outside them
+        const double lnp = log(p);
+        const int e0 = mech::RX_PLOG_OFF[er], e1 = mech::RX_PLOG_OFF[er + 1] - 1;
+        const double* E = mech::RX_PLOG;
+        int e = e0;
+        double w = 0.0;
+        if (lnp >= E[4 * e1]) {
+            e = e1;
+        } else if (lnp > E[4 * e0]) {
+            while (e + 1 < e1 && lnp >= E[4 * (e + 1)]) ++e;
+            w = (lnp - E[4 * e]) / (E[4 * (e + 1)] - E[4 * e]);
+        }
+        const int e2 = e < e1 ? e + 1 : e;
+        const double pla = fma(w, E[4 * e2 + 1] - E[4 * e + 1], E[4 * e + 1]);
+        const double plb = fma(w, E[4 * e2 + 2] - E[4 * e + 2], E[4 * e + 2]);
+        const double ple = fma(w, E[4 * e2 + 3] - E[4 * e + 3], E[4 * e + 3]);
+        lnk = lnk + (lnT * plb - iT * ple + pla);
+        pb += plb;
+        pe += ple;
+    }
     int sp[NSLOT], nu[NSLOT];
     S c[NSLOT];
     S lnKc = 0.0, dH = 0.0, ws = 0.0;
@@ -193,14 +217,14 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     }
     lnKc = fma((double)dnu, lnPRT, lnKc);
     S Mc = ctot;
-    if (er >= 0) {
+    if (er >= 0 && kind != 5) {
         for (int m = 0; m < NS; ++m) Mc = fma(mech::EFF[er * NS + m] - 1.0, L[mech::L_C + m], Mc);
     }
     S kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0, Pr = 0.0;
-    S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;
-    if (kind < 2) {
+    S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0, dlnF_T = 0.0;
+    if (kind < 2 || kind == 5) {
         kf = chem_math::exp_poly(lnk);
-        kr = chem_math::exp_poly(lnk - lnKc);
+        kr = irrev ? S(0.0) : chem_math::exp_poly(lnk - lnKc);
     } else {
         // P_r = k0 [M] / k_inf, one exponential for the ratio
         const double* lo = &mech::RX_LOW[j * 3];
@@ -235,11 +259,26 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
                 dF_dPr = floored ? S(0.0) : tg * tn / (tden * tden);
                 dF_dFc = 1.0 / opx2 + tg * (-0.67 * tn + 1.27 * tu) / (tden * tden);
                 dlogFc_dT = dFc / (Fc * mech::LN10);
+                dlnF_T = mech::LN10 * dF_dFc * dlogFc_dT;
+            }
+        } else if (kind == 4) {
+            // SRI: F = d [a exp(-b/T) + exp(-T/c)]^X T^e, X = 1 / (1 + log10(P_r)^2);
+            // row: a, -b, 1/c, b, ln d, e
+            const double* sr = &mech::RX_TROE[j * 8];
+            const S sea = sr[0] * chem_math::exp_poly(sr[1] * iT);
+            const S sec = chem_math::exp_poly(-T * sr[2]);
+            const S sY = sea + sec;
+            const S lnsY = log(sY);
+            const S sX = 1.0 / (1.0 + logPr * logPr);
+            Fb = chem_math::exp_poly(sX * lnsY + sr[5] * lnT + sr[4]);
+            if (MODE != F_ONLY) {
+                dF_dPr = floored ? S(0.0) : lnsY * (-2.0 / mech::LN10) * logPr * sX * sX;
+                dlnF_T = sX * (sea * sr[3] * iT * iT - sec * sr[2]) / sY + sr[5] * iT;
             }
         }
         ipr1 = 1.0 / (1.0 + Pr);
         kf = kinf * Pr * ipr1 * Fb;
-        iKc = chem_math::exp_poly(-lnKc);
+        iKc = irrev ? S(0.0) : chem_math::exp_poly(-lnKc);
         kr = kf * iKc;
     }
     S pf = 1.0, pr = 1.0;
@@ -257,7 +296,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
         // -R T (sum nu H/RT) / (rho c_p); d q / d ln A of the main rate (k_inf
         // for falloff, through P_r = k0 [M] / k_inf)
         const S wsum = ws * irho - L[mech::L_W] * (mech::RU * T) * dH * rcpinv;
-        const S qA = kind >= 2 ? q * (Pr * ipr1 - dF_dPr) : q;
+        const S qA = (kind >= 2 && kind <= 4) ? q * (Pr * ipr1 - dF_dPr) : q;
         const S gq = wsum * qA;
         g[0] += gq;
         g[1] += gq * lnT;
@@ -272,10 +311,10 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     const S dlnkinf = (pb + pe * iT) * iT;
     S dlnkf = dlnkinf;
     S dM = kind == 1 ? fwd - rev : S(0.0);
-    if (kind >= 2) {
+    if (kind >= 2 && kind <= 4) {
         const double* lo = &mech::RX_LOW[j * 3];
         const S dlnk0 = (lo[1] + lo[2] * iT) * iT;
-        dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + mech::LN10 * dF_dFc * dlogFc_dT;
+        dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + dlnF_T;
         const S dkdM = kinf * r0 * Fb * (ipr1 * ipr1 + dF_dPr * ipr1);
         dM = dkdM * (pf - iKc * pr);
     }
@@ -380,7 +419,7 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
             const int j = r * G + i;
-            if (j < NR) reaction<S, MODE>(j, pk[r], par, L, T, lnT, iT, lnPRT, ctot, irho, rcp, g[r]);
+            if (j < NR) reaction<S, MODE>(j, pk[r], par, L, T, lnT, iT, lnPRT, ctot, irho, rcp, p, g[r]);
         }
         return S(0.0);
     }
@@ -392,7 +431,7 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
         for (int q = 1; q < ROUNDS; ++q)
 #pragma unroll
             for (int t = 0; t < 3; ++t) pr[t] = (q == r) ? pk[q][t] : pr[t];
-        if (j < NR) reaction<S, MODE>(j, pr, par, L, T, lnT, iT, lnPRT, ctot, irho, irho, g[0]);
+        if (j < NR) reaction<S, MODE>(j, pr, par, L, T, lnT, iT, lnPRT, ctot, irho, irho, p, g[0]);
     }
     lds_sync();
     // species lists come padded to multiples of 4: four entries' loads in flight

@@ -77,11 +77,24 @@ struct Reader {
         else if (t[1] == "thirdbody") { r.kind = RxnKind::ThirdBody; need = 7; }
         else if (t[1] == "lindemann") { r.kind = RxnKind::Lindemann; need = 10; }
         else if (t[1] == "troe") { r.kind = RxnKind::Troe; need = 14; }
+        else if (t[1] == "sri") { r.kind = RxnKind::Sri; need = 15; }
+        else if (t[1] == "plog") { r.kind = RxnKind::Plog; need = 7; }
         else return fail(CHEM_E_PARSE, "unknown reaction kind " + t[1]);
-        const bool has_eff = t.size() == need + 1 && t.back().rfind("eff=", 0) == 0;
-        if (t.size() != need + (has_eff ? 1 : 0)) return fail(CHEM_E_PARSE, "wrong field count");
-        if (has_eff && r.kind == RxnKind::Elementary)
-            return fail(CHEM_E_PARSE, "efficiencies on an elementary reaction");
+        if (t.size() < need) return fail(CHEM_E_PARSE, "wrong field count");
+        // trailing flags, each at most once: eff=..., plog=..., irrev
+        std::string eff_txt, plog_txt;
+        bool irrev = false;
+        for (size_t i = need; i < t.size(); ++i) {
+            if (t[i].rfind("eff=", 0) == 0 && eff_txt.empty()) eff_txt = t[i].substr(4);
+            else if (t[i].rfind("plog=", 0) == 0 && plog_txt.empty()) plog_txt = t[i].substr(5);
+            else if (t[i] == "irrev" && !irrev) irrev = true;
+            else return fail(CHEM_E_PARSE, "wrong field count or unknown flag '" + t[i] + "'");
+        }
+        if (!eff_txt.empty() && (r.kind == RxnKind::Elementary || r.kind == RxnKind::Plog))
+            return fail(CHEM_E_PARSE, "efficiencies on a reaction without a third body");
+        if ((r.kind == RxnKind::Plog) != !plog_txt.empty())
+            return fail(CHEM_E_PARSE, "a plog= table belongs to (and only to) a plog reaction");
+        r.reversible = !irrev;
         if (int rc = side(t[2], r.reac)) return rc;
         if (int rc = side(t[3], r.prod)) return rc;
         int order = 0;
@@ -91,13 +104,14 @@ struct Reader {
         if (!to_double(t[4], A) || !to_double(t[5], b) || !to_double(t[6], Ea))
             return fail(CHEM_E_PARSE, "bad Arrhenius numbers");
         if (!(A > 0.0)) return fail(CHEM_E_MECH_INVALID, "A must be positive");
-        // cm-mol-s to SI: each concentration factor beyond the first carries cm^3/mol
-        const int orderA = order + (r.kind == RxnKind::ThirdBody ? 1 : 0);
+        // cm-mol-s to SI: each concentration factor beyond the first carries
+        // cm^3/mol; a plog reaction's main rate is a plain factor on its table
+        const int orderA = r.kind == RxnKind::Plog ? 1 : order + (r.kind == RxnKind::ThirdBody ? 1 : 0);
         r.lnA = std::log(A) + (orderA - 1) * std::log(1e-6);
         r.b = b;
         r.EaR = Ea * 1e3 / kRu;
         r.eff.assign(m.species.size(), 1.0);
-        if (r.kind == RxnKind::Lindemann || r.kind == RxnKind::Troe) {
+        if (is_falloff(r.kind)) {
             double A0, b0, Ea0;
             if (!to_double(t[7], A0) || !to_double(t[8], b0) || !to_double(t[9], Ea0))
                 return fail(CHEM_E_PARSE, "bad low-pressure numbers");
@@ -114,8 +128,29 @@ struct Reader {
             if (!(r.T3 > 0.0) || !(r.T1 > 0.0))
                 return fail(CHEM_E_MECH_INVALID, "Troe T3 and T1 must be positive");
         }
-        if (has_eff) {
-            for (const auto& item : split(t.back().substr(4), ',')) {
+        if (r.kind == RxnKind::Sri) {
+            for (int i = 0; i < 5; ++i)
+                if (!to_double(t[10 + i], r.sri[i])) return fail(CHEM_E_PARSE, "bad SRI numbers");
+            if (!(r.sri[0] >= 0.0) || !(r.sri[2] > 0.0) || !(r.sri[3] > 0.0))
+                return fail(CHEM_E_MECH_INVALID, "SRI needs a >= 0, c > 0, d > 0");
+        }
+        if (r.kind == RxnKind::Plog) {
+            for (const auto& item : split(plog_txt, ',')) {
+                auto f = split(item, ':');
+                double pp, pa, pb, pe;
+                if (f.size() != 4 || !to_double(f[0], pp) || !to_double(f[1], pa) || !to_double(f[2], pb) ||
+                    !to_double(f[3], pe))
+                    return fail(CHEM_E_PARSE, "bad plog entry '" + item + "'");
+                if (!(pp > 0.0) || !(pa > 0.0)) return fail(CHEM_E_MECH_INVALID, "plog p and A must be positive");
+                const double lnp = std::log(pp);
+                if (!r.plog.empty() && !(lnp > r.plog.back().lnp))
+                    return fail(CHEM_E_MECH_INVALID, "plog pressures must increase");
+                r.plog.push_back({lnp, std::log(pa) + (order - 1) * std::log(1e-6), pb, pe * 1e3 / kRu});
+            }
+            if (r.plog.size() > kMaxPlog) return fail(CHEM_E_UNSUPPORTED, "more than 16 plog pressures");
+        }
+        if (!eff_txt.empty()) {
+            for (const auto& item : split(eff_txt, ',')) {
                 auto kv = split(item, ':');
                 double e;
                 if (kv.size() != 2 || !sp_index.count(kv[0]) || !to_double(kv[1], e) || e < 0.0)
@@ -123,7 +158,14 @@ struct Reader {
                 r.eff[sp_index[kv[0]]] = e;
             }
         }
-        // element balance, exact in integers
+        if (int rc = balance(r)) return rc;
+        m.reactions.push_back(std::move(r));
+        return 0;
+    }
+
+    // element balance, exact in integers
+    int balance(const ReactionData& r)
+    {
         for (size_t e = 0; e < m.elements.size(); ++e) {
             long bal = 0;
             for (auto& x : r.reac) bal -= (long)x.nu * m.species[x.sp].atoms[e];
@@ -131,7 +173,6 @@ struct Reader {
             if (bal != 0)
                 return fail(CHEM_E_MECH_INVALID, "element " + m.elements[e] + " is not balanced");
         }
-        m.reactions.push_back(std::move(r));
         return 0;
     }
 
@@ -228,6 +269,11 @@ int parse_mechanism(const std::string& path, MechanismData& m, std::string& err)
         err = "truncated mechanism file (no 'end')";
         return CHEM_E_PARSE;
     }
+    return validate_mechanism(m, err);
+}
+
+int validate_mechanism(MechanismData& m, std::string& err)
+{
     if (m.species.empty()) {
         err = "no species";
         return CHEM_E_MECH_INVALID;

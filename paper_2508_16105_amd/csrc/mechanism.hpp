@@ -1,7 +1,9 @@
 // mechanism.hpp -- host representation of a reaction mechanism read from a
-// `chemmi-mech 1` file: species with NASA-7 thermo, reversible reactions with
-// modified-Arrhenius rates, third-body efficiencies and Lindemann/Troe falloff
-// (the "reactions and thermo data" of the detailed-chemistry model, Sec. 2.1).
+// `chemmi-mech 1` file or a CHEMKIN-format file: species with NASA-7 thermo,
+// reversible or irreversible reactions with modified-Arrhenius rates,
+// third-body efficiencies, Lindemann/Troe/SRI falloff and pressure-tabulated
+// (PLOG) rates (the "reactions and thermo data" of the detailed-chemistry
+// model, Sec. 2.1).
 #pragma once
 
 #include <cstdint>
@@ -12,8 +14,16 @@ namespace chemmi {
 
 constexpr double kRu = 8.314462618;      // J/(mol K)
 constexpr double kPatm = 101325.0;       // Pa, standard state of the equilibrium constants
+constexpr size_t kMaxPlog = 16;          // pressures of one PLOG rate
 
-enum class RxnKind { Elementary, ThirdBody, Lindemann, Troe };
+enum class RxnKind { Elementary, ThirdBody, Lindemann, Troe, Sri, Plog };
+
+inline bool is_falloff(RxnKind k) { return k == RxnKind::Lindemann || k == RxnKind::Troe || k == RxnKind::Sri; }
+
+// One pressure of a PLOG rate: ln p (p in Pa) and the Arrhenius set there.
+struct PlogEntry {
+    double lnp, lnA, b, EaR;
+}; 
 
 struct SpeciesData {
     std::string name;
@@ -37,6 +47,9 @@ struct ReactionData {
     double lnA0 = 0.0, b0 = 0.0, EaR0 = 0.0;   // low-pressure limit (falloff)
     double alpha = 0.0, T3 = 1.0, T1 = 1.0, T2 = 0.0;
     bool has_T2 = false;
+    double sri[5] = {0.0, 0.0, 1.0, 1.0, 0.0};  // SRI a, b (K), c (K), d, e
+    std::vector<PlogEntry> plog;         // increasing pressure; the main rate multiplies it
+    bool reversible = true;
     std::vector<double> eff;             // per species (third-body and falloff)
 };
 
@@ -52,6 +65,15 @@ struct MechanismData {
 
 // Parse and validate.  Returns 0, or a negative chem error code with `err` set.
 int parse_mechanism(const std::string& path, MechanismData& out, std::string& err);
+
+// Read a CHEMKIN-format mechanism (ELEMENTS, SPECIES, THERMO, REACTIONS),
+// with the thermo data in the same file or in `thermo_path` (may be empty).
+int parse_chemkin(const std::string& path, const std::string& thermo_path, MechanismData& out,
+                  std::string& err);
+
+// Checks shared by both readers once everything is read: species present, each
+// with thermo data, and within CHEM_MAX_SPECIES.
+int validate_mechanism(MechanismData& m, std::string& err);
 
 // Arrhenius parameters in the layout the kernels read: lnA[nr], b[nr], EaR[nr].
 std::vector<double> pack_params(const MechanismData& m);

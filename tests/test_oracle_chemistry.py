@@ -172,7 +172,7 @@ def test_troe_center_value(oracle_lib, write_mech):
 
 # ---------------- source terms ----------------
 
-@pytest.mark.parametrize("mech", ["m9", "m13", "m32"])
+@pytest.mark.parametrize("mech", ["m9", "m13", "m32", "m13x", "m32x"])
 def test_rhs_conserves_mass_elements_enthalpy(oracle_lib, mech):
     m = oracle_lib.Mechanism(mech_path(mech))
     T, p, Y = uniform_cells(mech_text(mech), 16, 7)
@@ -207,7 +207,7 @@ def test_rhs_zero_at_detailed_balance(oracle_lib, write_mech):
 
 # ---------------- Jacobian ----------------
 
-@pytest.mark.parametrize("mech", ["m9", "m13", "m32"])
+@pytest.mark.parametrize("mech", ["m9", "m13", "m32", "m13x", "m32x"])
 def test_analytic_jacobian_matches_complex_step(oracle_lib, mech):
     m = oracle_lib.Mechanism(mech_path(mech))
     T, p, Y = uniform_cells(mech_text(mech), 8, 3)

@@ -6,7 +6,7 @@ from workloads import WORKLOADS, gen_mech, mech_path, mech_text
 from workloads import states
 
 
-@pytest.mark.parametrize("name", ["m9", "m13", "m32"])
+@pytest.mark.parametrize("name", ["m9", "m13", "m32", "m13x", "m32x"])
 def test_committed_mechanisms_regenerate_exactly(name):
     assert gen_mech.build(name) == mech_text(name)
 
@@ -78,3 +78,19 @@ def test_workload_table():
     assert WORKLOADS["rde1m"]["width"] * WORKLOADS["rde1m"]["height"] == 1048576
     sizes = states.amr_field_sizes(WORKLOADS["amr64"]["seed"])
     assert len(sizes) == 64 and min(sizes) >= 10000 and max(sizes) <= 2000000
+
+
+@pytest.mark.parametrize("name,base,nsri,nlind,nplog,nirrev", [("m13x", "m13", 1, 1, 4, 6),
+                                                               ("m32x", "m32", 5, 3, 12, 30)])
+def test_variant_mechanisms_use_every_form(name, base, nsri, nlind, nplog, nirrev):
+    rx = [l.split() for l in mech_text(name).splitlines() if l.startswith("reaction")]
+    rb = [l.split() for l in mech_text(base).splitlines() if l.startswith("reaction")]
+    assert len(rx) == len(rb)
+    kinds = [l[1] for l in rx]
+    assert kinds.count("sri") == nsri and kinds.count("lindemann") == nlind
+    assert kinds.count("plog") == nplog and sum(l[-1] == "irrev" for l in rx) == nirrev
+    for l, b in zip(rx, rb):
+        assert l[2:4] == b[2:4]                 # same species and coefficients
+        if l[1] == "plog":
+            ps = [float(e.split(":")[0]) for e in next(t for t in l if t.startswith("plog="))[5:].split(",")]
+            assert ps == sorted(ps) and len(set(ps)) == len(ps)

@@ -62,7 +62,7 @@ INERT_SPECIES = {"AR", "HE"}
 
 @dataclass
 class Reaction:
-    kind: str                      # elementary | thirdbody | troe | lindemann
+    kind: str                      # elementary | thirdbody | troe | lindemann | sri | plog
     reac: dict                     # species -> stoichiometric coefficient
     prod: dict
     A: float                       # cm-mol-s units of the reaction's order
@@ -71,6 +71,9 @@ class Reaction:
     low: tuple | None = None       # (A0, b0, Ea0) for falloff
     troe: tuple | None = None      # (alpha, T3, T1, T2 or None)
     eff: dict = field(default_factory=dict)
+    sri: tuple | None = None       # (a, b, c, d, e)
+    plog: list | None = None       # [(p Pa, A, b, Ea kJ/mol)], increasing p
+    irrev: bool = False
 
 
 @dataclass
@@ -304,13 +307,19 @@ def to_text(m: Mechanism) -> str:
     for rx in m.reactions:
         line = f"reaction {rx.kind} {_side(rx.reac)} {_side(rx.prod)} " \
                f"{_fmt(rx.A)} {_fmt(rx.b)} {_fmt(rx.Ea)}"
-        if rx.kind in ("troe", "lindemann"):
+        if rx.kind in ("troe", "lindemann", "sri"):
             line += " " + " ".join(_fmt(x) for x in rx.low)
         if rx.kind == "troe":
             a, t3, t1, t2 = rx.troe
             line += f" {_fmt(a)} {_fmt(t3)} {_fmt(t1)} " + ("-" if t2 is None else _fmt(t2))
-        if rx.kind != "elementary" and rx.eff:
+        if rx.kind == "sri":
+            line += " " + " ".join(_fmt(x) for x in rx.sri)
+        if rx.kind not in ("elementary", "plog") and rx.eff:
             line += " eff=" + ",".join(f"{s}:{_fmt(v)}" for s, v in rx.eff.items())
+        if rx.kind == "plog":
+            line += " plog=" + ",".join(":".join(_fmt(x) for x in e) for e in rx.plog)
+        if rx.irrev:
+            line += " irrev"
         out.append(line)
     out.append("end")
     return "\n".join(out) + "\n"
@@ -329,9 +338,15 @@ def format_doc() -> str:
   reaction thirdbody  <reac> <prod> A b Ea [eff=<sp>:<e>,...]
   reaction lindemann  <reac> <prod> A b Ea A0 b0 Ea0 [eff=...]
   reaction troe       <reac> <prod> A b Ea A0 b0 Ea0 alpha T3 T1 T2|- [eff=...]
-      <reac>/<prod>: <species>=<nu>[,...]; every reaction is reversible.
+  reaction sri        <reac> <prod> A b Ea A0 b0 Ea0 a b c d e [eff=...]
+  reaction plog       <reac> <prod> A b Ea plog=<p>:<A>:<b>:<Ea>[,...]
+      <reac>/<prod>: <species>=<nu>[,...].  A trailing 'irrev' drops the
+      reverse reaction; otherwise it runs at k_f / K_c.
       A in cm-mol-s units of the reaction's order (+1 for third-body and for
       the low-pressure A0), Ea in kJ/mol; unlisted efficiencies are 1.
+      SRI: F = d [a exp(-b/T) + exp(-T/c)]^X T^e, X = 1 / (1 + log10(P_r)^2).
+      plog: pressures in Pa, increasing; ln k linear in ln p between them,
+      the end rates outside; the main A (plain factor), b, Ea multiply it.
   end
 """
 
@@ -346,7 +361,47 @@ MECHS = {
 }
 
 
+# Variants that exercise every reaction form: some Troe reactions become SRI
+# or Lindemann, some elementary ones pressure-tabulated, some irreversible.
+VARIANTS = {
+    "m13x": dict(base="m13", seed=9012, n_sri=1, n_lindemann=1, n_plog=4, n_irrev=6),
+    "m32x": dict(base="m32", seed=9013, n_sri=5, n_lindemann=3, n_plog=12, n_irrev=30),
+}
+
+# PLOG pressure sets (atm): around, inside and outside the 1-30 atm of the fields
+PLOG_PRESSURES = [(0.1, 1.0, 10.0, 100.0), (2.0, 5.0), (1.0,), (0.01, 0.3, 3.0, 8.0, 20.0, 300.0)]
+P_ATM = 101325.0
+
+
+def variant(m: Mechanism, name, seed, n_sri, n_lindemann, n_plog, n_irrev) -> Mechanism:
+    rng = np.random.default_rng(seed)
+    rx = [Reaction(**{k: getattr(r, k) for k in r.__dataclass_fields__}) for r in m.reactions]
+    troe = [i for i, r in enumerate(rx) if r.kind == "troe"]
+    for i in troe[:n_sri]:
+        rx[i].kind, rx[i].troe = "sri", None
+        rx[i].sri = (float(rng.uniform(0.3, 1.5)), float(rng.uniform(100.0, 1000.0)),
+                     float(rng.uniform(200.0, 2000.0)), float(rng.uniform(0.8, 1.3)),
+                     float(rng.uniform(-0.4, 0.4)))
+    for i in troe[n_sri:n_sri + n_lindemann]:
+        rx[i].kind, rx[i].troe = "lindemann", None
+    elem = [i for i, r in enumerate(rx) if r.kind == "elementary"]
+    for n, i in enumerate(rng.permutation(elem)[:n_plog]):
+        r = rx[i]
+        entries = []
+        for p in PLOG_PRESSURES[n % len(PLOG_PRESSURES)]:
+            entries.append((p * P_ATM, float(r.A * 10.0 ** rng.uniform(-0.7, 0.7)),
+                            float(r.b + rng.uniform(-0.3, 0.3)), float(max(0.0, r.Ea + rng.uniform(-10.0, 10.0)))))
+        r.kind, r.plog, r.A, r.b, r.Ea = "plog", entries, 1.0, 0.0, 0.0
+    for i in rng.permutation(len(rx))[:n_irrev]:
+        rx[i].irrev = True
+    return Mechanism(name, m.elements, m.species, m.thermo, rx)
+
+
 def build(name: str) -> str:
+    if name in VARIANTS:
+        kw = dict(VARIANTS[name])
+        base = kw.pop("base")
+        return to_text(variant(generate(base, **MECHS[base]), name, **kw))
     kw = dict(MECHS[name])
     return to_text(generate(name, **kw))
 
@@ -356,6 +411,6 @@ if __name__ == "__main__":
     import sys
     outdir = pathlib.Path(__file__).parent / "mech"
     outdir.mkdir(exist_ok=True)
-    for nm in (sys.argv[1:] or list(MECHS)):
+    for nm in (sys.argv[1:] or list(MECHS) + list(VARIANTS)):
         (outdir / f"{nm}.mech").write_text(build(nm))
         print("wrote", outdir / f"{nm}.mech")

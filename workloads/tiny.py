@@ -28,14 +28,15 @@ def text(elements, species, thermo, reactions):
     return "\n".join(lines) + "\n"
 
 
-def isomer_pair(A=1.0e6, dS_R=1.0, b=0.0, Ea=0.0):
+def isomer_pair(A=1.0e6, dS_R=1.0, b=0.0, Ea=0.0, irrev=False):
     """A <=> B + inert N2; A and B are isomers (same weight) with identical
-    cp and H, differing only in S by dS_R (so K_c = exp(dS_R), dH = 0)."""
+    cp and H, differing only in S by dS_R (so K_c = exp(dS_R), dH = 0).
+    irrev: A => B only."""
     return text([("H", 1.008), ("O", 15.999), ("N", 14.007)],
                 [("A", "H=1,O=1"), ("B", "H=1,O=1"), ("N2", "N=2")],
                 [_thermo("A", 3.5, -1000.0, 5.0), _thermo("B", 3.5, -1000.0, 5.0 + dS_R),
                  _thermo("N2", 3.5, -1000.0, 4.0)],
-                [f"reaction elementary A=1 B=1 {_fmt(A)} {_fmt(b)} {_fmt(Ea)}"])
+                [f"reaction elementary A=1 B=1 {_fmt(A)} {_fmt(b)} {_fmt(Ea)}" + (" irrev" if irrev else "")])
 
 
 def isomer_network(rates, dS):
@@ -61,18 +62,37 @@ def dissociation(A=1.0e14, b=0.0, Ea=100.0, a6_H=25000.0, a7_H=-1.0, a7_H2=-3.0)
 
 
 def falloff(kind="troe", A=1.0e13, b=0.0, Ea=0.0, A0=1.0e16, b0=0.0, Ea0=0.0,
-            troe=(0.5, 200.0, 2000.0, None), eff=None):
+            troe=(0.5, 200.0, 2000.0, None), eff=None, sri=(0.5, 300.0, 1500.0, 1.0, 0.0),
+            irrev=False):
     """A + B (+M) <=> AB (+M) with inert N2 and constant-cp thermo."""
     line = f"reaction {kind} A=1,B=1 AB=1 {_fmt(A)} {_fmt(b)} {_fmt(Ea)}"
-    if kind in ("troe", "lindemann"):
+    if kind in ("troe", "lindemann", "sri"):
         line += f" {_fmt(A0)} {_fmt(b0)} {_fmt(Ea0)}"
     if kind == "troe":
         a, t3, t1, t2 = troe
         line += f" {_fmt(a)} {_fmt(t3)} {_fmt(t1)} " + ("-" if t2 is None else _fmt(t2))
+    if kind == "sri":
+        line += " " + " ".join(_fmt(x) for x in sri)
     if eff:
         line += " eff=" + ",".join(f"{s}:{_fmt(v)}" for s, v in eff.items())
+    if irrev:
+        line += " irrev"
+    return _abn2([line])
+
+
+def plog(entries, A=1.0, b=0.0, Ea=0.0, irrev=False):
+    """A + B <=> AB with a pressure-tabulated rate: entries = [(p Pa, A, b, Ea
+    kJ/mol)], the main rate (A, b, Ea) a factor on it."""
+    line = f"reaction plog A=1,B=1 AB=1 {_fmt(A)} {_fmt(b)} {_fmt(Ea)} plog=" + ",".join(
+        ":".join(_fmt(x) for x in e) for e in entries)
+    if irrev:
+        line += " irrev"
+    return _abn2([line])
+
+
+def _abn2(reactions):
     return text([("H", 1.008), ("O", 15.999), ("N", 14.007)],
                 [("A", "H=1"), ("B", "O=1"), ("AB", "H=1,O=1"), ("N2", "N=2")],
                 [_thermo("A", 2.5, 20000.0, 2.0), _thermo("B", 2.5, 25000.0, 3.0),
                  _thermo("AB", 3.5, 4000.0, 4.0), _thermo("N2", 3.5, -1043.5, 4.0)],
-                [line])
+                reactions)
