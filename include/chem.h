@@ -119,6 +119,28 @@ typedef struct {
    CHEM_E_UNSUPPORTED, CHEM_E_COMPILE. */
 int chem_load_mechanism(const char *path, chem_mechanism **out);
 
+/* Read a mechanism in the CHEMKIN text format and build its device code as
+   chem_load_mechanism does (which also takes a CHEMKIN file, recognised by
+   its first keyword, with the thermo data inline).  mech_path: ELEMENTS
+   (symbols, optional /weight/; standard weights for H D HE C N O F NE SI S CL
+   AR KR XE), SPECIES, an optional THERMO section, REACTIONS with the unit
+   keywords CAL/MOLE (default), KCAL/MOLE, JOULES/MOLE, KJOULES/MOLE, KELVINS,
+   EVOLTS and MOLES.  thermo_path: NULL, or a file of NASA-7 four-line
+   records (optionally opened by THERMO [ALL] and the default temperatures)
+   used for species the mechanism file gives no record for.  Reactions:
+   "=", "<=>" (reversible at k_f / K_c) and "=>" (irreversible); "+M" third
+   bodies with species/efficiency/ pairs; "(+M)" and "(+species)" falloff with
+   LOW and optional TROE (3 or 4 values) or SRI (3 or 5 values); PLOG/p A b E/
+   lines (p in atm, increasing; ln k linear in ln p between them, the end
+   rates outside), which replace the reaction line's own rate; DUPLICATE,
+   required on every reaction that repeats another's species and third-body
+   form.  Integer coefficients only.  REV, FORD/RORD, HIGH, CHEB, LT and the
+   other rate forms give CHEM_E_UNSUPPORTED naming the line.  A PLOG
+   reaction's parameters (chem_get_params) are a factor on its table
+   (A = 1, b = 0, Ea = 0 as loaded).  Errors as chem_load_mechanism, with
+   "file:line: " in chem_last_error(). */
+int chem_load_chemkin(const char *mech_path, const char *thermo_path, chem_mechanism **out);
+
 /* Free the handle and every device resource the library holds for it. */
 void chem_free_mechanism(chem_mechanism *m);
 

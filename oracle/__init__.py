@@ -230,6 +230,23 @@ class Mechanism:
         return gT0, gY0.reshape(n, self.ns), ga, gb, ge
 
 
+def chemkin_mechanism(path, thermo=None):
+    """A Mechanism from a CHEMKIN-format file (thermo: optional separate
+    thermo file), through the converter in oracle/chemkin.py."""
+    import os
+    import tempfile
+    from . import chemkin
+    text = pathlib.Path(path).read_text()
+    ttext = pathlib.Path(thermo).read_text() if thermo else None
+    fd, tmp = tempfile.mkstemp(suffix=".mech")
+    try:
+        with os.fdopen(fd, "w") as f:
+            f.write(chemkin.convert(text, ttext, name=pathlib.Path(path).stem))
+        return Mechanism(tmp)
+    finally:
+        os.unlink(tmp)
+
+
 def tableau(method=RODAS4):
     s, g = C.c_int(0), C.c_double(0)
     a, c, m, e = np.zeros(36), np.zeros(36), np.zeros(6), np.zeros(6)

@@ -54,11 +54,13 @@ def _check_tensor(t, name, shape=None, dtype=None):
 
 
 class Mechanism:
-    """A loaded mechanism (chem_load_mechanism)."""
+    """A loaded mechanism: a `chemmi-mech 1` or CHEMKIN file
+    (chem_load_mechanism), or a CHEMKIN file with its thermo data in a second
+    file (chem_load_chemkin)."""
 
-    def __init__(self, path):
+    def __init__(self, path, thermo=None):
         self.path = str(path)
-        self.h = _lib.load_mechanism_handle(self.path)
+        self.h = _lib.load_mechanism_handle(self.path, thermo)
         ns, nr = C.c_int(), C.c_int()
         _lib.check(_lib.lib().chem_mechanism_info(self.h, C.byref(ns), C.byref(nr)))
         self.ns, self.nr = ns.value, nr.value

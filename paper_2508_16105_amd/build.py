@@ -20,8 +20,11 @@ LIB = PKG / "libchemmi.so"
 ROOT = PKG.parent
 # (mechanism, CHEM_LANE_MAX_SPECIES at load): the default builds and the
 # wave-cooperative builds of the 9- and 13-species mechanisms
-PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0")]
-HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "codegen.cpp"]
+PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0"),
+            ("m13x", None), ("m13x", "0"), ("m32x", None)]
+# CHEMKIN renderings the tests load (written into the build folder first)
+PREBUILT_CHEMKIN = ["m9", "m32x"]
+HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "chemkin.cpp", "codegen.cpp"]
 
 
 def embed_device_source():
@@ -62,6 +65,16 @@ def prebuild_mechanisms(builds=None):
             else:
                 os.environ["CHEM_LANE_MAX_SPECIES"] = lane_max
             _lib.load_mechanism_handle(str(mdir / f"{nm}.mech"))
+        os.environ.pop("CHEM_LANE_MAX_SPECIES", None)
+        _lib.load_mechanism_handle(str(ROOT / "tests" / "golden" / "ck_small.inp"))
+        if builds is None:
+            import tempfile
+            from workloads import gen_mech
+            with tempfile.TemporaryDirectory() as td:
+                for nm in PREBUILT_CHEMKIN:
+                    p = pathlib.Path(td) / f"{nm}.inp"
+                    p.write_text(gen_mech.to_chemkin(gen_mech.build_mechanism(nm)))
+                    _lib.load_mechanism_handle(str(p))
     finally:
         if old is None:
             os.environ.pop("CHEM_LANE_MAX_SPECIES", None)

@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -109,20 +111,11 @@ Options resolve_options(const chem_options* o)
 
 }  // namespace chemmi
 
-extern "C" {
+namespace {
 
-const char* chem_last_error(void) { return g_last_error.c_str(); }
-
-const char* chem_version(void) { return "chemmi 0.1 (gfx950, RODAS4, FP64)"; }
-
-int chem_load_mechanism(const char* path, chem_mechanism** out)
+int finish_load(std::unique_ptr<chem_mechanism> m, chem_mechanism** out)
 {
-    g_last_error.clear();
-    if (!path || !out) return set_error(CHEM_E_INVAL, "null argument");
-    *out = nullptr;
-    auto m = std::make_unique<chem_mechanism>();
     std::string err;
-    if (int rc = parse_mechanism(path, m->data, err)) return set_error(rc, err);
     if (m->data.ns() > CHEM_MAX_SPECIES)
         return set_error(CHEM_E_UNSUPPORTED, "more than " + std::to_string(CHEM_MAX_SPECIES) + " species");
     m->params = pack_params(m->data);
@@ -140,6 +133,57 @@ int chem_load_mechanism(const char* path, chem_mechanism** out)
     if (int rc = build_code_object(m->source, m->code, err, &m->cache_file)) return set_error(rc, err);
     *out = m.release();
     return CHEM_OK;
+}
+
+// First word of the file that is not blank or a comment ('#' or '!').
+std::string first_word(const char* path)
+{
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        for (char c : {'#', '!'}) {
+            auto k = line.find(c);
+            if (k != std::string::npos) line.resize(k);
+        }
+        std::istringstream ss(line);
+        std::string w;
+        if (ss >> w) return w;
+    }
+    return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* chem_last_error(void) { return g_last_error.c_str(); }
+
+const char* chem_version(void) { return "chemmi 0.1 (gfx950, RODAS4, FP64)"; }
+
+int chem_load_mechanism(const char* path, chem_mechanism** out)
+{
+    g_last_error.clear();
+    if (!path || !out) return set_error(CHEM_E_INVAL, "null argument");
+    *out = nullptr;
+    auto m = std::make_unique<chem_mechanism>();
+    std::string err;
+    std::string w = first_word(path);
+    for (auto& c : w) c = (char)std::toupper((unsigned char)c);
+    const bool chemkin = w == "ELEMENTS" || w == "ELEM" || w == "SPECIES" || w == "SPEC" || w == "THERMO";
+    if (int rc = chemkin ? parse_chemkin(path, "", m->data, err) : parse_mechanism(path, m->data, err))
+        return set_error(rc, err);
+    return finish_load(std::move(m), out);
+}
+
+int chem_load_chemkin(const char* mech_path, const char* thermo_path, chem_mechanism** out)
+{
+    g_last_error.clear();
+    if (!mech_path || !out) return set_error(CHEM_E_INVAL, "null argument");
+    *out = nullptr;
+    auto m = std::make_unique<chem_mechanism>();
+    std::string err;
+    if (int rc = parse_chemkin(mech_path, thermo_path ? thermo_path : "", m->data, err)) return set_error(rc, err);
+    return finish_load(std::move(m), out);
 }
 
 void chem_free_mechanism(chem_mechanism* m)

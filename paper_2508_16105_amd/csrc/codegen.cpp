@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <sstream>
 
 namespace chemmi {
@@ -217,31 +218,23 @@ struct Emitter {
             }
     }
 
-    // PLOG: the Arrhenius set at this pressure, linear in ln p between the
-    // tabulated pressures and the end sets outside them (pla, plb, ple).
+    // PLOG: the Arrhenius set at this pressure (pla, plb, ple), linear in ln p
+    // between the tabulated pressures and the end sets outside them, written
+    // without branches: with w_i = clamp((ln p - ln p_i) / (ln p_i+1 - ln p_i),
+    // 0, 1) the set is x_0 + sum_i w_i (x_i+1 - x_i), which telescopes to x_i +
+    // w_i (x_i+1 - x_i) inside interval i and to the end sets outside.
     void plog_set(const ReactionData& r)
     {
         const auto& e = r.plog;
-        const size_t n = e.size();
-        auto set = [&](size_t i) {
-            return "pla = " + lit(e[i].lnA) + "; plb = " + lit(e[i].b) + "; ple = " + lit(e[i].EaR) + ";";
-        };
-        o << "    double pla, plb, ple;\n";
-        if (n == 1) {
-            o << "    " << set(0) << "\n";
-            return;
+        o << "    double pla = " << lit(e[0].lnA) << ", plb = " << lit(e[0].b) << ", ple = " << lit(e[0].EaR)
+          << ";\n";
+        for (size_t i = 0; i + 1 < e.size(); ++i) {
+            o << "    { const double w = fmin(1.0, fmax(0.0, (lnp - " << lit(e[i].lnp) << ") * "
+              << lit(1.0 / (e[i + 1].lnp - e[i].lnp)) << "));\n"
+                 "      pla = fma(w, " << lit(e[i + 1].lnA - e[i].lnA) << ", pla);\n"
+                 "      plb = fma(w, " << lit(e[i + 1].b - e[i].b) << ", plb);\n"
+                 "      ple = fma(w, " << lit(e[i + 1].EaR - e[i].EaR) << ", ple); }\n";
         }
-        o << "    if (!(lnp > " << lit(e[0].lnp) << ")) { " << set(0) << " }\n";
-        for (size_t i = 0; i + 1 < n; ++i) {
-            o << "    else if (lnp < " << lit(e[i + 1].lnp) << ") {\n"
-                 "      const double w = (lnp - " << lit(e[i].lnp) << ") * " << lit(1.0 / (e[i + 1].lnp - e[i].lnp))
-              << ";\n"
-                 "      pla = fma(w, " << lit(e[i + 1].lnA - e[i].lnA) << ", " << lit(e[i].lnA) << ");\n"
-                 "      plb = fma(w, " << lit(e[i + 1].b - e[i].b) << ", " << lit(e[i].b) << ");\n"
-                 "      ple = fma(w, " << lit(e[i + 1].EaR - e[i].EaR) << ", " << lit(e[i].EaR) << ");\n"
-                 "    }\n";
-        }
-        o << "    else { " << set(n - 1) << " }\n";
     }
 
     std::string third_body_sum(const ReactionData& r)

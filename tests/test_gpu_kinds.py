@@ -150,3 +150,47 @@ def test_adjoint_matches_oracle(chem, mechs, dev, key):
     assert np.all(np.max(np.abs(gY0 - oY0), axis=1) <= np.maximum(1e-5 * sc, 4 * spread[1]))
     for i, g, o in ((2, ga, oa), (3, gb, ob), (4, ge, oe)):
         assert np.max(np.abs(g - o)) <= max(1e-5 * np.max(np.abs(o)), 4 * spread[i]), i
+
+
+# ---------------- mechanisms read from CHEMKIN files ----------------
+
+@pytest.fixture(scope="module")
+def ck(chem, oracle_lib, tmp_path_factory):
+    """The hand-written CHEMKIN fixture (9 species, every reaction form, lane
+    form) and the m32x mechanism written as CHEMKIN with its thermo in a
+    separate file (wave-cooperative form), each with the oracle's reading of
+    the same files and the `chemmi-mech 1` text of that reading."""
+    import pathlib
+    from oracle import chemkin
+    from workloads import gen_mech
+    fixture = pathlib.Path(__file__).resolve().parent / "golden" / "ck_small.inp"
+    d = tmp_path_factory.mktemp("ck")
+    m = gen_mech.build_mechanism("m32x")
+    bare, thermo = d / "m32x.inp", d / "therm.dat"
+    bare.write_text(gen_mech.to_chemkin(m, inline_thermo=False))
+    thermo.write_text(gen_mech.thermo_chemkin(m))
+    return {"ck_small": (chem.Mechanism(fixture), oracle_lib.chemkin_mechanism(fixture),
+                         chemkin.convert(fixture.read_text())),
+            "m32x_ck": (chem.Mechanism(bare, thermo=thermo), oracle_lib.chemkin_mechanism(bare, thermo),
+                        chemkin.convert(bare.read_text(), thermo.read_text()))}
+
+
+@pytest.mark.parametrize("key,n,dt", [("ck_small", 777, 1e-7), ("m32x_ck", 130, 1e-5)])
+def test_chemkin_mechanisms_match_oracle(chem, ck, dev, key, n, dt):
+    gm, om, text = ck[key]
+    T, p, Y = uniform_cells(text, n, 86)
+    p = PATM * np.exp(np.random.default_rng(87).uniform(np.log(0.005), np.log(2000.0), n))
+    f, J = chem.eval_source(gm, _g(T, dev), _g(p, dev), _g(Y, dev))
+    f, J = f.cpu().numpy(), J.cpu().numpy()
+    for i in range(0, n, 7):
+        y = np.concatenate([[T[i]], Y[i]])
+        fo = om.rhs(p[i], y)
+        assert np.all(np.abs(f[i] - fo) <= 1e-11 * np.abs(fo).max() + 1e-300), (key, i)
+        Jo, Ja = om.jac_cs(p[i], y), om.jac(p[i], y)
+        sc = np.abs(Jo).max(axis=1, keepdims=True) * np.maximum(np.abs(y), 1e-3)[None, :] \
+            / np.maximum(np.abs(y), 1e-3).max()
+        assert np.all(np.abs(J[i] - Jo) <= 1e-10 * (np.abs(Jo) + sc) + 4.0 * np.abs(Ja - Jo)), (key, i)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), dt, RTOL, ATOL)
+    To, Yo, _, _, sto = om.integrate(T, p, Y, dt, RTOL, ATOL)
+    assert stats["failed"] == 0 and np.all(sto == 0)
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, key)

@@ -325,6 +325,72 @@ def to_text(m: Mechanism) -> str:
     return "\n".join(out) + "\n"
 
 
+# --------------------------------------------------------------------------
+# the same mechanisms in the CHEMKIN text format
+# --------------------------------------------------------------------------
+
+def _e15(x):
+    return f"{x:15.8E}"
+
+
+def thermo_chemkin(m: Mechanism) -> str:
+    """THERMO ALL section: four-line NASA-7 records in the fixed columns
+    (coefficients to nine significant digits, as the format holds them)."""
+    out = ["THERMO ALL", f"   {T_LOW:.3f}  {T_MID:.3f}  {T_HIGH:.3f}"]
+    for s, comp in m.species:
+        lo, hi = m.thermo[s]
+        fields = "".join(f"{e:<2}{n:>3d}" for e, n in comp.items()).ljust(20)
+        out.append(f"{s:<18}{'':6}{fields}G{T_LOW:10.3f}{T_HIGH:10.3f}{T_MID:8.2f}{'':6}1")
+        out.append("".join(_e15(x) for x in hi[:5]) + "    2")
+        out.append("".join(_e15(x) for x in list(hi[5:7]) + list(lo[:3])) + "    3")
+        out.append("".join(_e15(x) for x in lo[3:7]) + " " * 15 + "    4")
+    out.append("END")
+    return "\n".join(out) + "\n"
+
+
+def _ck_side(d, m_mark=""):
+    return "+".join((f"{c}{s}" if c > 1 else s) for s, c in d.items()) + m_mark
+
+
+def to_chemkin(m: Mechanism, inline_thermo=True) -> str:
+    """The mechanism as a CHEMKIN file: energies in kJ/mol (KJOULES/MOLE),
+    PLOG pressures in atm; thermo inline (THERMO ALL) or left to a separate
+    file (thermo_chemkin)."""
+    out = [f"! {m.name}: seeded synthetic mechanism", "ELEMENTS"]
+    out.append(" ".join(f"{e}/{_fmt(ATOMIC_WEIGHTS[e])}/" for e in m.elements))
+    out += ["END", "SPECIES", " ".join(s for s, _ in m.species), "END"]
+    if inline_thermo:
+        out.append(thermo_chemkin(m).rstrip("\n"))
+    out.append("REACTIONS KJOULES/MOLE MOLES")
+    for rx in m.reactions:
+        mark = {"thirdbody": "+M", "troe": "(+M)", "lindemann": "(+M)", "sri": "(+M)"}.get(rx.kind, "")
+        arrow = "=>" if rx.irrev else "<=>"
+        A, b, Ea = (rx.plog[0][1:] if rx.kind == "plog" else (rx.A, rx.b, rx.Ea))
+        out.append(f"{_ck_side(rx.reac, mark)}{arrow}{_ck_side(rx.prod, mark)}   {_fmt(A)} {_fmt(b)} {_fmt(Ea)}")
+        if rx.kind in ("troe", "lindemann", "sri"):
+            out.append("    LOW / " + " ".join(_fmt(x) for x in rx.low) + " /")
+        if rx.kind == "troe":
+            a, t3, t1, t2 = rx.troe
+            out.append(f"    TROE / {_fmt(a)} {_fmt(t3)} {_fmt(t1)}" + ("" if t2 is None else f" {_fmt(t2)}") + " /")
+        if rx.kind == "sri":
+            out.append("    SRI / " + " ".join(_fmt(x) for x in rx.sri) + " /")
+        if rx.kind == "plog":
+            for p, Ap, bp, Ep in rx.plog:
+                out.append(f"    PLOG / {_fmt(p / 101325.0)} {_fmt(Ap)} {_fmt(bp)} {_fmt(Ep)} /")
+        if rx.kind not in ("elementary", "plog") and rx.eff:
+            out.append("    " + " ".join(f"{s}/{_fmt(v)}/" for s, v in rx.eff.items()))
+    out.append("END")
+    return "\n".join(out) + "\n"
+
+
+def build_mechanism(name: str) -> Mechanism:
+    if name in VARIANTS:
+        kw = dict(VARIANTS[name])
+        base = kw.pop("base")
+        return variant(generate(base, **MECHS[base]), name, **kw)
+    return generate(name, **MECHS[name])
+
+
 def format_doc() -> str:
     return """chemmi-mech 1 -- one record per line, '#' starts a comment
   name <id>
@@ -398,12 +464,7 @@ def variant(m: Mechanism, name, seed, n_sri, n_lindemann, n_plog, n_irrev) -> Me
 
 
 def build(name: str) -> str:
-    if name in VARIANTS:
-        kw = dict(VARIANTS[name])
-        base = kw.pop("base")
-        return to_text(variant(generate(base, **MECHS[base]), name, **kw))
-    kw = dict(MECHS[name])
-    return to_text(generate(name, **kw))
+    return to_text(build_mechanism(name))
 
 
 if __name__ == "__main__":
