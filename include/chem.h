@@ -141,6 +141,23 @@ int chem_load_mechanism(const char *path, chem_mechanism **out);
    "file:line: " in chem_last_error(). */
 int chem_load_chemkin(const char *mech_path, const char *thermo_path, chem_mechanism **out);
 
+/* Read a mechanism in OpenFOAM's chemistry dictionary format (the input of
+   the paper's detailed-chemistry model, Sec. 2.1) and build its device code.
+   reactions_path: a dictionary file with `species (names);`, an optional
+   `elements (names);` and a `reactions { name { type ...; reaction "a + b =
+   c"; ... } ... }` dictionary; types (with or without a trailing "Reaction")
+   reversible/irreversible + Arrhenius, ThirdBodyArrhenius,
+   ArrheniusLindemannFallOff, ArrheniusTroeFallOff (F: alpha Tsss Ts Tss),
+   ArrheniusSRIFallOff (F: a b c d e); rates as A beta Ta with A in
+   (m^3/kmol)^(order-1)/s and Ta = Ea/R in K; k0 and kInf dictionaries for
+   falloff; thirdBodyEfficiencies { coeffs N ((species value) ...); }.
+   thermo_path: one dictionary per species with specie { molWeight (kg/kmol) },
+   thermodynamics { Tlow Thigh Tcommon highCpCoeffs (7) lowCpCoeffs (7) } and
+   elements { symbol count; ... }; species weights come from molWeight.
+   Reaction orders (^), non-integer coefficients and other reaction types give
+   CHEM_E_UNSUPPORTED naming the reaction.  Errors as chem_load_mechanism. */
+int chem_load_openfoam(const char *reactions_path, const char *thermo_path, chem_mechanism **out);
+
 /* Free the handle and every device resource the library holds for it. */
 void chem_free_mechanism(chem_mechanism *m);
 

@@ -247,6 +247,23 @@ def chemkin_mechanism(path, thermo=None):
         os.unlink(tmp)
 
 
+def openfoam_mechanism(reactions, thermo):
+    """A Mechanism from an OpenFOAM reactions/thermo dictionary pair, through
+    the converter in oracle/foam.py."""
+    import os
+    import tempfile
+    from . import foam
+    text = foam.convert(pathlib.Path(reactions).read_text(), pathlib.Path(thermo).read_text(),
+                        name=pathlib.Path(reactions).stem)
+    fd, tmp = tempfile.mkstemp(suffix=".mech")
+    try:
+        with os.fdopen(fd, "w") as f:
+            f.write(text)
+        return Mechanism(tmp)
+    finally:
+        os.unlink(tmp)
+
+
 def tableau(method=RODAS4):
     s, g = C.c_int(0), C.c_double(0)
     a, c, m, e = np.zeros(36), np.zeros(36), np.zeros(6), np.zeros(6)

@@ -191,7 +191,7 @@ int om_load(const char *path, omech **out, char *err, int errlen)
             snprintf(m->ename[m->ne], 8, "%s", tok[1]);
             m->ew[m->ne++] = atof(tok[2]);
         } else if (!strcmp(tok[0], "species")) {
-            if (nt != 3 || m->ns >= OM_NSMAX) FAIL(OM_E_SIZE, "line %d: bad species", lineno);
+            if ((nt != 3 && nt != 4) || m->ns >= OM_NSMAX) FAIL(OM_E_SIZE, "line %d: bad species", lineno);
             int k = m->ns++;
             snprintf(m->sname[k], 24, "%s", tok[1]);
             double w = 0.0;
@@ -205,6 +205,11 @@ int om_load(const char *path, omech **out, char *err, int errlen)
                 w += m->ew[e] * atoi(eq + 1);
             }
             m->W[k] = w * 1e-3;
+            if (nt == 4) {                      /* W=<molar mass, g/mol> given explicitly */
+                if (strncmp(tok[3], "W=", 2) || !(atof(tok[3] + 2) > 0.0))
+                    FAIL(OM_E_PARSE, "line %d: bad species weight", lineno);
+                m->W[k] = atof(tok[3] + 2) * 1e-3;
+            }
         } else if (!strcmp(tok[0], "thermo")) {
             if (nt != 19) FAIL(OM_E_PARSE, "line %d: thermo needs 17 numbers", lineno);
             int k = find_species(m, tok[1]);

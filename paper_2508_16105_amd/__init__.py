@@ -55,12 +55,13 @@ def _check_tensor(t, name, shape=None, dtype=None):
 
 class Mechanism:
     """A loaded mechanism: a `chemmi-mech 1` or CHEMKIN file
-    (chem_load_mechanism), or a CHEMKIN file with its thermo data in a second
-    file (chem_load_chemkin)."""
+    (chem_load_mechanism), a CHEMKIN file with its thermo data in a second
+    file (chem_load_chemkin), or an OpenFOAM reactions/thermo pair
+    (fmt="openfoam", chem_load_openfoam)."""
 
-    def __init__(self, path, thermo=None):
+    def __init__(self, path, thermo=None, fmt=None):
         self.path = str(path)
-        self.h = _lib.load_mechanism_handle(self.path, thermo)
+        self.h = _lib.load_mechanism_handle(self.path, thermo, fmt)
         ns, nr = C.c_int(), C.c_int()
         _lib.check(_lib.lib().chem_mechanism_info(self.h, C.byref(ns), C.byref(nr)))
         self.ns, self.nr = ns.value, nr.value

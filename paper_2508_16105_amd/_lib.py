@@ -14,7 +14,7 @@ ERRORS = {-1: "CHEM_E_INVAL", -2: "CHEM_E_PARSE", -3: "CHEM_E_MECH_INVALID", -4:
 FORM_AUTO, FORM_PLAIN, FORM_PERSISTENT = 0, 1, 2
 ORDER_COST, ORDER_NATURAL = 1, 2
 
-EXPORTS = ["chem_load_mechanism", "chem_load_chemkin", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
+EXPORTS = ["chem_load_mechanism", "chem_load_chemkin", "chem_load_openfoam", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
            "chem_set_params", "chem_eval_source", "chem_step_fixed", "chem_integrate",
            "chem_integrate_source", "chem_integrate_batched", "chem_integrate_adjoint",
            "chem_last_error", "chem_version"]
@@ -54,6 +54,7 @@ def lib():
         vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
         L.chem_load_mechanism.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.chem_load_chemkin.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(vp)]
+        L.chem_load_openfoam.argtypes = [C.c_char_p, C.c_char_p, C.POINTER(vp)]
         L.chem_free_mechanism.argtypes = [vp]
         L.chem_free_mechanism.restype = None
         L.chem_mechanism_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
@@ -84,10 +85,13 @@ def check(rc, allow=()):
     return rc
 
 
-def load_mechanism_handle(path: str, thermo: str | None = None) -> C.c_void_p:
-    """chem_load_mechanism, or chem_load_chemkin when a thermo file is given."""
+def load_mechanism_handle(path: str, thermo: str | None = None, fmt: str | None = None) -> C.c_void_p:
+    """chem_load_mechanism; chem_load_chemkin when a thermo file is given;
+    chem_load_openfoam for fmt == "openfoam" (path: reactions, thermo: thermo)."""
     h = C.c_void_p()
-    if thermo is None:
+    if fmt == "openfoam":
+        check(lib().chem_load_openfoam(str(path).encode(), str(thermo).encode(), C.byref(h)))
+    elif thermo is None:
         check(lib().chem_load_mechanism(str(path).encode(), C.byref(h)))
     else:
         check(lib().chem_load_chemkin(str(path).encode(), str(thermo).encode(), C.byref(h)))

@@ -24,7 +24,9 @@ PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0"
             ("m13x", None), ("m13x", "0"), ("m32x", None)]
 # CHEMKIN renderings the tests load (written into the build folder first)
 PREBUILT_CHEMKIN = ["m9", "m32x"]
-HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "chemkin.cpp", "codegen.cpp"]
+# OpenFOAM renderings the tests load
+PREBUILT_OPENFOAM = ["m9", "m32s"]
+HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "chemkin.cpp", "foam.cpp", "codegen.cpp"]
 
 
 def embed_device_source():
@@ -75,6 +77,14 @@ def prebuild_mechanisms(builds=None):
                     p = pathlib.Path(td) / f"{nm}.inp"
                     p.write_text(gen_mech.to_chemkin(gen_mech.build_mechanism(nm)))
                     _lib.load_mechanism_handle(str(p))
+                for nm in PREBUILT_OPENFOAM:
+                    r, t = gen_mech.to_openfoam(gen_mech.build_mechanism(nm))
+                    rp, tp = pathlib.Path(td) / f"{nm}.foam", pathlib.Path(td) / "thermo"
+                    rp.write_text(r)
+                    tp.write_text(t)
+                    _lib.load_mechanism_handle(str(rp), str(tp), "openfoam")
+            fx = ROOT / "tests" / "golden" / "foam_small"
+            _lib.load_mechanism_handle(str(fx / "reactions"), str(fx / "thermo"), "openfoam")
     finally:
         if old is None:
             os.environ.pop("CHEM_LANE_MAX_SPECIES", None)

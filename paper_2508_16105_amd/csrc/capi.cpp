@@ -175,6 +175,17 @@ int chem_load_mechanism(const char* path, chem_mechanism** out)
     return finish_load(std::move(m), out);
 }
 
+int chem_load_openfoam(const char* reactions_path, const char* thermo_path, chem_mechanism** out)
+{
+    g_last_error.clear();
+    if (!reactions_path || !thermo_path || !out) return set_error(CHEM_E_INVAL, "null argument");
+    *out = nullptr;
+    auto m = std::make_unique<chem_mechanism>();
+    std::string err;
+    if (int rc = parse_openfoam(reactions_path, thermo_path, m->data, err)) return set_error(rc, err);
+    return finish_load(std::move(m), out);
+}
+
 int chem_load_chemkin(const char* mech_path, const char* thermo_path, chem_mechanism** out)
 {
     g_last_error.clear();

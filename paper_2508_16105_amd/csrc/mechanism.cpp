@@ -194,7 +194,8 @@ struct Reader {
             return 0;
         }
         if (k == "species") {
-            if (t.size() != 3 || sp_index.count(t[1])) return fail(CHEM_E_PARSE, "bad species record");
+            // species <name> <composition> [W=<molar mass g/mol>]
+            if ((t.size() != 3 && t.size() != 4) || sp_index.count(t[1])) return fail(CHEM_E_PARSE, "bad species record");
             if (!m.reactions.empty()) return fail(CHEM_E_PARSE, "species must precede reactions");
             SpeciesData s;
             s.name = t[1];
@@ -209,6 +210,12 @@ struct Reader {
                 w += n * m.element_w[el_index[kv[0]]];
             }
             s.W = w * 1e-3;
+            if (t.size() == 4) {
+                double wg;
+                if (t[3].rfind("W=", 0) != 0 || !to_double(t[3].substr(2), wg) || !(wg > 0.0))
+                    return fail(CHEM_E_PARSE, "bad species weight '" + t[3] + "'");
+                s.W = wg * 1e-3;
+            }
             sp_index[s.name] = (int)m.species.size();
             m.species.push_back(std::move(s));
             return 0;

@@ -71,7 +71,13 @@ int parse_mechanism(const std::string& path, MechanismData& out, std::string& er
 int parse_chemkin(const std::string& path, const std::string& thermo_path, MechanismData& out,
                   std::string& err);
 
-// Checks shared by both readers once everything is read: species present, each
+// Read an OpenFOAM chemistry dictionary pair: the `reactions` file (species
+// list, reactions dictionary) and the `thermo` file (molWeight, janaf NASA-7
+// coefficients, element counts per species).
+int parse_openfoam(const std::string& reactions_path, const std::string& thermo_path, MechanismData& out,
+                   std::string& err);
+
+// Checks shared by the readers once everything is read: species present, each
 // with thermo data, and within CHEM_MAX_SPECIES.
 int validate_mechanism(MechanismData& m, std::string& err);
 

@@ -152,14 +152,15 @@ def test_adjoint_matches_oracle(chem, mechs, dev, key):
         assert np.max(np.abs(g - o)) <= max(1e-5 * np.max(np.abs(o)), 4 * spread[i]), i
 
 
-# ---------------- mechanisms read from CHEMKIN files ----------------
+# ---------------- mechanisms read from CHEMKIN files and OpenFOAM dictionaries ----------------
 
 @pytest.fixture(scope="module")
 def ck(chem, oracle_lib, tmp_path_factory):
-    """The hand-written CHEMKIN fixture (9 species, every reaction form, lane
-    form) and the m32x mechanism written as CHEMKIN with its thermo in a
-    separate file (wave-cooperative form), each with the oracle's reading of
-    the same files and the `chemmi-mech 1` text of that reading."""
+    """The hand-written CHEMKIN and OpenFOAM fixtures (9 species, every
+    reaction form each format has, lane form), m32x written as CHEMKIN with
+    its thermo in a separate file and m32s as OpenFOAM dictionaries
+    (wave-cooperative form), each with the oracle's reading of the same files
+    and the `chemmi-mech 1` text of that reading."""
     import pathlib
     from oracle import chemkin
     from workloads import gen_mech
@@ -169,13 +170,25 @@ def ck(chem, oracle_lib, tmp_path_factory):
     bare, thermo = d / "m32x.inp", d / "therm.dat"
     bare.write_text(gen_mech.to_chemkin(m, inline_thermo=False))
     thermo.write_text(gen_mech.thermo_chemkin(m))
+    from oracle import foam
+    fx = pathlib.Path(__file__).resolve().parent / "golden" / "foam_small"
+    fr, ft = fx / "reactions", fx / "thermo"
+    sr, st = d / "m32s.foam", d / "thermo"
+    r, t = gen_mech.to_openfoam(gen_mech.build_mechanism("m32s"))
+    sr.write_text(r)
+    st.write_text(t)
     return {"ck_small": (chem.Mechanism(fixture), oracle_lib.chemkin_mechanism(fixture),
                          chemkin.convert(fixture.read_text())),
             "m32x_ck": (chem.Mechanism(bare, thermo=thermo), oracle_lib.chemkin_mechanism(bare, thermo),
-                        chemkin.convert(bare.read_text(), thermo.read_text()))}
+                        chemkin.convert(bare.read_text(), thermo.read_text())),
+            "foam_small": (chem.Mechanism(fr, thermo=ft, fmt="openfoam"), oracle_lib.openfoam_mechanism(fr, ft),
+                           foam.convert(fr.read_text(), ft.read_text())),
+            "m32s_foam": (chem.Mechanism(sr, thermo=st, fmt="openfoam"), oracle_lib.openfoam_mechanism(sr, st),
+                          foam.convert(sr.read_text(), st.read_text()))}
 
 
-@pytest.mark.parametrize("key,n,dt", [("ck_small", 777, 1e-7), ("m32x_ck", 130, 1e-5)])
+@pytest.mark.parametrize("key,n,dt", [("ck_small", 777, 1e-7), ("m32x_ck", 130, 1e-5), ("foam_small", 777, 1e-7),
+                                      ("m32s_foam", 130, 1e-5)])
 def test_chemkin_mechanisms_match_oracle(chem, ck, dev, key, n, dt):
     gm, om, text = ck[key]
     T, p, Y = uniform_cells(text, n, 86)

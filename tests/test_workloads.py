@@ -6,7 +6,7 @@ from workloads import WORKLOADS, gen_mech, mech_path, mech_text
 from workloads import states
 
 
-@pytest.mark.parametrize("name", ["m9", "m13", "m32", "m13x", "m32x"])
+@pytest.mark.parametrize("name", ["m9", "m13", "m32", "m13x", "m32x", "m32s"])
 def test_committed_mechanisms_regenerate_exactly(name):
     assert gen_mech.build(name) == mech_text(name)
 
@@ -81,7 +81,8 @@ def test_workload_table():
 
 
 @pytest.mark.parametrize("name,base,nsri,nlind,nplog,nirrev", [("m13x", "m13", 1, 1, 4, 6),
-                                                               ("m32x", "m32", 5, 3, 12, 30)])
+                                                               ("m32x", "m32", 5, 3, 12, 30),
+                                                               ("m32s", "m32", 5, 3, 0, 30)])
 def test_variant_mechanisms_use_every_form(name, base, nsri, nlind, nplog, nirrev):
     rx = [l.split() for l in mech_text(name).splitlines() if l.startswith("reaction")]
     rb = [l.split() for l in mech_text(base).splitlines() if l.startswith("reaction")]

@@ -383,6 +383,71 @@ def to_chemkin(m: Mechanism, inline_thermo=True) -> str:
     return "\n".join(out) + "\n"
 
 
+# --------------------------------------------------------------------------
+# the same mechanisms as OpenFOAM chemistry dictionaries
+# --------------------------------------------------------------------------
+
+FOAM_TYPES = {"elementary": "Arrhenius", "thirdbody": "ThirdBodyArrhenius",
+              "lindemann": "ArrheniusLindemannFallOff", "troe": "ArrheniusTroeFallOff",
+              "sri": "ArrheniusSRIFallOff"}
+
+
+def _foam_side(d):
+    return " + ".join((f"{c}{s}" if c > 1 else s) for s, c in d.items())
+
+
+def to_openfoam(m: Mechanism) -> tuple[str, str]:
+    """(reactions, thermo) dictionary texts: A in (m^3/kmol)^(order-1)/s, Ta =
+    Ea/R in K, molWeight in kg/kmol.  PLOG has no OpenFOAM form here."""
+    names = [s for s, _ in m.species]
+    out = ["FoamFile { version 2.0; format ascii; class dictionary; object reactions; }",
+           f"elements {len(m.elements)} ( {' '.join(m.elements)} );",
+           f"species {len(names)} ( {' '.join(names)} );", "reactions", "{"]
+
+    def arr(indent, A, b, Ea, order):
+        return [f"{indent}A {_fmt(A * 1e-3 ** (order - 1))};", f"{indent}beta {_fmt(b)};",
+                f"{indent}Ta {_fmt(Ea * 1e3 / R_J)};"]
+
+    for i, rx in enumerate(m.reactions):
+        if rx.kind == "plog":
+            raise ValueError("PLOG reactions have no OpenFOAM form")
+        order = sum(rx.reac.values())
+        kind = ("irreversible" if rx.irrev else "reversible") + FOAM_TYPES[rx.kind]
+        out += [f"    un-named-reaction-{i}", "    {", f"        type {kind};",
+                f'        reaction "{_foam_side(rx.reac)} = {_foam_side(rx.prod)}";']
+        if rx.kind in ("elementary", "thirdbody"):
+            out += arr("        ", rx.A, rx.b, rx.Ea, order + (rx.kind == "thirdbody"))
+        else:
+            A0, b0, Ea0 = rx.low
+            out += ["        k0", "        {"] + arr("            ", A0, b0, Ea0, order + 1) + ["        }"]
+            out += ["        kInf", "        {"] + arr("            ", rx.A, rx.b, rx.Ea, order) + ["        }"]
+            out += ["        F", "        {"]
+            if rx.kind == "troe":
+                a, t3, t1, t2 = rx.troe
+                out += [f"            alpha {_fmt(a)};", f"            Tsss {_fmt(t3)};", f"            Ts {_fmt(t1)};",
+                        f"            Tss {_fmt(1e30 if t2 is None else t2)};"]
+            elif rx.kind == "sri":
+                out += [f"            {k} {_fmt(v)};" for k, v in zip("abcde", rx.sri)]
+            out += ["        }"]
+        if rx.kind != "elementary":
+            coeffs = " ".join(f"({s} {_fmt(rx.eff.get(s, 1.0))})" for s in names)
+            out += ["        thirdBodyEfficiencies", "        {", f"            coeffs {len(names)} ( {coeffs} );",
+                    "        }"]
+        out += ["    }"]
+    out += ["}", f"Tlow {_fmt(T_LOW)};", f"Thigh {_fmt(T_HIGH)};"]
+    th = ["FoamFile { version 2.0; format ascii; class dictionary; object thermo; }"]
+    for s, comp in m.species:
+        lo, hi = m.thermo[s]
+        W = sum(ATOMIC_WEIGHTS[e] * n for e, n in comp.items())
+        th += [s, "{", f"    specie {{ molWeight {_fmt(W)}; }}", "    thermodynamics", "    {",
+               f"        Tlow {_fmt(T_LOW)};", f"        Thigh {_fmt(T_HIGH)};", f"        Tcommon {_fmt(T_MID)};",
+               "        highCpCoeffs ( " + " ".join(_fmt(x) for x in hi) + " );",
+               "        lowCpCoeffs ( " + " ".join(_fmt(x) for x in lo) + " );", "    }",
+               "    transport { As 1.67212e-06; Ts 170.672; }",
+               "    elements { " + " ".join(f"{e} {n};" for e, n in comp.items()) + " }", "}"]
+    return "\n".join(out) + "\n", "\n".join(th) + "\n"
+
+
 def build_mechanism(name: str) -> Mechanism:
     if name in VARIANTS:
         kw = dict(VARIANTS[name])
@@ -395,7 +460,8 @@ def format_doc() -> str:
     return """chemmi-mech 1 -- one record per line, '#' starts a comment
   name <id>
   element <symbol> <atomic weight g/mol>
-  species <name> <element>=<count>[,<element>=<count>...]
+  species <name> <element>=<count>[,<element>=<count>...] [W=<molar mass g/mol>]
+      (without W the molar mass is the sum of the element weights)
   thermo <name> <Tlow> <Tmid> <Thigh> <a1..a7 for T<Tmid> <a1..a7 for T>=Tmid>
       NASA-7: cp/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4,
               H/RT = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T,
@@ -432,6 +498,8 @@ MECHS = {
 VARIANTS = {
     "m13x": dict(base="m13", seed=9012, n_sri=1, n_lindemann=1, n_plog=4, n_irrev=6),
     "m32x": dict(base="m32", seed=9013, n_sri=5, n_lindemann=3, n_plog=12, n_irrev=30),
+    # the same forms without PLOG, which OpenFOAM's dictionaries do not have
+    "m32s": dict(base="m32", seed=9014, n_sri=5, n_lindemann=3, n_plog=0, n_irrev=30),
 }
 
 # PLOG pressure sets (atm): around, inside and outside the 1-30 atm of the fields
