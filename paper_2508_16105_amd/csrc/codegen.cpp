@@ -336,11 +336,14 @@ struct Emitter {
                 o << "    const S iKc = chem_math::exp_poly(-lnKc);\n"
                      "    const S kr = kf * iKc;\n";
         }
-        o << "    const S pf = " << side_product(r.reac) << ";\n"
-             "    const S fwd = kf * pf;\n";
         if (rev_on)
-            o << "    const S pr = " << side_product(r.prod) << ";\n"
+            o << "    const S pf = " << side_product(r.reac) << ";\n"
+                 "    const S pr = " << side_product(r.prod) << ";\n"
+                 "    const S fwd = kf * pf;\n"
                  "    const S rev = kr * pr;\n";
+        else
+            o << "    const S pf = " << side_product(r.reac) << ";\n"
+                 "    const S fwd = kf * pf;\n";
         const std::string net = rev_on ? "(fwd - rev)" : "fwd";
         if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * " << net << ";\n";
         else o << "    const S q = " << (rev_on ? "fwd - rev" : "fwd") << ";\n";
@@ -738,6 +741,17 @@ std::string generate_wide_source(const MechanismData& m, const WideLayout& w)
          "// 1/T*, T**, -(1-alpha)/T***, -alpha/T*, [T** given]; SRI: a, -b, 1/c, b, ln d, e\n";
     dbls("RX_LOW", low);
     dbls("RX_TROE", troe);
+    {
+        bool sri = false, irrev = false;
+        for (const auto& r : m.reactions) {
+            sri = sri || r.kind == RxnKind::Sri;
+            irrev = irrev || !r.reversible;
+        }
+        o << "// reaction forms present (the kernels leave out the code of the absent ones)\n"
+             "constexpr bool HAS_PLOG = " << (nplog > 0 ? "true" : "false") << ";\n"
+             "constexpr bool HAS_SRI = " << (sri ? "true" : "false") << ";\n"
+             "constexpr bool HAS_IRREV = " << (irrev ? "true" : "false") << ";\n";
+    }
     o << "// PLOG tables: entries RX_PLOG_OFF[t] .. RX_PLOG_OFF[t+1] of (ln p, ln A SI, b, Ea/R)\n";
     ints("RX_PLOG_OFF", plog_off);
     dbls("RX_PLOG", plog);

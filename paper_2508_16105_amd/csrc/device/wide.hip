@@ -168,7 +168,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     // the slot's packed table entry (loaded by the caller ahead of time)
     // kind: 0 elementary, 1 third body, 2 Lindemann, 3 Troe, 4 SRI, 5 PLOG
     const int kind = (int)(pk[2] & 7u);
-    const bool irrev = (pk[2] >> 3) & 1u;
+    const bool irrev = mech::HAS_IRREV && ((pk[2] >> 3) & 1u);
     const int dnu = (int)((pk[2] >> 4) & 7u) - 4;
     const int er = (int)((pk[2] >> 7) & 511u) - 1;   // EFF row, or PLOG table for kind 5
     const int oj = (int)(pk[2] >> 16);
@@ -176,7 +176,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     S lnk = lnT * pb;
     lnk = fma(-iT, pe, lnk);
     lnk = lnk + par[oj];
-    if (kind == 5) {
+    if (mech::HAS_PLOG && kind == 5) {
         // the Arrhenius set at this pressure: linear in ln p between the
         // tabulated pressures, the end sets outside them
         const double lnp = log(p);
@@ -217,12 +217,12 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     }
     lnKc = fma((double)dnu, lnPRT, lnKc);
     S Mc = ctot;
-    if (er >= 0 && kind != 5) {
+    if (er >= 0 && !(mech::HAS_PLOG && kind == 5)) {
         for (int m = 0; m < NS; ++m) Mc = fma(mech::EFF[er * NS + m] - 1.0, L[mech::L_C + m], Mc);
     }
     S kf, kr, kinf = 0.0, r0 = 0.0, Fb = 1.0, ipr1 = 0.0, iKc = 0.0, Pr = 0.0;
     S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0, dlnF_T = 0.0;
-    if (kind < 2 || kind == 5) {
+    if (kind < 2 || (mech::HAS_PLOG && kind == 5)) {
         kf = chem_math::exp_poly(lnk);
         kr = irrev ? S(0.0) : chem_math::exp_poly(lnk - lnKc);
     } else {
@@ -261,7 +261,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
                 dlogFc_dT = dFc / (Fc * mech::LN10);
                 dlnF_T = mech::LN10 * dF_dFc * dlogFc_dT;
             }
-        } else if (kind == 4) {
+        } else if (mech::HAS_SRI && kind == 4) {
             // SRI: F = d [a exp(-b/T) + exp(-T/c)]^X T^e, X = 1 / (1 + log10(P_r)^2);
             // row: a, -b, 1/c, b, ln d, e
             const double* sr = &mech::RX_TROE[j * 8];
@@ -296,7 +296,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
         // -R T (sum nu H/RT) / (rho c_p); d q / d ln A of the main rate (k_inf
         // for falloff, through P_r = k0 [M] / k_inf)
         const S wsum = ws * irho - L[mech::L_W] * (mech::RU * T) * dH * rcpinv;
-        const S qA = (kind >= 2 && kind <= 4) ? q * (Pr * ipr1 - dF_dPr) : q;
+        const S qA = (kind >= 2 && !(mech::HAS_PLOG && kind == 5)) ? q * (Pr * ipr1 - dF_dPr) : q;
         const S gq = wsum * qA;
         g[0] += gq;
         g[1] += gq * lnT;
@@ -311,7 +311,7 @@ __device__ __forceinline__ void reaction(int j, const unsigned (&pk)[3], const d
     const S dlnkinf = (pb + pe * iT) * iT;
     S dlnkf = dlnkinf;
     S dM = kind == 1 ? fwd - rev : S(0.0);
-    if (kind >= 2 && kind <= 4) {
+    if (kind >= 2 && !(mech::HAS_PLOG && kind == 5)) {
         const double* lo = &mech::RX_LOW[j * 3];
         const S dlnk0 = (lo[1] + lo[2] * iT) * iT;
         dlnkf = dlnkinf + (ipr1 + dF_dPr) * (dlnk0 - dlnkinf) + dlnF_T;
