@@ -215,6 +215,30 @@ int chem_integrate_source(const chem_mechanism *m, int64_t ncell, double *T, con
                           double *qdot, const chem_options *opt, chem_stats *stats,
                           int32_t *cell_status, void *stream);
 
+/* One step of a minimal one-dimensional reactive-Euler solver around the
+   chemistry step (the flow equations of Appendix A with the chemistry as the
+   source terms of eqs. (20)-(21)): first-order finite volumes on a uniform
+   grid of ncell cells of width dx with the local Lax-Friedrichs flux and
+   reflecting ends, forward Euler in time, the chemistry advanced over the same
+   dt by chem_integrate_source (constant pressure, each cell's own state) and
+   entering as wdot_k in the species equations and qdot in the sensible-energy
+   equation.
+   U, U_out: device, [ncell][3 + ns] row-major conserved state rho (kg/m^3),
+   rho u (kg/(m^2 s)), rho E_s (J/m^3; E_s = e_s + u^2/2, e_s = sum_k Y_k
+   (h_k(T) - h_k(298.15 K)) - p/rho with h_k from the NASA-7 data), rho Y_k;
+   U_out must not be U.  T: device [ncell], in: a starting guess for the
+   temperature of U (<= 0: 1000 K), out: that temperature (Newton's method on
+   e_s).  rtol, atol, opt: as chem_integrate (opt->h0 must be NULL).  stats:
+   the chemistry step's.  max_cfl: NULL, or receives max over cells of
+   (|u| + c) dt / dx with the frozen sound speed c (the step is taken whatever
+   its value; it is stable for max_cfl <= 1).  Synchronises the stream.
+   Errors: CHEM_E_INVAL for bad arguments or a cell whose state gives no
+   temperature (nothing written then); CHEM_E_CELL_FAILED if a cell's
+   chemistry failed (its U_out entries are NaN). */
+int chem_euler1d_step(const chem_mechanism *m, int64_t ncell, double dx, double dt, const double *U,
+                      double *U_out, double *T, double rtol, double atol, const chem_options *opt,
+                      chem_stats *stats, double *max_cfl, void *stream);
+
 /* Integrate nfield independent fields (e.g. the cell sets of different mesh
    refinement levels) of sizes ncell[f] in one launch.  T, p, Y are host
    arrays of nfield device pointers.  With CHEM_FORM_PERSISTENT (the default

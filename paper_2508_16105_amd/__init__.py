@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN, ORDER_COST, ORDER_NATURAL
 
 __all__ = ["Mechanism", "integrate", "integrate_source", "integrate_batched", "integrate_adjoint", "eval_source",
-           "step_fixed", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
+           "step_fixed", "euler1d_step", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
            "FORM_PERSISTENT", "ORDER_COST", "ORDER_NATURAL", "version"]
 
 
@@ -150,6 +150,31 @@ def integrate_source(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAI
     _lib.check(rc, allow=(-6,) if allow_failed else ())
     out = (T, Y, wdot, qdot, s.as_dict() if s is not None else None)
     return out + (st,) if return_status else out
+
+
+def euler1d_step(mech: Mechanism, U, dx, dt, T=None, rtol=1e-8, atol=1e-12, *, form=FORM_PLAIN, stats=True,
+                 stream=None, allow_failed=False, **opts):
+    """One step of the 1D reactive-Euler driver (chem_euler1d_step).  U:
+    [ncell, 3 + ns] conserved state (rho, rho u, rho E_s, rho Y_k) on the GPU;
+    T: [ncell] temperature guess (None: 1000 K).  Returns (U_new, T of U,
+    stats dict or None, max CFL number)."""
+    torch = _torch()
+    n = U.shape[0]
+    _check_tensor(U, "U", (n, 3 + mech.ns))
+    if T is None:
+        T = torch.zeros(n, dtype=torch.float64, device=U.device)
+    else:
+        _check_tensor(T, "T", (n,))
+        T = T.clone()
+    Un = torch.empty_like(U)
+    s = _lib.Stats() if stats else None
+    o = _options(form=form, **opts)
+    cfl = C.c_double(0.0)
+    rc = _lib.lib().chem_euler1d_step(mech.h, n, float(dx), float(dt), _ptr(U), _ptr(Un), _ptr(T), float(rtol),
+                                      float(atol), C.byref(o), C.byref(s) if s is not None else None,
+                                      C.byref(cfl), _stream(stream))
+    _lib.check(rc, allow=(-6,) if allow_failed else ())
+    return Un, T, s.as_dict() if s is not None else None, cfl.value
 
 
 def integrate_batched(mech: Mechanism, Ts, ps, Ys, dt, rtol, atol, *, form=FORM_PERSISTENT,

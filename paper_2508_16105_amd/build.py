@@ -33,7 +33,8 @@ def embed_device_source():
     delim = "CHEMDEV"
     out = "// generated from device/*.hip by build.py; do not edit\n"
     for var, name in (("kMathSource", "math.hip"), ("kCommonSource", "common.hip"),
-                      ("kIntegratorSource", "integrator.hip"), ("kWideSource", "wide.hip")):
+                      ("kIntegratorSource", "integrator.hip"), ("kWideSource", "wide.hip"),
+                      ("kEulerSource", "euler.hip")):
         src = (CSRC / "device" / name).read_text()
         assert f"){delim}\"" not in src
         out += f"static const char {var}[] = R\"{delim}(\n{src}){delim}\";\n"

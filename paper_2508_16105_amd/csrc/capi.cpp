@@ -343,6 +343,25 @@ int chem_integrate_source(const chem_mechanism* mc, int64_t ncell, double* T, co
     return run_source(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, wdot, qdot, (hipStream_t)stream);
 }
 
+int chem_euler1d_step(const chem_mechanism* mc, int64_t ncell, double dx, double dt, const double* U,
+                      double* U_out, double* T, double rtol, double atol, const chem_options* opt,
+                      chem_stats* stats, double* max_cfl, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 1) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return set_error(CHEM_E_INVAL, "dx must be positive");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (int rc = check_device_ptrs({{U, "U"}, {U_out, "U_out"}, {T, "T"}})) return rc;
+    if (U == U_out) return set_error(CHEM_E_INVAL, "U_out must not be U");
+    Options o = resolve_options(opt);
+    if (o.h0) return set_error(CHEM_E_INVAL, "h0 is not used by the 1D driver");
+    std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
+    return run_euler1d(m, ncell, dx, dt, U, U_out, T, rtol, atol, o, stats, max_cfl, (hipStream_t)stream);
+}
+
 int chem_integrate_batched(const chem_mechanism* mc, int nfield, double* const* T,
                            const double* const* p, double* const* Y, const int64_t* ncell, double dt,
                            double rtol, double atol, const chem_options* opt, chem_stats* stats,

@@ -97,6 +97,8 @@ struct Emitter {
                                a[4] * T * T * T * T / 5 + a[5] / T;
             o << lit(kRu * T * hrt / sp.W) << (k + 1 < ns ? ", " : "};\n");
         }
+        o << "__constant__ double THERMO_TMID[NS] = {";
+        for (int k = 0; k < ns; ++k) o << lit(m.species[k].tmid) << (k + 1 < ns ? ", " : "};\n");
         o << "__constant__ double THERMO[NS][2][20] = {\n";
         for (int k = 0; k < ns; ++k) {
             o << "  {";

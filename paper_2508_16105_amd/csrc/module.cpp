@@ -16,12 +16,12 @@
 
 namespace chemmi {
 
-#include "_device_source.inc"   // kMathSource, kCommonSource, kIntegratorSource, kWideSource
+#include "_device_source.inc"   // kMathSource, kCommonSource, kIntegratorSource, kWideSource, kEulerSource
 
 std::string device_source(const std::string& mechanism_code, bool wide)
 {
     return std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kCommonSource) + "\n" +
-           std::string(wide ? kWideSource : kIntegratorSource);
+           std::string(wide ? kWideSource : kIntegratorSource) + "\n" + std::string(kEulerSource);
 }
 
 const std::vector<std::string>& compile_options()

@@ -89,6 +89,8 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_reduce_params", &d.f_rparams);
         rc = rc ? rc : load_function(d.module, "chem_source_begin", &d.f_src_begin);
         rc = rc ? rc : load_function(d.module, "chem_source_end", &d.f_src_end);
+        rc = rc ? rc : load_function(d.module, "chem_euler_prim", &d.f_euler_prim);
+        rc = rc ? rc : load_function(d.module, "chem_euler_update", &d.f_euler_update);
         if (!m->wide) {   // one-cell-per-lane module only
             rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
             rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
@@ -552,6 +554,53 @@ int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, dou
     }
     if (rc && rc != CHEM_E_CELL_FAILED) return rc;
     if (int rc2 = launch_1d(d->f_src_end, ncell, 256, &a, sizeof a, stream, "chem_source_end")) return rc2;
+    return rc;
+}
+
+int run_euler1d(chem_mechanism* m, int64_t ncell, double dx, double dt, const double* U, double* U_out,
+                double* T, double rtol, double atol, const Options& o, chem_stats* stats, double* max_cfl,
+                hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    const int ns = m->data.ns();
+    Scratch s(stream);
+    double *p, *Y, *u, *c, *wdot, *qdot, *cfl, *Tc;
+    int* bad;
+    if (int rc = s.alloc(&p, ncell, "euler p")) return rc;
+    if (int rc = s.alloc(&Y, (size_t)ncell * ns, "euler Y")) return rc;
+    if (int rc = s.alloc(&u, ncell, "euler u")) return rc;
+    if (int rc = s.alloc(&c, ncell, "euler c")) return rc;
+    if (int rc = s.alloc(&wdot, (size_t)ncell * ns, "euler wdot")) return rc;
+    if (int rc = s.alloc(&qdot, ncell, "euler qdot")) return rc;
+    if (int rc = s.alloc(&cfl, ncell, "euler cfl")) return rc;
+    if (int rc = s.alloc(&Tc, ncell, "euler T")) return rc;
+    if (int rc = s.alloc(&bad, 1, "euler flag")) return rc;
+    HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), stream), "clear flag");
+    struct {
+        const double* U; long n; double *T, *p, *Y, *u, *c; int* bad;
+    } pa{U, (long)ncell, T, p, Y, u, c, bad};
+    if (int rc = launch_1d(d->f_euler_prim, ncell, 256, &pa, sizeof pa, stream, "chem_euler_prim")) return rc;
+    int hbad = 0;
+    HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag copy");
+    HIPCHECK(hipStreamSynchronize(stream), "flag sync");
+    if (hbad) return set_error(CHEM_E_INVAL, "a cell's conserved state gives no temperature (rho <= 0 or no root)");
+    // the chemistry advances its own copy of T; Y is a scratch copy already
+    HIPCHECK(hipMemcpyAsync(Tc, T, sizeof(double) * ncell, hipMemcpyDeviceToDevice, stream), "copy T");
+    const int rc = run_source(m, ncell, Tc, p, Y, dt, rtol, atol, o, stats, nullptr, wdot, qdot, stream);
+    if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+    struct {
+        const double *U, *p, *u, *c, *wdot, *qdot; long n; double dt, dx; double *Unew, *cfl;
+    } ua{U, p, u, c, wdot, qdot, (long)ncell, dt, dx, U_out, cfl};
+    if (int rc2 = launch_1d(d->f_euler_update, ncell, 256, &ua, sizeof ua, stream, "chem_euler_update")) return rc2;
+    if (max_cfl) {
+        std::vector<double> h(ncell);
+        HIPCHECK(hipMemcpyAsync(h.data(), cfl, sizeof(double) * ncell, hipMemcpyDeviceToHost, stream), "cfl copy");
+        HIPCHECK(hipStreamSynchronize(stream), "cfl sync");
+        double mx = 0.0;
+        for (double x : h) mx = std::max(mx, x);
+        *max_cfl = mx;
+    }
     return rc;
 }
 

@@ -156,7 +156,8 @@ struct DeviceState {
     hipFunction_t f_plain = nullptr, f_eval = nullptr, f_fixed = nullptr, f_zero = nullptr,
                   f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr,
                   f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr, f_adjoint = nullptr,
-                  f_rparams = nullptr, f_src_begin = nullptr, f_src_end = nullptr;
+                  f_rparams = nullptr, f_src_begin = nullptr, f_src_end = nullptr, f_euler_prim = nullptr,
+                  f_euler_update = nullptr;
     double* par = nullptr;               // 3 * nr device doubles
     uint64_t par_version = 0;
     unsigned long long* stats = nullptr; // 4 counters
@@ -226,6 +227,13 @@ int run_persistent(chem_mechanism* m, const FieldView* fields, int nfield, doubl
 // Integration with the operator-split source terms (see chem_integrate_source):
 // the initial density and state are kept in wdot/qdot, the cells integrated in
 // the form o asks for, and the mean rates over the step written back.
+// One step of the 1D reactive-Euler driver: primitive recovery, the coupled
+// chemistry step over dt (run_source), and the finite-volume update with the
+// chemistry's source terms; *max_cfl gets the largest (|u| + c) dt / dx.
+int run_euler1d(chem_mechanism* m, int64_t ncell, double dx, double dt, const double* U, double* U_out,
+                double* T, double rtol, double atol, const Options& o, chem_stats* stats, double* max_cfl,
+                hipStream_t stream);
+
 int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
                double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
                double* wdot, double* qdot, hipStream_t stream);

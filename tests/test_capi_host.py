@@ -88,4 +88,10 @@ def test_params_roundtrip_and_argument_errors(L):
                                    1e-12, host.ctypes.data, host.ctypes.data, None, None, None, None) == -1
     assert L.chem_integrate_source(None, 10, None, None, None, 1e-8, 1e-8, 1e-12, None, None, None, None,
                                    None, None) == -1
+    # the 1D driver: the same checks before any launch
+    assert L.chem_euler1d_step(h, 0, 1e-4, 1e-9, None, None, None, 1e-8, 1e-12, None, None, None, None) == -1
+    assert L.chem_euler1d_step(h, 8, 0.0, 1e-9, None, None, None, 1e-8, 1e-12, None, None, None, None) == -1
+    assert L.chem_euler1d_step(h, 8, 1e-4, -1.0, None, None, None, 1e-8, 1e-12, None, None, None, None) == -1
+    assert L.chem_euler1d_step(h, 8, 1e-4, 1e-9, host.ctypes.data, host.ctypes.data, host.ctypes.data, 1e-8,
+                               1e-12, None, None, None, None) == -1
     L.chem_free_mechanism(h)

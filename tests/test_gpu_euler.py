@@ -1,0 +1,152 @@
+"""GPU 1D reactive-Euler driver (chem_euler1d_step, row F1's driver) against
+the oracle's step (oracle/euler1d.py): per-step parity on a reacting tube;
+conservation of mass, elements and total energy over many GPU steps in a
+closed tube; and, for plausibility only (no reference data), a detonation
+initiated by a hot high-pressure section that settles at the Chapman-Jouguet
+speed of its thermo.
+
+Per-step bars: rho and rho u to 1e-10 relative (flux arithmetic and the
+recovered T, both converged to round-off); rho Y_k to 1e-8 rho and rho E_s to
+1e-8 of the cell's chemical-energy scale (sum_k |h_k(298)| rho), since they
+take the chemistry's Delta Y, which agrees to the integration parity bar of
+1e-8."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from workloads import mech_path, mech_text  # noqa: E402
+from workloads.states import parse_species, stoich_air  # noqa: E402
+
+PATM = 101325.0
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def m9(oracle_lib):
+    import paper_2508_16105_amd as chem
+    return chem, chem.Mechanism(mech_path("m9")), oracle_lib.Mechanism(mech_path("m9"))
+
+
+def _tube(om, n, hot=0.15, T_hot=2800.0, p_hot=30.0):
+    from oracle import euler1d as E
+    names, W = parse_species(mech_text("m9"))
+    Y = np.tile(stoich_air(names, W), (n, 1))
+    x = (np.arange(n) + 0.5) / n
+    T = np.where(x < hot, T_hot, 300.0)
+    p = np.where(x < hot, p_hot * PATM, PATM)
+    return E.conserved(om, T, p, Y, np.zeros(n)), T
+
+
+def _g(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def test_step_matches_oracle(m9, dev):
+    from oracle import euler1d as E
+    chem, gm, om = m9
+    n, dx, dt = 96, 1e-4, 2e-9
+    U, T = _tube(om, n)
+    href, _ = E._species_h_cp(om, E.T_REF)
+    for k in range(4):
+        Ug, Tg, st, cfl = chem.euler1d_step(gm, _g(U, dev), dx, dt, T=_g(T, dev))
+        Uo, To, w, q = E.step(om, U, dx, dt, T_guess=T)
+        Ug, Tg = Ug.cpu().numpy(), Tg.cpu().numpy()
+        assert st["failed"] == 0 and 0.0 < cfl < 1.0
+        assert np.allclose(Tg, To, rtol=1e-11, atol=0)
+        for v in (0, 1):
+            assert np.all(np.abs(Ug[:, v] - Uo[:, v]) <= 1e-10 * np.abs(Uo[:, 0:3]).max(axis=1)), (k, v)
+        rho = Uo[:, 0]
+        assert np.all(np.abs(Ug[:, 3:] - Uo[:, 3:]) <= 1e-8 * rho[:, None]), k
+        scale = np.abs(Uo[:, 3:]) @ np.abs(href)
+        assert np.all(np.abs(Ug[:, 2] - Uo[:, 2]) <= 1e-8 * scale + 1e-10 * np.abs(Uo[:, 2])), k
+        U, T = Uo, To                       # next step from the oracle's state
+
+
+def _totals(om, U, dx):
+    from oracle import euler1d as E
+    href, _ = E._species_h_cp(om, E.T_REF)
+    comps = [dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in l.split()[2].split(","))
+             for l in mech_text("m9").splitlines() if l.startswith("species")]
+    W = om.weights()
+    el = [dx * (U[:, 3:].sum(axis=0) @ np.array([c.get(e, 0) / w for c, w in zip(comps, W)])) for e in "HON"]
+    return np.array([dx * U[:, 0].sum(), dx * (U[:, 2].sum() + (U[:, 3:] @ href).sum())] + el)
+
+
+def _run(chem, gm, U, T, dx, dt, steps, dev, every=0):
+    Ug, Tg = _g(U, dev), _g(T, dev)
+    fronts = []
+    for s in range(steps):
+        Ug, Tg, st, cfl = chem.euler1d_step(gm, Ug, dx, dt, T=Tg)
+        assert st["failed"] == 0 and cfl < 0.8, (s, cfl)
+        if every and (s + 1) % every == 0:
+            fronts.append((s + 1, Tg.cpu().numpy()))
+    return Ug.cpu().numpy(), Tg.cpu().numpy(), fronts
+
+
+def test_closed_tube_conserves_mass_elements_energy(m9, dev):
+    chem, gm, om = m9
+    n, dx, dt = 400, 5e-5, 5e-9
+    U, T = _tube(om, n)
+    t0 = _totals(om, U, dx)
+    U1, T1, _ = _run(chem, gm, U, T, dx, dt, 200, dev)
+    t1 = _totals(om, U1, dx)
+    assert np.all(np.abs(t1 - t0) <= 1e-11 * np.abs(t0)), (t0, t1)
+    assert T1.max() > 2000.0
+
+
+def test_detonation_runs_at_the_cj_speed(dev, oracle_lib, write_mech):
+    """Plausibility (no reference data): with one irreversible global reaction
+    2 H2 + O2 => 2 H2O and H2O's standard formation enthalpy (the seeded
+    mechanisms' random rates do not ignite H2-air within 200 us), a hot
+    high-pressure section at the closed left end (3000 K, 40 atm) sets off a
+    detonation in stoichiometric H2-air at 300 K, 1 atm that settles at the
+    Chapman-Jouguet speed of the same thermo (oracle: tangency of the Rayleigh
+    line and the complete-reaction Hugoniot), with the gas behind it burnt."""
+    import paper_2508_16105_amd as chem
+    from oracle import euler1d as E
+    from workloads import tiny
+    path = write_mech(tiny.global_h2_air(), "global.mech")
+    gm, om = chem.Mechanism(path), oracle_lib.Mechanism(path)
+    W = om.weights()
+    x0 = np.array([2.0, 1.0, 0.0, 3.76])
+    Y0 = x0 * W / (x0 @ W)
+    xb = np.array([0.0, 0.0, 2.0, 3.76])
+    Yb = xb * W / (xb @ W)
+    D_cj, T_cj, p_cj = E.cj_speed(om, 300.0, PATM, Y0, Yb)
+    n, dx, dt = 2400, 2.5e-5, 2e-9
+    x = (np.arange(n) + 0.5) * dx
+    hot = x < 0.05 * n * dx
+    T = np.where(hot, 3000.0, 300.0)
+    p = np.where(hot, 40 * PATM, PATM)
+    U = E.conserved(om, T, p, np.tile(Y0, (n, 1)), np.zeros(n))
+    U1, T1, fronts = _run(chem, gm, U, T, dx, dt, 10000, dev, every=1000)
+    xf = np.array([dx * (np.nonzero(Tf > 1000.0)[0].max() + 1) for _, Tf in fronts])
+    t = np.array([s * dt for s, _ in fronts])
+    v = np.diff(xf) / np.diff(t)
+    print(f"front at {np.round(xf * 1e3, 2)} mm; speed {np.round(v, 0)} m/s; D_CJ {D_cj:.1f} m/s")
+    late = v[len(v) // 2:]
+    assert np.all(np.abs(late / D_cj - 1.0) < 0.05), (late, D_cj)
+    behind = (T1 > 2000.0) & (x < xf[-1] - 2e-3)
+    assert behind.sum() > 200 and np.median(U1[behind, 5] / U1[behind, 0]) > 0.9 * Yb[2]
+
+
+def test_argument_and_state_errors(m9, dev):
+    chem, gm, om = m9
+    U, T = _tube(om, 8)
+    Ug = _g(U, dev)
+    from paper_2508_16105_amd import _lib
+    L = _lib.lib()
+    Tg = _g(T, dev)
+    assert L.chem_euler1d_step(gm.h, 8, 1e-4, 1e-9, Ug.data_ptr(), Ug.data_ptr(), Tg.data_ptr(), 1e-8, 1e-12,
+                               None, None, None, None) == -1                         # U_out is U
+    bad = U.copy()
+    bad[3, 0] = -1.0                                                               # negative density
+    with pytest.raises(chem.ChemError):
+        chem.euler1d_step(gm, _g(bad, dev), 1e-4, 1e-9)

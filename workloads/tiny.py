@@ -96,3 +96,18 @@ def _abn2(reactions):
                 [_thermo("A", 2.5, 20000.0, 2.0), _thermo("B", 2.5, 25000.0, 3.0),
                  _thermo("AB", 3.5, 4000.0, 4.0), _thermo("N2", 3.5, -1043.5, 4.0)],
                 reactions)
+
+
+def global_h2_air(A=3.6e18, b=0.0, Ea=120.0):
+    """One irreversible global reaction 2 H2 + O2 => 2 H2O with inert N2, for
+    the 1D driver's detonation run: constant-cp thermo (cp/R: H2 3.5, O2 3.7,
+    H2O 4.5, N2 3.6) with H2O's standard formation enthalpy -241.8 kJ/mol at
+    298.15 K (a6 = h_f/R - a1 298.15), the others zero.  A in cm^6/(mol^2 s),
+    Ea in kJ/mol."""
+    R = 8.314462618
+    hf = -241.8e3 / R
+    return text([("H", 1.008), ("O", 15.999), ("N", 14.007)],
+                [("H2", "H=2"), ("O2", "O=2"), ("H2O", "H=2,O=1"), ("N2", "N=2")],
+                [_thermo("H2", 3.5, -3.5 * 298.15, 0.0), _thermo("O2", 3.7, -3.7 * 298.15, 0.0),
+                 _thermo("H2O", 4.5, hf - 4.5 * 298.15, 0.0), _thermo("N2", 3.6, -3.6 * 298.15, 0.0)],
+                [f"reaction elementary H2=2,O2=1 H2O=2 {_fmt(A)} {_fmt(b)} {_fmt(Ea)} irrev"])
