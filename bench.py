@@ -28,6 +28,7 @@ RODAS4_STAGES = 6
 KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
                   "paper_2508_16105_amd/csrc/device/common.hip",
                   "paper_2508_16105_amd/csrc/device/math.hip",
+                  "paper_2508_16105_amd/csrc/device/euler.hip",
                   "paper_2508_16105_amd/csrc/codegen.cpp",
                   "paper_2508_16105_amd/csrc/module.cpp"]
 TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
@@ -256,6 +257,40 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
     return res
 
 
+def euler_leg(chem, torch, dev, n=65536, steps=20, warmup=3):
+    """The 1D reactive-Euler driver (chem_euler1d_step): a detonation tube of
+    n cells of 25 um with the one-step global H2-air reaction (3000 K / 40 atm
+    driver over the first 5 %, stoichiometric H2-air at 300 K / 1 atm), dt =
+    2 ns; time per driver step (primitive recovery, coupled chemistry step,
+    flux update, and the host synchronisation the step does for its checks)."""
+    import tempfile
+    from workloads import tiny
+    from workloads.states import parse_species, stoich_air
+    text = tiny.global_h2_air()
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "global.mech")
+        with open(path, "w") as f:
+            f.write(text)
+        gm = chem.Mechanism(path)
+    names, W = parse_species(text)
+    Y0 = stoich_air(names, W)
+    dx, dt = 2.5e-5, 2e-9
+    hot = np.arange(n) < n // 20
+    g = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    T = g(np.where(hot, 3000.0, 300.0))
+    U = chem.euler1d_init(gm, T, g(np.where(hot, 40 * 101325.0, 101325.0)), g(np.tile(Y0, (n, 1))))
+    for _ in range(warmup):
+        U, T, _, cfl = chem.euler1d_step(gm, U, dx, dt, T=T, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, T, _, cfl = chem.euler1d_step(gm, U, dx, dt, T=T, stats=False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"cells": n, "steps": steps, "ms_per_step": ms, "cell_steps_per_s": n / (ms * 1e-3),
+            "mechanism": "one-step global H2-air (4 species)", "dt": dt, "dx": dx, "max_cfl": cfl}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +302,7 @@ def main():
     ap.add_argument("--forms", default="persistent,persistent_adjacent,persistent_history,"
                                         "persistent_natural,plain")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-euler", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--no-big", action="store_true")
     ap.add_argument("--big-only", action="store_true")
@@ -429,6 +465,8 @@ def main():
         sms = 1e3 * (time.perf_counter() - t0) / args.steps
         line["source_mode"] = {"form": "persistent", "ms_per_step": sms,
                                "over_integrate": sms / results["persistent"]["ms_per_step"]}
+    if not args.no_euler:
+        line["euler1d"] = euler_leg(chem, torch, dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
     if not args.no_amr:   # the 13-species per-field plain launches (~80 s) only with --amr-only

@@ -215,6 +215,13 @@ int chem_integrate_source(const chem_mechanism *m, int64_t ncell, double *T, con
                           double *qdot, const chem_options *opt, chem_stats *stats,
                           int32_t *cell_status, void *stream);
 
+/* The conserved state of the 1D driver (layout as chem_euler1d_step's U)
+   from temperature T, pressure p (Pa), mass fractions Y [ncell][ns] and
+   velocity u (NULL: at rest), all device pointers: rho = p / (R T sum Y/W),
+   rho E_s = rho (e_s(T) + u^2/2).  Errors: CHEM_E_INVAL for bad arguments. */
+int chem_euler1d_init(const chem_mechanism *m, int64_t ncell, const double *T, const double *p,
+                      const double *Y, const double *u, double *U, void *stream);
+
 /* One step of a minimal one-dimensional reactive-Euler solver around the
    chemistry step (the flow equations of Appendix A with the chemistry as the
    source terms of eqs. (20)-(21)): first-order finite volumes on a uniform

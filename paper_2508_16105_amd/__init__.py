@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN, ORDER_COST, ORDER_NATURAL
 
 __all__ = ["Mechanism", "integrate", "integrate_source", "integrate_batched", "integrate_adjoint", "eval_source",
-           "step_fixed", "euler1d_step", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
+           "step_fixed", "euler1d_init", "euler1d_step", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
            "FORM_PERSISTENT", "ORDER_COST", "ORDER_NATURAL", "version"]
 
 
@@ -150,6 +150,21 @@ def integrate_source(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAI
     _lib.check(rc, allow=(-6,) if allow_failed else ())
     out = (T, Y, wdot, qdot, s.as_dict() if s is not None else None)
     return out + (st,) if return_status else out
+
+
+def euler1d_init(mech: Mechanism, T, p, Y, u=None, stream=None):
+    """The 1D driver's conserved state [ncell, 3 + ns] from T, p, Y [ncell,
+    ns] and u (None: at rest), on the GPU (chem_euler1d_init)."""
+    torch = _torch()
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    if u is not None:
+        _check_tensor(u, "u", (n,))
+    U = torch.empty((n, 3 + mech.ns), dtype=torch.float64, device=T.device)
+    _lib.check(_lib.lib().chem_euler1d_init(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), _ptr(u), _ptr(U),
+                                            _stream(stream)))
+    return U
 
 
 def euler1d_step(mech: Mechanism, U, dx, dt, T=None, rtol=1e-8, atol=1e-12, *, form=FORM_PLAIN, stats=True,

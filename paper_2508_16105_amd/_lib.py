@@ -16,7 +16,7 @@ ORDER_COST, ORDER_NATURAL = 1, 2
 
 EXPORTS = ["chem_load_mechanism", "chem_load_chemkin", "chem_load_openfoam", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
            "chem_set_params", "chem_eval_source", "chem_step_fixed", "chem_integrate",
-           "chem_integrate_source", "chem_euler1d_step", "chem_integrate_batched", "chem_integrate_adjoint",
+           "chem_integrate_source", "chem_euler1d_init", "chem_euler1d_step", "chem_integrate_batched", "chem_integrate_adjoint",
            "chem_last_error", "chem_version"]
 
 
@@ -64,6 +64,7 @@ def lib():
         L.chem_step_fixed.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
         L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, C.POINTER(Options),
                                      C.POINTER(Stats), vp, vp, vp, vp]
+        L.chem_euler1d_init.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.chem_euler1d_step.argtypes = [vp, i64, dbl, dbl, vp, vp, vp, dbl, dbl, C.POINTER(Options),
                                         C.POINTER(Stats), C.POINTER(dbl), vp]
         L.chem_integrate_source.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, C.POINTER(Options),

@@ -343,6 +343,20 @@ int chem_integrate_source(const chem_mechanism* mc, int64_t ncell, double* T, co
     return run_source(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, wdot, qdot, (hipStream_t)stream);
 }
 
+int chem_euler1d_init(const chem_mechanism* mc, int64_t ncell, const double* T, const double* p,
+                      const double* Y, const double* u, double* U, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {U, "U"}})) return rc;
+    if (u && !is_device_ptr(u)) return set_error(CHEM_E_INVAL, "u is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
+    return run_euler1d_init(m, ncell, T, p, Y, u, U, (hipStream_t)stream);
+}
+
 int chem_euler1d_step(const chem_mechanism* mc, int64_t ncell, double dx, double dt, const double* U,
                       double* U_out, double* T, double rtol, double atol, const chem_options* opt,
                       chem_stats* stats, double* max_cfl, void* stream)

@@ -86,6 +86,39 @@ extern "C" __global__ void __launch_bounds__(256) chem_euler_prim(PrimArgs a)
     for (int k = 0; k < mech::NS; ++k) a.Y[i * mech::NS + k] = Y[k];
 }
 
+struct InitArgs {
+    const double* T;
+    const double* p;
+    const double* Y;   // [ncell][NS]
+    const double* u;   // may be null (gas at rest)
+    long ncell;
+    double* U;         // [ncell][NV]
+};
+
+// The conserved state of cells given T, p, Y and u.
+extern "C" __global__ void __launch_bounds__(256) chem_euler_init(InitArgs a)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ncell) return;
+    double Y[mech::NS];
+    double sig = 0.0;
+    for (int k = 0; k < mech::NS; ++k) {
+        Y[k] = a.Y[i * mech::NS + k];
+        sig = fma(Y[k], mech::MWTAB[mech::NS + k], sig);
+    }
+    const double Rm = mech::RU * sig;
+    const double T = a.T[i];
+    const double rho = a.p[i] / (Rm * T);
+    const double u = a.u ? a.u[i] : 0.0;
+    double es, cv;
+    energy(Y, T, Rm, es, cv);
+    double* U = a.U + i * NV;
+    U[0] = rho;
+    U[1] = rho * u;
+    U[2] = rho * (es + 0.5 * u * u);
+    for (int k = 0; k < mech::NS; ++k) U[3 + k] = rho * Y[k];
+}
+
 struct UpdateArgs {
     const double* U;
     const double* p;

@@ -91,6 +91,7 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_source_end", &d.f_src_end);
         rc = rc ? rc : load_function(d.module, "chem_euler_prim", &d.f_euler_prim);
         rc = rc ? rc : load_function(d.module, "chem_euler_update", &d.f_euler_update);
+        rc = rc ? rc : load_function(d.module, "chem_euler_init", &d.f_euler_init);
         if (!m->wide) {   // one-cell-per-lane module only
             rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
             rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
@@ -555,6 +556,17 @@ int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, dou
     if (rc && rc != CHEM_E_CELL_FAILED) return rc;
     if (int rc2 = launch_1d(d->f_src_end, ncell, 256, &a, sizeof a, stream, "chem_source_end")) return rc2;
     return rc;
+}
+
+int run_euler1d_init(chem_mechanism* m, int64_t ncell, const double* T, const double* p, const double* Y,
+                     const double* u, double* U, hipStream_t stream)
+{
+    DeviceState* d;
+    if (int rc = device_state(m, stream, &d)) return rc;
+    struct {
+        const double *T, *p, *Y, *u; long n; double* U;
+    } a{T, p, Y, u, (long)ncell, U};
+    return launch_1d(d->f_euler_init, ncell, 256, &a, sizeof a, stream, "chem_euler_init");
 }
 
 int run_euler1d(chem_mechanism* m, int64_t ncell, double dx, double dt, const double* U, double* U_out,

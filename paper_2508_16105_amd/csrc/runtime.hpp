@@ -157,7 +157,7 @@ struct DeviceState {
                   f_stats = nullptr, f_persistent = nullptr, f_reset = nullptr, f_gather = nullptr,
                   f_okey = nullptr, f_oscan = nullptr, f_oscatter = nullptr, f_adjoint = nullptr,
                   f_rparams = nullptr, f_src_begin = nullptr, f_src_end = nullptr, f_euler_prim = nullptr,
-                  f_euler_update = nullptr;
+                  f_euler_update = nullptr, f_euler_init = nullptr;
     double* par = nullptr;               // 3 * nr device doubles
     uint64_t par_version = 0;
     unsigned long long* stats = nullptr; // 4 counters
@@ -227,6 +227,10 @@ int run_persistent(chem_mechanism* m, const FieldView* fields, int nfield, doubl
 // Integration with the operator-split source terms (see chem_integrate_source):
 // the initial density and state are kept in wdot/qdot, the cells integrated in
 // the form o asks for, and the mean rates over the step written back.
+// Conserved 1D state U from T, p, Y and u (u may be null).
+int run_euler1d_init(chem_mechanism* m, int64_t ncell, const double* T, const double* p, const double* Y,
+                     const double* u, double* U, hipStream_t stream);
+
 // One step of the 1D reactive-Euler driver: primitive recovery, the coupled
 // chemistry step over dt (run_source), and the finite-volume update with the
 // chemistry's source terms; *max_cfl gets the largest (|u| + c) dt / dx.

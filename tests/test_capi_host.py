@@ -94,4 +94,7 @@ def test_params_roundtrip_and_argument_errors(L):
     assert L.chem_euler1d_step(h, 8, 1e-4, -1.0, None, None, None, 1e-8, 1e-12, None, None, None, None) == -1
     assert L.chem_euler1d_step(h, 8, 1e-4, 1e-9, host.ctypes.data, host.ctypes.data, host.ctypes.data, 1e-8,
                                1e-12, None, None, None, None) == -1
+    assert L.chem_euler1d_init(h, 0, None, None, None, None, None, None) == 0
+    assert L.chem_euler1d_init(h, 8, host.ctypes.data, host.ctypes.data, host.ctypes.data, None,
+                               host.ctypes.data, None) == -1
     L.chem_free_mechanism(h)

@@ -48,6 +48,20 @@ def _g(a, dev):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
 
 
+def test_init_matches_oracle(m9, dev):
+    """chem_euler1d_init: the conserved state of given (T, p, Y, u)."""
+    from oracle import euler1d as E
+    chem, gm, om = m9
+    from workloads.states import uniform_cells
+    T, p, Y = uniform_cells(mech_text("m9"), 300, 91)
+    u = np.random.default_rng(92).uniform(-800.0, 800.0, 300)
+    Ug = chem.euler1d_init(gm, _g(T, dev), _g(p, dev), _g(Y, dev), _g(u, dev)).cpu().numpy()
+    Uo = E.conserved(om, T, p, Y, u)
+    assert np.allclose(Ug, Uo, rtol=1e-12, atol=1e-12 * np.abs(Uo).max(axis=1, keepdims=True).max())
+    U0 = chem.euler1d_init(gm, _g(T, dev), _g(p, dev), _g(Y, dev)).cpu().numpy()
+    assert np.all(U0[:, 1] == 0.0)
+
+
 def test_step_matches_oracle(m9, dev):
     from oracle import euler1d as E
     chem, gm, om = m9
