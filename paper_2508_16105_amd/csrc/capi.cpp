@@ -279,7 +279,6 @@ int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, co
     auto* m = const_cast<chem_mechanism*>(mc);
     if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
     if (int rc = check_tolerances(h, rtol, atol)) return rc;
-    if (m->wide) return set_error(CHEM_E_UNSUPPORTED, "fixed steps are not built for the wave-cooperative form");
     if (ncell == 0) return CHEM_OK;
     if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}, {ynew, "ynew"},
                                     {errnorm, "errnorm"}, {ok, "ok"}}))
@@ -289,6 +288,9 @@ int chem_step_fixed(const chem_mechanism* mc, int64_t ncell, const double* T, co
     DeviceState* d;
     if (int rc = device_state(m, (hipStream_t)stream, &d)) return rc;
     FixedStepArgs a{d->par, T, p, Y, (long)ncell, h, ynew, errnorm, rtol, atol, ok};
+    if (m->wide)
+        return launch_1d(d->f_fixed, ncell * m->layout.G, 64, &a, sizeof a, (hipStream_t)stream, "chem_fixed_step",
+                         m->layout.lds_bytes());
     return launch_1d(d->f_fixed, ncell, 64, &a, sizeof a, (hipStream_t)stream, "chem_fixed_step",
                      d->stage_lds(64));
 }

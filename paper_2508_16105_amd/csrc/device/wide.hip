@@ -995,6 +995,40 @@ extern "C" __global__ void __launch_bounds__(64) chem_eval(EvalArgs a)
     if (i < N) a.f[cell * N + i] = f;
 }
 
+// ---- one fixed RODAS4 step of size h per cell (y_new and the error norm) ----
+struct FixedStepArgs {
+    const double* par;
+    const double* T;
+    const double* p;
+    const double* Y;
+    long ncell;
+    double h;
+    double* ynew;   // [ncell][N]
+    double* err;    // [ncell]
+    double rtol, atol;
+    int* ok;
+};
+
+extern "C" __global__ void __launch_bounds__(64) chem_fixed_step(FixedStepArgs a)
+{
+    using namespace chemw;
+    extern __shared__ double lds[];
+    const int grp = (int)threadIdx.x / G;
+    const long cell = (long)blockIdx.x * CPW + grp;
+    if (cell >= a.ncell) return;
+    double* L = lds + grp * mech::LDS_CELL;
+    const int i = gl();
+    const double p = a.p[cell];
+    const double yi = i == 0 ? a.T[cell] : (i <= NS ? a.Y[cell * NS + i - 1] : 0.0);
+    double yn, en;
+    const bool ok = ros_step(a.par, p, 1.0 / p, yi, a.h, a.rtol, a.atol, L, L + mech::L_J, yn, en);
+    if (i < N) a.ynew[cell * N + i] = yn;
+    if (i == 0) {
+        a.err[cell] = en;
+        a.ok[cell] = ok ? 1 : 0;
+    }
+}
+
 // ---- persistent form: groups pull cells from one global counter ----
 // Cells of all fields form one index space [0, total); each group takes the
 // next cell when its current one is done, so no group idles while cells

@@ -92,8 +92,8 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         rc = rc ? rc : load_function(d.module, "chem_euler_prim", &d.f_euler_prim);
         rc = rc ? rc : load_function(d.module, "chem_euler_update", &d.f_euler_update);
         rc = rc ? rc : load_function(d.module, "chem_euler_init", &d.f_euler_init);
+        rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
         if (!m->wide) {   // one-cell-per-lane module only
-            rc = rc ? rc : load_function(d.module, "chem_fixed_step", &d.f_fixed);
             rc = rc ? rc : load_function(d.module, "chem_gather_sample", &d.f_gather);
             rc = rc ? rc : load_function(d.module, "chem_order_key", &d.f_okey);
             rc = rc ? rc : load_function(d.module, "chem_order_scan", &d.f_oscan);
