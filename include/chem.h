@@ -106,7 +106,9 @@ typedef struct {
     double kernel_ms;           /* device time of the integration launches */
 } chem_stats;
 
-/* Read and validate a `chemmi-mech 1` file (format: NASA-7 species thermo;
+/* Read and validate a `chemmi-mech 1` file, or a CHEMKIN file with its thermo
+   inline (recognised by a first keyword ELEMENTS/ELEM/SPECIES/SPEC/THERMO; read
+   as chem_load_chemkin does) (native format: NASA-7 species thermo;
    elementary, third-body, Lindemann, Troe, SRI and pressure-tabulated (PLOG)
    reactions, reversible at k_f / K_c or irreversible; the "reactions and
    thermo data" of Sec. 2.1), check the element balance of every reaction
