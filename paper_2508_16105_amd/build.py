@@ -94,7 +94,7 @@ def prebuild_mechanisms(builds=None):
 
 
 def prune_cache(since):
-    """Drop cached code objects that this build did not produce or use."""
+    """Drop cached code objects neither produced nor used since `since`."""
     for f in (PKG / "kcache").glob("*.co"):
         if f.stat().st_mtime < since:
             f.unlink()
