@@ -247,3 +247,21 @@ def test_batched_fields_with_every_form(chem, mechs, dev):
     for (T, p, Y), Tb, Yb in zip(fields, Ts, Ys):
         Tp, Yp, _ = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), DT["m13x"], RTOL, ATOL)
         assert torch.equal(Tp, Tb) and torch.equal(Yp, Yb)
+
+
+@pytest.mark.parametrize("key,side", [("m13x", 512), ("m32x", 256)])
+def test_rde_field_with_every_form_sampled(chem, mechs, dev, key, side):
+    """A whole RDE-shaped field (fresh, front and burnt regions; 1-30 atm, so
+    inside the PLOG tables) in the persistent form at dt = 5 ns, with 32 cells
+    of every region against the oracle."""
+    from workloads.states import rde_field
+    gm, om = mechs[key]
+    T, p, Y, reg = rde_field(mech_text(key), side, side, 107)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL,
+                                   form=chem.FORM_PERSISTENT)
+    assert stats["failed"] == 0 and stats["cells"] == side * side
+    rng = np.random.default_rng(108)
+    idx = np.concatenate([rng.choice(np.nonzero(reg == r)[0], 32, replace=False) for r in (0, 1, 2)])
+    To, Yo, _, _, sto = om.integrate(T[idx], p[idx], Y[idx], 5e-9, RTOL, ATOL)
+    assert np.all(sto == 0)
+    _assert_state_parity(Tg.cpu().numpy()[idx], Yg.cpu().numpy()[idx], To, Yo, key)
