@@ -367,14 +367,15 @@ int parse_openfoam(const std::string& reactions_path, const std::string& thermo_
         const Entry* th = d.find("thermodynamics");
         const Entry* els = d.find("elements");
         double W = 0.0;
-        if (!spc || !spc->dict || rd.scalar(*spc->dict, "molWeight", W, nm)) return CHEM_E_PARSE;
+        if (!spc || !spc->dict) return rd.fail(CHEM_E_PARSE, nm, "needs specie { molWeight ...; }");
+        if (int rc = rd.scalar(*spc->dict, "molWeight", W, nm)) return rc;
         if (!(W > 0.0)) return rd.fail(CHEM_E_MECH_INVALID, nm, "molWeight must be positive");
         s.W = W * 1e-3;   // kg/kmol -> kg/mol
         if (!th || !th->dict) return rd.fail(CHEM_E_PARSE, nm, "needs thermodynamics");
         double tl, th_, tc;
-        if (rd.scalar(*th->dict, "Tlow", tl, nm) || rd.scalar(*th->dict, "Thigh", th_, nm) ||
-            rd.scalar(*th->dict, "Tcommon", tc, nm))
-            return CHEM_E_PARSE;
+        if (int rc = rd.scalar(*th->dict, "Tlow", tl, nm)) return rc;
+        if (int rc = rd.scalar(*th->dict, "Thigh", th_, nm)) return rc;
+        if (int rc = rd.scalar(*th->dict, "Tcommon", tc, nm)) return rc;
         s.tmid = tc;
         for (auto [key, dst] : {std::pair<const char*, double*>{"lowCpCoeffs", s.lo}, {"highCpCoeffs", s.hi}}) {
             const Entry* c = th->dict->find(key);
