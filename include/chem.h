@@ -281,7 +281,7 @@ int chem_integrate_batched(const chem_mechanism *m, int nfield, double *const *T
    CHEM_E_CELL_FAILED if a cell failed (stats or not): such cells get NaN
    gT0/gY0 and add nothing to the parameter gradients.  Both kernel forms
    provide it: one cell per lane, or one group of lanes per cell for the
-   wave-cooperative form (mechanisms above 20 species), whose transposed
+   wave-cooperative form (mechanisms above 13 species), whose transposed
    solves and Jacobian-transpose products are group reductions. */
 int chem_integrate_adjoint(const chem_mechanism *m, int64_t ncell, const double *T0,
                            const double *p, const double *Y0, double dt, double rtol,

@@ -28,11 +28,14 @@ namespace {
 // Mechanisms with up to kLaneSpecies species run one cell per lane (the
 // cell's Jacobian and LU factors in one lane's registers); larger ones run
 // wave-cooperatively.  At 13 species the lane form spills registers but keeps
-// 64 cells in flight per SIMD against 8, and wins on large fields; the
-// wave-cooperative form has the shorter latency per cell.
+// 64 cells in flight per SIMD against 8, and wins on large fields (28 M cells:
+// 7.2 s against 9.4 s); the wave-cooperative form has the shorter latency per
+// cell.  From 14 species on, the lane form's spills grow steeply and the
+// wave-cooperative form is 3-4x faster even on a 65 k-cell field (14, 15, 16
+// and 18 species measured), so 13 is the default limit.
 // CHEM_LANE_MAX_SPECIES overrides the choice at load time (the lane form is
 // built for at most kMaxLaneSpecies species).
-constexpr int kLaneSpecies = 20;
+constexpr int kLaneSpecies = 13;
 constexpr int kMaxLaneSpecies = 20;
 
 int lane_max_species()
