@@ -21,7 +21,7 @@ ROOT = PKG.parent
 # (mechanism, CHEM_LANE_MAX_SPECIES at load): the default builds and the
 # wave-cooperative builds of the 9- and 13-species mechanisms
 PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0"),
-            ("m13x", None), ("m13x", "0"), ("m32x", None)]
+            ("m13x", None), ("m13x", "0"), ("m32x", None), ("m16", None)]
 # CHEMKIN renderings the tests load (written into the build folder first)
 PREBUILT_CHEMKIN = ["m9", "m32x"]
 # OpenFOAM renderings the tests load

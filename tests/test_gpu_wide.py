@@ -235,3 +235,27 @@ def test_wide_source_mode(chem, mechs, dev):
     wg, qg = wg.cpu().numpy(), qg.cpu().numpy()
     assert np.all(np.abs(wg - ws) <= 1e-12 * np.abs(ws) + 1e-300)
     assert np.all(np.abs(qg + (ws * hf).sum(axis=1)) <= 1e-12 * np.abs(ws * hf).sum(axis=1) + 1e-300)
+
+
+def test_mid_size_mechanism_runs_wave_cooperatively_at_parity(chem, oracle_lib, dev):
+    """A 16-species mechanism (above the one-cell-per-lane limit) loads in the
+    wave-cooperative form by default (G = 32: two cells per wave) and matches
+    the oracle on uniform cells and on every region of an RDE-shaped field,
+    plain and persistent."""
+    import ctypes as C
+    gm = chem.Mechanism(mech_path("m16"))
+    om = oracle_lib.Mechanism(mech_path("m16"))
+    T, p, Y = uniform_cells(mech_text("m16"), 301, 76)
+    Tg, Yg, stats = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL)
+    To, Yo, _, _, sto = om.integrate(T, p, Y, 1e-8, RTOL, ATOL)
+    assert stats["failed"] == 0 and np.all(sto == 0)
+    _assert_state_parity(Tg.cpu().numpy(), Yg.cpu().numpy(), To, Yo, "m16 uniform")
+    T, p, Y, reg = rde_field(mech_text("m16"), 128, 128, 77)
+    Tp, Yp, sp = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL, form=chem.FORM_PERSISTENT)
+    Tq, Yq, sq = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 5e-9, RTOL, ATOL)
+    assert torch.equal(Tp, Tq) and torch.equal(Yp, Yq) and sp["failed"] == 0
+    rng = np.random.default_rng(78)
+    idx = np.concatenate([rng.choice(np.nonzero(reg == r)[0], 16, replace=False) for r in (0, 1, 2)])
+    To, Yo, _, _, sto = om.integrate(T[idx], p[idx], Y[idx], 5e-9, RTOL, ATOL)
+    assert np.all(sto == 0)
+    _assert_state_parity(Tp.cpu().numpy()[idx], Yp.cpu().numpy()[idx], To, Yo, "m16 field")

@@ -6,7 +6,7 @@ from workloads import WORKLOADS, gen_mech, mech_path, mech_text
 from workloads import states
 
 
-@pytest.mark.parametrize("name", ["m9", "m13", "m32", "m13x", "m32x", "m32s"])
+@pytest.mark.parametrize("name", ["m9", "m13", "m32", "m13x", "m32x", "m32s", "m16"])
 def test_committed_mechanisms_regenerate_exactly(name):
     assert gen_mech.build(name) == mech_text(name)
 

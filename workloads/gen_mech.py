@@ -490,6 +490,9 @@ MECHS = {
                 n_troe=3, n_thirdbody=4, inert=tuple(INERT_SPECIES)),
     "m32": dict(species=SPECIES_H_O_N + SPECIES_EXTRA_13 + SPECIES_EXTRA_32,
                 n_reactions=150, seed=9003, n_troe=15, inert=tuple(INERT_SPECIES)),
+    # a mid-sized mechanism (above the one-cell-per-lane limit of 13 species)
+    "m16": dict(species=SPECIES_H_O_N + SPECIES_EXTRA_13 + SPECIES_EXTRA_32[:3],
+                n_reactions=48, seed=9016, n_troe=4, n_thirdbody=4, inert=tuple(INERT_SPECIES)),
 }
 
 
