@@ -98,3 +98,26 @@ def test_params_roundtrip_and_argument_errors(L):
     assert L.chem_euler1d_init(h, 8, host.ctypes.data, host.ctypes.data, host.ctypes.data, None,
                                host.ctypes.data, None) == -1
     L.chem_free_mechanism(h)
+
+
+def test_product_path_never_reaches_the_oracle():
+    """The library and its binding neither import, link nor name the oracle,
+    and libchemmi.so needs no oracle symbol."""
+    pkg = ROOT / "paper_2508_16105_amd"
+    for f in list(pkg.rglob("*.py")) + list((pkg / "csrc").rglob("*.[ch]pp")) + list((pkg / "csrc").rglob("*.hip")):
+        text = f.read_text()
+        assert not re.search(r"\boracle\b|liboracle|om_\w+\(", text), f
+    so = (pkg / "libchemmi.so").read_bytes()
+    assert b"liboracle" not in so
+    for name in set(re.findall(r"\b(om_\w+)\(", (ROOT / "oracle" / "oracle.h").read_text())):
+        assert name.encode() + b"\0" not in so, name
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises at once: there is no
+    fallback path."""
+    from paper_2508_16105_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", tmp_path / "libchemmi.so")
+    with pytest.raises(ImportError, match="not built"):
+        _lib.lib()
