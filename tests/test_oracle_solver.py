@@ -56,10 +56,19 @@ def _original_form(t):
     return t["a"] @ G, G, t["m"] @ G, (t["m"] - t["e"]) @ G
 
 
-def test_rodas4_order_conditions(oracle_lib):
-    t = oracle_lib.tableau()
+@pytest.mark.parametrize("method", ["RODAS4", "ROS4"])
+def test_rosenbrock_order_conditions(oracle_lib, method):
+    """Both tableaux the oracle carries: the eight order-4 conditions of a
+    Rosenbrock method (Hairer & Wanner, Sec. IV.7, Table 7.1), the embedded
+    solution of order 3 (and not 4), stiff accuracy (RODAS4 only), and
+    stability: |R(iw)| <= 1 and R(-inf) = 0 for RODAS4; for ROS4 the
+    published coefficients are rounded (gamma = 0.57282), so R(-inf) is
+    small, not zero."""
+    t = oracle_lib.tableau(getattr(oracle_lib, method))
     alpha, G, b, bh = _original_form(t)
     g = t["gamma"]
+    s = t["s"]
+    assert s == (6 if method == "RODAS4" else 4)
     assert np.allclose(np.diag(G), g, atol=1e-14)
     bp = alpha + G - np.diag(np.diag(G))
     a_i, be_i = alpha.sum(1), bp.sum(1)
@@ -73,12 +82,41 @@ def test_rodas4_order_conditions(oracle_lib):
     assert np.abs(conds(b)).max() < 1e-13               # order 4
     assert np.abs(conds(bh)[:4]).max() < 1e-13          # embedded order 3
     assert abs(conds(bh)[4:]).max() > 1e-6              # ... and not 4
-    assert np.allclose(b, alpha[-1] + G[-1], atol=1e-14)   # stiffly accurate
-    # L-stable: R(z) = 1 + z b^T (I - z B)^-1 1 -> 0 as z -> -inf, |R(iw)| <= 1
+    if method == "RODAS4":
+        assert np.allclose(b, alpha[-1] + G[-1], atol=1e-14)   # stiffly accurate
+    # stability function R(z) = 1 + z b^T (I - z B)^-1 1
     B = alpha + G
-    R = lambda z: 1 + z * b @ np.linalg.solve(np.eye(t["s"]) - z * B, np.ones(t["s"]))
-    assert abs(R(-1e12)) < 1e-9
+    R = lambda z: 1 + z * b @ np.linalg.solve(np.eye(s) - z * B, np.ones(s))
+    assert abs(R(-1e12)) < (1e-9 if method == "RODAS4" else 1e-4)
     assert max(abs(R(1j * w)) for w in np.logspace(-3, 4, 200)) <= 1 + 1e-12
+    # a plausible mistake in any stored coefficient (a, c or the weights m,
+    # off by 0.1 %) breaks an order condition
+    for key in ("a", "c", "m"):
+        arr = t[key]
+        for ix in zip(*np.nonzero(arr)):
+            t2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in t.items()}
+            t2[key][ix] *= 1.001
+            a2, G2, b2, _ = _original_form(t2)
+            bp2 = a2 + G2 - np.diag(np.diag(G2))
+            ai2, bei2 = a2.sum(1), bp2.sum(1)
+            r = [b2.sum() - 1, b2 @ bei2 - (0.5 - g), b2 @ ai2**2 - 1 / 3,
+                 b2 @ (bp2 @ bei2) - (1 / 6 - g + g * g), b2 @ ai2**3 - 1 / 4,
+                 b2 @ (ai2 * (a2 @ bei2)) - (1 / 8 - g / 3), b2 @ (bp2 @ ai2**2) - (1 / 12 - g / 3),
+                 b2 @ (bp2 @ (bp2 @ bei2)) - (1 / 24 - g / 2 + 1.5 * g * g - g**3)]
+            assert max(abs(x) for x in r) > 1e-8, (method, key, ix)
+
+
+def test_ros4_integrates_like_rodas4(oracle_lib):
+    """ROS4 is a second, independent order-4 method: an adaptive solve of a
+    reacting front cell with it lands within the tolerance of RODAS4's."""
+    m = oracle_lib.Mechanism(mech_path("m9"))
+    T, p, Y, reg = rde_field(mech_text("m9"), 64, 64, 101)
+    idx = np.concatenate([np.where(reg == r)[0][:4] for r in (0, 1, 2)])
+    Ta, Ya, na, _, sa = m.integrate(T[idx], p[idx], Y[idx], 5e-9, 1e-10, 1e-14)
+    Tb, Yb, nb, _, sb = m.integrate(T[idx], p[idx], Y[idx], 5e-9, 1e-10, 1e-14, method=oracle_lib.ROS4)
+    assert np.all(sa == 0) and np.all(sb == 0)
+    assert np.all(np.abs(Ta - Tb) <= 1e-7 * Ta), np.abs(Ta - Tb).max()
+    assert np.abs(Ya - Yb).max() <= 1e-9
 
 
 def test_observed_order_on_nonlinear_problem(oracle_lib):
