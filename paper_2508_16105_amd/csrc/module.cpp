@@ -2,13 +2,16 @@
 #include "module.hpp"
 
 #include <dlfcn.h>
+#include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
+#include <link.h>
 #include <sys/stat.h>
 #include <utime.h>
 #include <unistd.h>
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <sstream>
 
@@ -55,6 +58,59 @@ std::string cache_dir()
 
 namespace {
 
+// The path (with its full version suffix), size and modification time of a
+// loaded shared library whose file name contains `part`, or "" if none is.
+std::string loaded_library(const char* part)
+{
+    struct Q {
+        const char* part;
+        std::string found;
+    } q{part, {}};
+    dl_iterate_phdr(
+        [](struct dl_phdr_info* info, size_t, void* data) -> int {
+            auto* qq = static_cast<Q*>(data);
+            if (info->dlpi_name && std::strstr(info->dlpi_name, qq->part)) {
+                char real[4096];
+                const char* path = realpath(info->dlpi_name, real) ? real : info->dlpi_name;
+                struct stat st{};
+                std::ostringstream o;
+                o << path;
+                if (stat(path, &st) == 0) o << " size " << st.st_size << " mtime " << st.st_mtime;
+                qq->found = o.str();
+                return 1;
+            }
+            return 0;
+        },
+        &q);
+    return q.found;
+}
+
+}  // namespace
+
+// Everything that decides the machine code hipRTC makes from a source: the
+// hipRTC and HIP runtime versions and the exact hipRTC and code-object
+// compiler (comgr) libraries this process loaded.  Part of every cache key,
+// so a host with another compiler build compiles afresh instead of running
+// code objects another compiler made.
+const std::string& compiler_identity()
+{
+    static const std::string id = [] {
+        int vmaj = 0, vmin = 0, rt = 0;
+        hiprtcVersion(&vmaj, &vmin);
+        (void)hipRuntimeGetVersion(&rt);
+        // hipRTC loads comgr on first use; load it now (it is the library hipRTC
+        // itself loads) so its identity is known before the first compile
+        if (!dlopen("libamd_comgr.so.3", RTLD_LAZY | RTLD_NOLOAD)) (void)dlopen("libamd_comgr.so.3", RTLD_LAZY);
+        std::ostringstream o;
+        o << "hiprtc " << vmaj << "." << vmin << "; hip runtime " << rt << "; " << loaded_library("libhiprtc.so")
+          << "; " << loaded_library("libamd_comgr.so");
+        return o.str();
+    }();
+    return id;
+}
+
+namespace {
+
 bool read_file(const std::string& path, std::vector<char>& out)
 {
     std::ifstream in(path, std::ios::binary);
@@ -80,11 +136,10 @@ void write_file_atomic(const std::string& path, const std::vector<char>& data)
 int build_code_object(const std::string& source, std::vector<char>& code, std::string& err,
                       std::string* cache_file)
 {
-    int vmaj = 0, vmin = 0;
-    hiprtcVersion(&vmaj, &vmin);
     std::string key_text = source;
     for (auto& o : compile_options()) key_text += "\n" + o;
-    key_text += "\nhiprtc " + std::to_string(vmaj) + "." + std::to_string(vmin);
+    key_text += "\n" + compiler_identity();
+    if (std::getenv("CHEM_LOG")) std::fprintf(stderr, "[chem] compiler: %s\n", compiler_identity().c_str());
     char name[40];
     std::snprintf(name, sizeof name, "%016llx.co", (unsigned long long)fnv1a(key_text));
     const std::string dir = cache_dir();

@@ -23,6 +23,10 @@ const std::vector<std::string>& compile_options();
 int build_code_object(const std::string& source, std::vector<char>& code, std::string& err,
                       std::string* cache_file = nullptr);
 
+// hipRTC/HIP versions and the loaded hipRTC and comgr libraries (path with
+// version suffix, size, mtime): part of every code-object cache key.
+const std::string& compiler_identity();
+
 // Directory of the kernel cache.
 std::string cache_dir();
 
