@@ -280,8 +280,11 @@ def _make_autograd():
         def forward(ctx, mech, T, p, Y, lnA, b, Ea, dt, rtol, atol):
             mech.set_params(lnA.detach().cpu().numpy(), b.detach().cpu().numpy(),
                             Ea.detach().cpu().numpy())
+            # with stats the call waits for the result and raises ChemError
+            # (CHEM_E_CELL_FAILED) if a cell failed, instead of handing back a
+            # failed cell's last accepted partial state
             Te, Ye, _ = integrate(mech, T.detach(), p.detach(), Y.detach(), dt, rtol, atol,
-                                  stats=False)
+                                  stats=True)
             ctx.mech, ctx.dt, ctx.rtol, ctx.atol = mech, dt, rtol, atol
             ctx.save_for_backward(T.detach(), p.detach(), Y.detach())
             ctx.params = (lnA.detach().cpu().numpy(), b.detach().cpu().numpy(), Ea.detach().cpu().numpy())

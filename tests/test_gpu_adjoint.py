@@ -282,30 +282,59 @@ def test_autograd_function_backward(chem, mechs, dev):
         assert np.array_equal(t.grad.cpu().numpy(), r)
 
 
-def test_adjoint_matches_central_differences_of_the_gpu_forward(chem, mechs, dev):
-    """The adjoint workload's own check: central differences (relative step
-    1e-6) of the GPU forward integration, per cell, for dL/dT0 and for
-    dL/dY0 along a random direction, against the adjoint.  The differences go
-    through the adaptive map (step sizes follow the perturbation) while the
-    adjoint differentiates the frozen-step map; the two agree to the 1e-5 bar
-    except where the perturbation flips an accept/reject decision, which is
-    allowed for at most 5 % of the cells."""
+@pytest.mark.parametrize("rtol,atol", [(RTOL, ATOL), (1e-11, 1e-15)])
+def test_adjoint_matches_central_differences_of_the_gpu_forward(chem, mechs, dev, rtol, atol):
+    """The adjoint workload's own check: central differences of the GPU
+    forward integration, per cell, for dL/dT0 (relative step 1e-6) and for
+    dL/dY0 along a random direction (each mass fraction moved by 1e-6 of
+    itself times a normal deviate), against the adjoint.  The differences go
+    through the adaptive map while the adjoint differentiates the frozen-step
+    map.  Where the perturbation changes a cell's accepted or rejected substep
+    count an accept/reject decision flipped and the adaptive map jumps: such
+    cells are exempt, and may be at most 5 % of the cells.  Every other cell
+    must agree within 1e-5 relative, plus the differences' own error: the
+    forward's rounding over hundreds of substeps (a burnt cell takes 367 at
+    rtol 1e-8 and 2,116 at 1e-11) moves L by a few hundred ulp, which a
+    difference quotient over a small perturbation magnifies.  That error is
+    estimated, cell by cell, as the change of the quotient between the step and
+    twice the step (the smooth part of the map gives the same quotient to
+    O(h^2)); a wrong gradient stays wrong at both steps and is caught."""
     gm, _ = mechs["m9"]
     T, p, Y, w = _adj256k_sample(per_region=32, seed=9)
     n = len(T)
     gT, gY = _loss_weights("m9", n, False)
-    gT0, gY0, *_ = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev)
+    out = chem.integrate_adjoint(gm, _g(T, dev), _g(p, dev), _g(Y, dev), w["dt"], rtol, atol, _g(gT, dev),
+                                 _g(gY, dev))
+    gT0, gY0 = out[0].cpu().numpy(), out[1].cpu().numpy()
 
     def loss(Tc, Yc):
-        Te, Ye, _ = chem.integrate(gm, _g(Tc, dev), _g(p, dev), _g(Yc, dev), w["dt"], RTOL, ATOL)
-        return Te.cpu().numpy() * gT + (Ye.cpu().numpy() * gY).sum(axis=1)
+        Te, Ye, _, _, na, nr = chem.integrate(gm, _g(Tc, dev), _g(p, dev), _g(Yc, dev), w["dt"], rtol, atol,
+                                              return_counts=True)
+        counts = np.stack([na.cpu().numpy(), nr.cpu().numpy()], axis=1)
+        return Te.cpu().numpy() * gT + (Ye.cpu().numpy() * gY).sum(axis=1), counts
+
+    _, c0 = loss(T, Y)
+
+    def central(dT, dYv):
+        """(L(y + d) - L(y - d)) / 2 for steps d and 2d, and whether every run
+        kept the base run's substep counts."""
+        quot, same = [], np.ones(n, dtype=bool)
+        for f in (1.0, 2.0):
+            (lp, cp), (lm, cm) = loss(T + f * dT, Y + f * dYv), loss(T - f * dT, Y - f * dYv)
+            quot.append((lp - lm) / (2.0 * f))
+            same &= np.all((cp == c0) & (cm == c0), axis=1)
+        return quot[0], np.abs(quot[0] - quot[1]), same
 
     hT = 1e-6 * T
-    fdT = (loss(T + hT, Y) - loss(T - hT, Y)) / (2 * hT)
-    # a relative perturbation of every mass fraction (zero stays zero)
+    qT, eT, sameT = central(hT, np.zeros_like(Y))
+    fdT, errT = qT / hT, eT / hT
     dY = 1e-6 * np.random.default_rng(21).standard_normal(Y.shape) * Y
-    fdY = (loss(T, Y + dY) - loss(T, Y - dY)) / 2
+    fdY, errY, sameY = central(np.zeros_like(T), dY)
     adY = (gY0 * dY).sum(axis=1)
-    okT = np.abs(fdT - gT0) <= 1e-5 * np.abs(gT0) + 1e-12
-    okY = np.abs(fdY - adY) <= 1e-5 * np.abs(adY) + 1e-15
-    assert okT.mean() >= 0.95 and okY.mean() >= 0.95, (okT.mean(), okY.mean())
+    okT = np.abs(fdT - gT0) <= 1e-5 * np.abs(gT0) + 2.0 * errT + 1e-12
+    okY = np.abs(fdY - adY) <= 1e-5 * np.abs(adY) + 2.0 * errY + 1e-15
+    assert sameT.mean() >= 0.95 and sameY.mean() >= 0.95, (sameT.mean(), sameY.mean())
+    assert np.all(okT[sameT]), (np.where(~okT & sameT)[0], fdT[~okT & sameT], gT0[~okT & sameT])
+    assert np.all(okY[sameY]), (np.where(~okY & sameY)[0], fdY[~okY & sameY], adY[~okY & sameY])
+    # the differences' own error estimate stays small: it is not what passes the cells
+    assert np.median(errT[sameT] / np.maximum(np.abs(gT0[sameT]), 1e-300)) < 1e-6

@@ -12,6 +12,8 @@ pytestmark = pytest.mark.gpu
 from workloads import WORKLOADS, mech_path, mech_text  # noqa: E402
 from workloads.states import rde_field, uniform_cells  # noqa: E402
 
+from errnorm_ref import errnorm_bar, errnorm_with_spread  # noqa: E402
+
 DT, RTOL, ATOL = 5e-9, 1e-8, 1e-12
 
 
@@ -101,10 +103,14 @@ def test_fixed_step_matches_oracle(chem, mechs, dev):
         yn, en, ok = chem.step_fixed(gm, _g(T, dev), _g(p, dev), _g(Y, dev), h, RTOL, ATOL)
         yn = yn.cpu().numpy()
         assert ok.cpu().numpy().all()
+        en = en.cpu().numpy()
         for i in range(len(T)):
-            yo, eo = om.step(p[i], np.concatenate([[T[i]], Y[i]]), h)
+            y0 = np.concatenate([[T[i]], Y[i]])
+            eno, spread, yo, eo = errnorm_with_spread(om, p[i], y0, h, RTOL, ATOL)
             assert abs(yn[i, 0] - yo[0]) <= 1e-10 * yo[0]
             assert np.all(np.abs(yn[i, 1:] - yo[1:]) <= 1e-12)
+            # the embedded error estimate that decides acceptance
+            assert abs(en[i] - eno) <= errnorm_bar(eno, spread), (h, i, en[i], eno, spread)
 
 
 def test_integrate_uniform4k_matches_oracle(chem, mechs, dev):

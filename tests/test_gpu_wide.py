@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 from workloads import WORKLOADS, mech_path, mech_text  # noqa: E402
 from workloads.states import rde_field, rde_field_n, uniform_cells  # noqa: E402
 
+from errnorm_ref import errnorm_bar, errnorm_with_spread  # noqa: E402
+
 RTOL, ATOL = 1e-8, 1e-12
 
 
@@ -188,7 +190,7 @@ def test_wide_fixed_step_matches_oracle(chem, mechs, dev, key):
     # are too ill-conditioned for the comparison, so it takes smaller steps
     for h in ((1e-12, 1e-11) if name == "m13" else (1e-11, 1e-9)):
         yn, en, ok = chem.step_fixed(gm, _g(T, dev), _g(p, dev), _g(Y, dev), h, RTOL, ATOL)
-        yn, ok = yn.cpu().numpy(), ok.cpu().numpy()
+        yn, ok, en = yn.cpu().numpy(), ok.cpu().numpy(), en.cpu().numpy()
         skipped = 0
         for i in range(len(T)):
             yo, eo = om.step(p[i], np.concatenate([[T[i]], Y[i]]), h)
@@ -214,6 +216,9 @@ def test_wide_fixed_step_matches_oracle(chem, mechs, dev, key):
                 continue
             assert abs(yn[i, 0] - yo[0]) <= 1e-10 * yo[0], (key, i)
             assert np.all(np.abs(yn[i, 1:] - yo[1:]) <= 1e-12), (key, i)
+            # the embedded error estimate that decides acceptance
+            eno, espread, _, _ = errnorm_with_spread(om, p[i], y0, h, RTOL, ATOL)
+            assert abs(en[i] - eno) <= errnorm_bar(eno, espread), (key, i, h, en[i], eno, espread)
         assert skipped <= len(T) // 5, (key, h, skipped)
 
 
