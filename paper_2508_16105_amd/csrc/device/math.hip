@@ -12,8 +12,9 @@
 // 1.5 ulp overall with Horner evaluation in double; printed by
 // exp_poly_coeffs.py in the package directory).  No lookup table, so no LDS read
 // whose latency a single wave per SIMD would have to wait out.  NaN
-// propagates, arguments beyond the double range give 0 or inf through ldexp,
-// +-inf give NaN (a failed step for the caller).
+// propagates, arguments beyond the double range give 0 or inf through ldexp
+// (the exponent is clamped before its conversion to int), +-inf give NaN (a
+// failed step for the caller).
 
 namespace chem_math {
 
@@ -23,7 +24,11 @@ __device__ __forceinline__ double exp_poly(double x)
     constexpr double kLn2Hi = 0.6931471805599453;           // ln 2 rounded to double
     constexpr double kLn2Lo = 2.3190468138462996e-17;       // ln 2 - kLn2Hi
     const double nd = __builtin_rint(x * kLog2e);
-    const int n = (int)nd;
+    // The exponent as an int, clamped first: converting a NaN or an
+    // out-of-range double to int is undefined behaviour (LLVM turns it into
+    // poison, which the optimiser may propagate anywhere).  2^+-2100 already
+    // saturates ldexp to inf or 0, and a NaN x still gives NaN through r.
+    const int n = (int)fmin(fmax(nd, -2100.0), 2100.0);
     double r = fma(-nd, kLn2Hi, x);
     r = fma(-nd, kLn2Lo, r);
     double q = fma(2.5110037605963777e-08, r, 2.763263963904103e-07);
@@ -38,6 +43,19 @@ __device__ __forceinline__ double exp_poly(double x)
     q = fma(q, r, 1.0);
     q = fma(q, r, 1.0);
     return ldexp(q, n);
+}
+
+// 1/x: the hardware reciprocal estimate refined by two Newton steps
+// (e = 1 - x r, r <- r + r e; each step doubles the correct bits), within an
+// ulp of the quotient for normal x whose reciprocal is normal (0 and inf give
+// NaN, which the integrator treats as a failed stage).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
 }  // namespace chem_math
@@ -102,6 +120,11 @@ __device__ __forceinline__ Dual exp(Dual x)
 {
     const double e = ::exp(x.v);
     return {e, e * x.d};
+}
+__device__ __forceinline__ Dual recip(Dual x)
+{
+    const double r = recip(x.v);
+    return {r, -(r * r) * x.d};
 }
 __device__ __forceinline__ Dual log(Dual x) { return {::log(x.v), x.d / x.v}; }
 __device__ __forceinline__ Dual log10(Dual x) { return {::log10(x.v), x.d / (x.v * 2.302585092994045684)}; }

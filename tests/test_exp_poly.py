@@ -35,13 +35,11 @@ def _fma(a, b, c):
 
 
 def _exp_poly(x, named, poly):
-    """The device sequence: rint, int conversion (saturating), two-part
+    """The device sequence: rint, the exponent clamped to [-2100, 2100]
+    (fmax then fmin, so NaN gives -2100) and converted to int, two-part
     reduction, Horner, ldexp."""
     nd = float(np.rint(x * named["kLog2e"]))
-    if math.isnan(nd):
-        n = 0
-    else:
-        n = int(max(min(nd, 2.0**31 - 1), -(2.0**31)))
+    n = -2100 if math.isnan(nd) else int(min(max(nd, -2100.0), 2100.0))
     r = _fma(-nd, named["kLn2Hi"], x)
     r = _fma(-nd, named["kLn2Lo"], r)
     q = _fma(poly[0], r, poly[1])
