@@ -58,12 +58,158 @@ std::string side_product(const std::vector<Term>& side, int dsp = -1)
     return r.empty() ? "1.0" : r;
 }
 
+// G_k(T) = S_k/R - H_k/RT of species k from its NASA-7 set (host side, for
+// the range checks of the generator)
+double gibbs_of(const SpeciesData& sp, double T)
+{
+    const double* a = T < sp.tmid ? sp.lo : sp.hi;
+    const double lnT = std::log(T);
+    const double s = a[0] * lnT + a[1] * T + a[2] * T * T / 2 + a[3] * T * T * T / 3 + a[4] * T * T * T * T / 4 + a[6];
+    const double h = a[0] + a[1] * T / 2 + a[2] * T * T / 3 + a[3] * T * T * T / 4 + a[4] * T * T * T * T / 5 +
+                     a[5] / T;
+    return s - h;
+}
+
+// The reverse rate k_r = k_f / K_c with 1/K_c as a product of per-species
+// factors, e^{G_k} for each reactant and e^{-G_k} for each product (times
+// (RT/P_atm)^dnu), so a reversible reaction costs a few multiplies instead of
+// an exponential of its own (ln K_c = sum_k nu_k G_k + dnu ln(P_atm/RT), the
+// standard-state equilibrium constant of the mass-action law).  The factors
+// are multiplied reactant, product, reactant, ... ; a reaction keeps the
+// exponential of ln k_f - ln K_c when some partial product would leave
+// [e^-650, e^650] anywhere on 200 .. 6000 K.
+struct SpeciesKc {
+    std::vector<bool> product_form;   // per reaction
+    std::vector<bool> need_gp, need_gm;   // per species: e^{G_k}, e^{-G_k}
+    bool any_dnu = false;
+};
+
+std::vector<std::pair<int, int>> kc_factor_order(const ReactionData& r)
+{
+    // (species, +1 for e^{G}, -1 for e^{-G}), one entry per unit of nu, alternating sides
+    std::vector<int> a, b;
+    for (const auto& t : r.reac)
+        for (int i = 0; i < t.nu; ++i) a.push_back(t.sp);
+    for (const auto& t : r.prod)
+        for (int i = 0; i < t.nu; ++i) b.push_back(t.sp);
+    std::vector<std::pair<int, int>> out;
+    for (size_t i = 0; i < std::max(a.size(), b.size()); ++i) {
+        if (i < a.size()) out.push_back({a[i], +1});
+        if (i < b.size()) out.push_back({b[i], -1});
+    }
+    return out;
+}
+
+SpeciesKc plan_species_kc(const MechanismData& m)
+{
+    SpeciesKc p;
+    const int ns = m.ns(), nr = m.nr();
+    p.product_form.assign(nr, false);
+    p.need_gp.assign(ns, false);
+    p.need_gm.assign(ns, false);
+    std::vector<double> temps;
+    for (double T = 200.0; T <= 6000.0; T += 5.0) temps.push_back(T);
+    for (const auto& sp : m.species) {
+        temps.push_back(sp.tmid);
+        temps.push_back(std::nextafter(sp.tmid, 0.0));
+    }
+    const double lim = 650.0;
+    for (int j = 0; j < nr; ++j) {
+        const auto& r = m.reactions[j];
+        if (!r.reversible) continue;
+        const auto order = kc_factor_order(r);
+        bool ok = true;
+        for (double T : temps) {
+            double acc = 0.0;
+            for (const auto& f : order) {
+                const double g = gibbs_of(m.species[f.first], T);
+                if (std::fabs(g) > lim) ok = false;
+                acc += f.second * g;
+                if (std::fabs(acc) > lim) ok = false;
+            }
+            acc += r.dnu * std::log(kRu * T / kPatm);
+            if (std::fabs(acc) > lim) ok = false;
+            if (!ok) break;
+        }
+        p.product_form[j] = ok;
+        if (!ok) continue;
+        for (const auto& f : order) (f.second > 0 ? p.need_gp : p.need_gm)[f.first] = true;
+        if (r.dnu != 0) p.any_dnu = true;
+    }
+    return p;
+}
+
+// c_1 e_1 + c_2 e_2 + ... as source text, led by its first term rather than
+// by "0.0 +" (x + 0.0 is not x for x = -0.0, so a compiler must keep such an
+// addition); "0.0" when there are no terms
+std::string lin_sum(const std::vector<std::pair<double, std::string>>& terms)
+{
+    if (terms.empty()) return "0.0";
+    std::string out;
+    for (size_t i = 0; i < terms.size(); ++i) {
+        const double c = terms[i].first;
+        const std::string& e = terms[i].second;
+        if (i == 0) out = c == 1.0 ? e : (c == -1.0 ? "-(" + e + ")" : lit(c) + "*" + e);
+        else if (c == 1.0) out += " + " + e;
+        else if (c == -1.0) out += " - " + e;
+        else if (c < 0.0) out += " - " + lit(-c) + "*" + e;
+        else out += " + " + lit(c) + "*" + e;
+    }
+    return out;
+}
+
+// Species no reaction produces or consumes (net coefficient zero in every
+// reaction): their rows of the source terms and of the Jacobian are zero.
+std::vector<bool> inert_species(const MechanismData& m)
+{
+    std::vector<bool> inert(m.ns(), true);
+    for (const auto& r : m.reactions) {
+        std::vector<int> nu(m.ns(), 0);
+        for (const auto& t : r.reac) nu[t.sp] -= t.nu;
+        for (const auto& t : r.prod) nu[t.sp] += t.nu;
+        for (int k = 0; k < m.ns(); ++k)
+            if (nu[k]) inert[k] = false;
+    }
+    return inert;
+}
+
+// Structural non-zeros of d wdot_k / d C_m: species k changed by a reaction
+// whose rate depends on C_m (a reactant, a product of a reversible reaction,
+// or a collision partner with non-zero efficiency).
+std::vector<std::vector<bool>> jc_pattern(const MechanismData& m)
+{
+    const int ns = m.ns();
+    std::vector<std::vector<bool>> nz(ns, std::vector<bool>(ns, false));
+    for (const auto& r : m.reactions) {
+        std::vector<int> nu(ns, 0);
+        for (const auto& t : r.reac) nu[t.sp] -= t.nu;
+        for (const auto& t : r.prod) nu[t.sp] += t.nu;
+        std::vector<bool> dep(ns, false);
+        for (const auto& t : r.reac) dep[t.sp] = true;
+        if (r.reversible)
+            for (const auto& t : r.prod) dep[t.sp] = true;
+        if (r.kind == RxnKind::ThirdBody || is_falloff(r.kind))
+            for (int k = 0; k < ns; ++k)
+                if (r.eff[k] != 0.0) dep[k] = true;
+        for (int k = 0; k < ns; ++k)
+            if (nu[k])
+                for (int mm = 0; mm < ns; ++mm)
+                    if (dep[mm]) nz[k][mm] = true;
+    }
+    return nz;
+}
+
 struct Emitter {
     const MechanismData& m;
     std::ostringstream o;
     int ns, nr;
+    SpeciesKc kc;
+    std::vector<bool> inert;
+    std::vector<std::vector<bool>> jnz;
 
-    explicit Emitter(const MechanismData& mm) : m(mm), ns(mm.ns()), nr(mm.nr()) {}
+    explicit Emitter(const MechanismData& mm)
+        : m(mm), ns(mm.ns()), nr(mm.nr()), kc(plan_species_kc(mm)), inert(inert_species(mm)),
+          jnz(jc_pattern(mm)) {}
 
     // NASA-7 coefficient table, per species and range (0: T < T_mid, 1: T >= T_mid):
     //  [0..4]  cp/R  = c0 + T(c1 + T(c2 + T(c3 + T c4)))          (a1..a5)
@@ -194,16 +340,25 @@ struct Emitter {
              "  cdbl* MW = (cdbl*)&MWTAB[0] + z;\n"
              "  const S T = y[0];\n"
              "  const S lnT = log(T);\n"
-             "  const S iT = 1.0 / T;\n"
+             "  const S iT = chem_math::recip(T);\n"
              "  const S T2 = T * T, T3 = T2 * T, T4 = T2 * T2;\n"
              "  S cpR[NS], HRT[NS], G[NS];\n";
         if (jac) o << "  S dcpR[NS];\n";
         thermo(jac);
+        // per-species equilibrium factors e^{G_k}, e^{-G_k} (see SpeciesKc)
+        for (int k = 0; k < ns; ++k) {
+            if (kc.need_gp[k] || kc.need_gm[k])
+                o << "  const S gp" << k << " = chem_math::exp_poly(G[" << k << "]);\n";
+            if (kc.need_gm[k]) o << "  const S gm" << k << " = chem_math::recip(gp" << k << ");\n";
+        }
+        if (kc.any_dnu)
+            o << "  const S rtp = T * " << lit(kRu / kPatm) << ";\n"
+                 "  const S prt = iT * " << lit(kPatm / kRu) << ";\n";
         o << "  S sig = 0.0;\n";
         for (int k = 0; k < ns; ++k)
             o << "  sig = fma(y[" << 1 + k << "], MW[" << ns + k << "], sig);\n";
         // rho = p / (R T sig); 1/rho = R T sig / p with 1/p given
-        o << "  const S Wbar = 1.0 / sig;\n"
+        o << "  const S Wbar = chem_math::recip(sig);\n"
              "  const S rho = p * Wbar * iT * " << lit(1.0 / kRu) << ";\n"
              "  const S irho = " << lit(kRu) << " * T * sig * ip;\n"
              "  const S ctot = p * iT * " << lit(1.0 / kRu) << ";\n"
@@ -264,17 +419,28 @@ struct Emitter {
             plog_set(r);
             o << "    lnk = lnk + (lnT * plb - iT * ple + pla);\n";
         }
-        // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
-        std::string lnkc;
-        for (auto& t : r.prod) lnkc += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
-        for (auto& t : r.reac) lnkc += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "G[" + std::to_string(t.sp) + "]";
-        if (r.dnu != 0) lnkc += " + " + lit(r.dnu) + "*lnPRT";
-        o << "    const S lnKc = 0.0" << lnkc << ";\n";
+        const bool pform = rev_on && kc.product_form[j];
+        if (pform) {
+            // 1/K_c = prod_reac e^{G} prod_prod e^{-G} (RT/P_atm)^dnu
+            std::string f;
+            for (const auto& t : kc_factor_order(r))
+                f += (f.empty() ? "" : " * ") + std::string(t.second > 0 ? "gp" : "gm") + std::to_string(t.first);
+            for (int i = 0; i < std::abs(r.dnu); ++i) f += (f.empty() ? "" : " * ") + std::string(r.dnu > 0 ? "rtp" : "prt");
+            o << "    const S ikc = " << (f.empty() ? std::string("1.0") : f) << ";\n";
+        } else if (rev_on) {
+            // ln K_c = sum nu (S/R - H/RT) + dnu ln(P_atm / RT)
+            std::vector<std::pair<double, std::string>> lnkc;
+            for (auto& t : r.prod) lnkc.push_back({(double)t.nu, "G[" + std::to_string(t.sp) + "]"});
+            for (auto& t : r.reac) lnkc.push_back({-(double)t.nu, "G[" + std::to_string(t.sp) + "]"});
+            if (r.dnu != 0) lnkc.push_back({(double)r.dnu, "lnPRT"});
+            o << "    const S lnKc = " << lin_sum(lnkc) << ";\n";
+        }
         const bool falloff = is_falloff(r.kind);
         if (r.kind != RxnKind::Elementary && !plog) o << "    const S Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
             o << "    const S kf = chem_math::exp_poly(lnk);\n";
-            if (rev_on) o << "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
+            if (pform) o << "    const S kr = kf * ikc;\n";
+            else if (rev_on) o << "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
             o << "    const S kinf = chem_math::exp_poly(lnk);\n"
@@ -301,9 +467,9 @@ struct Emitter {
                      "    const S tn = 0.75 - 1.27*logFc;\n"
                      "    const S tu = logPr + tc;\n"
                      "    const S tden = tn - 0.14*tu;\n"
-                     "    const S tx = tu / tden;\n"
+                     "    const S tx = tu * chem_math::recip(tden);\n"
                      "    const S opx2 = 1.0 + tx*tx;\n"
-                     "    const S logF = logFc / opx2;\n"
+                     "    const S logF = logFc * chem_math::recip(opx2);\n"
                      "    const S Fb = exp(" << lit(std::log(10.0)) << " * logF);\n";
                 if (jac) {
                     o << "    const S tg = -logFc * 2.0 * tx / (opx2*opx2);\n"
@@ -319,7 +485,7 @@ struct Emitter {
                      "    const S sec = chem_math::exp_poly(-T * " << lit(1.0 / c[2]) << ");\n"
                      "    const S sY = sea + sec;\n"
                      "    const S lnsY = log(sY);\n"
-                     "    const S sX = 1.0 / (1.0 + logPr * logPr);\n"
+                     "    const S sX = chem_math::recip(1.0 + logPr * logPr);\n"
                      "    const S Fb = chem_math::exp_poly(sX * lnsY + " << lit(c[4]) << " * lnT + " << lit(std::log(c[3]))
                   << ");\n";
                 if (jac)
@@ -332,9 +498,12 @@ struct Emitter {
                 o << "    const S Fb = 1.0;\n";
                 if (jac) o << "    const S dF_dPr = 0.0, dF_dFc = 0.0, dlogFc_dT = 0.0;\n";
             }
-            o << "    const S ipr1 = 1.0 / (1.0 + Pr);\n"
+            o << "    const S ipr1 = chem_math::recip(1.0 + Pr);\n"
                  "    const S kf = kinf * Pr * ipr1 * Fb;\n";
-            if (rev_on)
+            if (pform)
+                o << "    const S iKc = ikc;\n"
+                     "    const S kr = kf * iKc;\n";
+            else if (rev_on)
                 o << "    const S iKc = chem_math::exp_poly(-lnKc);\n"
                      "    const S kr = kf * iKc;\n";
         }
@@ -357,10 +526,12 @@ struct Emitter {
             if (nu[k]) o << "    wd[" << k << "] = fma(" << lit(nu[k]) << ", q, wd[" << k << "]);\n";
         if (jac) {
             // d ln k_f / dT at fixed [M]; d ln K_c / dT = (sum nu H/RT - dnu) / T
-            std::string sh;
-            for (auto& t : r.prod) sh += " + " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
-            for (auto& t : r.reac) sh += " - " + (t.nu == 1 ? "" : lit(t.nu) + "*") + "HRT[" + std::to_string(t.sp) + "]";
-            if (rev_on) o << "    const S dlnKc = (0.0" << sh << " - " << lit(r.dnu) << ") * iT;\n";
+            std::vector<std::pair<double, std::string>> sh;
+            for (auto& t : r.prod) sh.push_back({(double)t.nu, "HRT[" + std::to_string(t.sp) + "]"});
+            for (auto& t : r.reac) sh.push_back({-(double)t.nu, "HRT[" + std::to_string(t.sp) + "]"});
+            if (rev_on)
+                o << "    const S dlnKc = (" << lin_sum(sh)
+                  << (r.dnu != 0 ? " - " + lit(r.dnu) : std::string()) << ") * iT;\n";
             if (plog)
                 o << "    const S dlnkinf = (P[" << nr + j << "] + plb + (P[" << 2 * nr + j << "] + ple)*iT) * iT;\n";
             else
@@ -400,16 +571,16 @@ struct Emitter {
                 // weights of this reaction's rate in w . f (species rows) and in the
                 // heat release: wY = sum_k nu_k W_k w_{1+k}, hs = sum_k nu_k H_k/RT;
                 // the columns of J^T w collect wY dq_m and hs dq_m; s = sum_m dq_m C_m
-                std::string ws, sh, sj;
+                std::vector<std::pair<double, std::string>> ws, hsum, sj;
                 for (int k = 0; k < ns; ++k)
-                    if (nu[k]) ws += " + " + lit(nu[k]) + "*(MW[" + std::to_string(k) + "]*w[" + std::to_string(1 + k) + "])";
+                    if (nu[k]) ws.push_back({(double)nu[k], "(MW[" + std::to_string(k) + "]*w[" + std::to_string(1 + k) + "])"});
                 for (int k = 0; k < ns; ++k)
-                    if (nu[k]) sh += " + " + lit(nu[k]) + "*HRT[" + std::to_string(k) + "]";
+                    if (nu[k]) hsum.push_back({(double)nu[k], "HRT[" + std::to_string(k) + "]"});
                 for (int mm = 0; mm < ns; ++mm)
-                    if (!dq[mm].empty()) sj += " + dq" + std::to_string(mm) + "*C[" + std::to_string(mm) + "]";
-                o << "    const S wY = 0.0" << ws << ";\n"
-                     "    const S hs = 0.0" << sh << ";\n"
-                     "    const S sj = 0.0" << sj << ";\n";
+                    if (!dq[mm].empty()) sj.push_back({1.0, "dq" + std::to_string(mm) + "*C[" + std::to_string(mm) + "]"});
+                o << "    const S wY = " << lin_sum(ws) << ";\n"
+                     "    const S hs = " << lin_sum(hsum) << ";\n"
+                     "    const S sj = " << lin_sum(sj) << ";\n";
                 for (int mm = 0; mm < ns; ++mm)
                     if (!dq[mm].empty())
                         o << "    colA[" << mm << "] = fma(wY, dq" << mm << ", colA[" << mm << "]); colH[" << mm
@@ -441,12 +612,16 @@ struct Emitter {
     void rhs_tail()
     {
         // 1/(rho cp) = T sig / (p cpm)
-        o << "  const S icpm = 1.0 / cpm;\n"
+        o << "  const S icpm = chem_math::recip(cpm);\n"
              "  const S rcpinv = T * sig * ip * icpm;\n";
+        // (species no reaction changes have wdot = 0: no terms, zero rows)
         o << "  S hw = 0.0;\n";
-        for (int k = 0; k < ns; ++k) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
         for (int k = 0; k < ns; ++k)
-            o << "  f[" << 1 + k << "] = MW[" << k << "] * (irho * wd[" << k << "]);\n";
+            if (!inert[k]) o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw);\n";
+        for (int k = 0; k < ns; ++k) {
+            if (inert[k]) o << "  f[" << 1 + k << "] = 0.0;\n";
+            else o << "  f[" << 1 + k << "] = MW[" << k << "] * (irho * wd[" << k << "]);\n";
+        }
         o << "  f[0] = -" << lit(kRu) << " * T * hw * rcpinv;\n";
     }
 
@@ -475,28 +650,38 @@ struct Emitter {
         //   J_00 = -R (cpw + T HwT - HS) / (rho cp) - f_T (dcp / cp - 1/T)
         // where HJ_m = sum_k H_k/RT Jc_km, HS = sum_k H_k/RT S_k, HwT = sum_k H_k/RT wT_k,
         // cpw = sum_k cp_k/R wdot_k.
+        // (sums run over the structural non-zeros of Jc only: a literal zero
+        // times a value is not folded away by the compiler, as the value could
+        // be infinite; rows of species no reaction changes are zero)
         o << "  S Sk[NS];\n";
         for (int k = 0; k < ns; ++k) {
-            o << "  Sk[" << k << "] = 0.0";
-            for (int l = 0; l < ns; ++l) o << " + J[" << 1 + k << "][" << 1 + l << "]*C[" << l << "]";
-            o << ";\n";
+            std::vector<std::pair<double, std::string>> t;
+            for (int l = 0; l < ns; ++l)
+                if (jnz[k][l])
+                    t.push_back({1.0, "J[" + std::to_string(1 + k) + "][" + std::to_string(1 + l) + "]*C[" + std::to_string(l) + "]"});
+            o << "  Sk[" << k << "] = " << lin_sum(t) << ";\n";
         }
         o << "  S HS = 0.0, HwT = 0.0, cpw = 0.0;\n";
         for (int k = 0; k < ns; ++k)
-            o << "  HS = fma(HRT[" << k << "], Sk[" << k << "], HS); HwT = fma(HRT[" << k << "], J[" << 1 + k
-              << "][0], HwT); cpw = fma(cpR[" << k << "], wd[" << k << "], cpw);\n";
+            if (!inert[k])
+                o << "  HS = fma(HRT[" << k << "], Sk[" << k << "], HS); HwT = fma(HRT[" << k << "], J[" << 1 + k
+                  << "][0], HwT); cpw = fma(cpR[" << k << "], wd[" << k << "], cpw);\n";
         o << "  const S fT = f[0];\n"
              "  const S RT = " << lit(kRu) << " * T;\n"
              "  const S icp = icpm * " << lit(1.0 / kRu) << ";\n";
         for (int mm = 0; mm < ns; ++mm) {
-            o << "  { S HJ = 0.0";
-            for (int k = 0; k < ns; ++k) o << " + HRT[" << k << "]*J[" << 1 + k << "][" << 1 + mm << "]";
-            o << ";\n    S t = fma(rho, HJ, -Wbar*HS) * (-RT * rcpinv);\n"
+            std::vector<std::pair<double, std::string>> hj;
+            for (int k = 0; k < ns; ++k)
+                if (jnz[k][mm])
+                    hj.push_back({1.0, "HRT[" + std::to_string(k) + "]*J[" + std::to_string(1 + k) + "][" + std::to_string(1 + mm) + "]"});
+            o << "  { S HJ = " << lin_sum(hj) << ";\n"
+                 "    S t = fma(rho, HJ, -Wbar*HS) * (-RT * rcpinv);\n"
                  "    S u = fma(cpR[" << mm << "], icp * " << lit(kRu) << ", -Wbar);\n"
                  "    J[0][" << 1 + mm << "] = fma(-fT, u, t) * MW[" << ns + mm << "]; }\n";
         }
         o << "  J[0][0] = -" << lit(kRu) << " * (cpw + T*HwT - HS) * rcpinv - fT * (dcp * icp - iT);\n";
         for (int k = 0; k < ns; ++k) {
+            if (inert[k]) continue;   // a zero row
             // J_km = (1/W_m)(W_k Jc_km + Wbar g_k), g_k = f_k - W_k S_k / rho
             o << "  { const S g = fma(-MW[" << k << "], Sk[" << k << "] * irho, f[" << 1 + k << "]);\n"
                  "    const S wg = Wbar * g;\n";
@@ -515,7 +700,21 @@ struct Emitter {
           << "constexpr int NS = " << ns << ";\n"
           << "constexpr int NR = " << nr << ";\n"
           << "constexpr int N = NS + 1;\n"
-          << "constexpr double RU = " << lit(kRu) << ";\n\n";
+          << "constexpr double RU = " << lit(kRu) << ";\n";
+        // elimination order of the step matrix: T and the species some reaction
+        // changes first, then the species no reaction changes, whose rows of
+        // M = I/(gamma h) - J are the diagonal alone
+        {
+            std::vector<int> perm{0};
+            for (int k = 0; k < ns; ++k)
+                if (!inert[k]) perm.push_back(1 + k);
+            const int nact = (int)perm.size();
+            for (int k = 0; k < ns; ++k)
+                if (inert[k]) perm.push_back(1 + k);
+            o << "constexpr int NACT = " << nact << ";   // components with a non-trivial row\n"
+              << "constexpr int PERM[N] = {";
+            for (int i = 0; i <= ns; ++i) o << perm[i] << (i < ns ? ", " : "};\n\n");
+        }
         // source terms only
         thermo_table();
         o << "template <class S>\n__device__ __forceinline__ void rhs(const double* __restrict__ par, double p, "
@@ -550,7 +749,7 @@ struct Emitter {
              "double* __restrict__ gb, double* __restrict__ gE)\n{\n";
         prologue(true);
         cp_sum(true);
-        o << "  const S icpm = 1.0 / cpm;\n"
+        o << "  const S icpm = chem_math::recip(cpm);\n"
              "  const S rcpinv = T * sig * ip * icpm;\n"
              "  S colA[NS], colH[NS];\n"
              "#pragma unroll\n  for (int k = 0; k < NS; ++k) { colA[k] = 0.0; colH[k] = 0.0; }\n"
@@ -558,8 +757,9 @@ struct Emitter {
         for (int j = 0; j < nr; ++j) reaction(j, 3);
         o << "  S hw = 0.0, Wf = 0.0, cpw = 0.0;\n";
         for (int k = 0; k < ns; ++k)
-            o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw); cpw = fma(cpR[" << k << "], wd[" << k
-              << "], cpw); Wf = fma(w[" << 1 + k << "], MW[" << k << "] * (irho * wd[" << k << "]), Wf);\n";
+            if (!inert[k])
+                o << "  hw = fma(HRT[" << k << "], wd[" << k << "], hw); cpw = fma(cpR[" << k << "], wd[" << k
+                  << "], cpw); Wf = fma(w[" << 1 + k << "], MW[" << k << "] * (irho * wd[" << k << "]), Wf);\n";
         o << "  const S fT = -" << lit(kRu) << " * T * hw * rcpinv;\n"
              "  const S RT = " << lit(kRu) << " * T;\n"
              "  const S icp = icpm * " << lit(1.0 / kRu) << ";\n"

@@ -21,50 +21,76 @@ constexpr int NS = mech::NS;
 
 
 // ---- dense LU with partial pivoting, one matrix per lane ----
-// Row interchanges are made with selects (the pivot row differs per lane), on
-// the trailing columns only, and skipped when no lane of the wave needs one;
-// piv[k] records the row swapped into k at step k (LINPACK order) and bit k of
-// the returned wave-uniform mask says whether any lane swapped at step k.  The
-// diagonal of U is stored as its reciprocal.
+// The step matrix is eliminated in the order mech::PERM: T and the species
+// some reaction changes (positions 0 .. NACT-1) first, then the species no
+// reaction changes, whose rows of M = I/(gamma h) - J hold the diagonal alone.
+// Their entries in the first NACT columns are zero, so they never become
+// pivots there and take no row updates; when their own columns come, only
+// such rows remain below the diagonal.  Skipping them is exact: this is dense
+// LU with partial pivoting of the symmetrically permuted matrix, with the
+// structural zeros of those rows left out.  Row interchanges are made with
+// selects (the pivot row differs per lane), on the trailing columns only, and
+// skipped when no lane of the wave needs one; piv[a] records the position
+// swapped into position a at step a (LINPACK order) and bit a of the returned
+// wave-uniform mask says whether any lane swapped at step a.  The diagonal of
+// U is stored as its reciprocal.
+constexpr int NACT = mech::NACT;
+
+__device__ __forceinline__ constexpr int P(int a) { return mech::PERM[a]; }
+
 __device__ __forceinline__ unsigned lu_factor(double (&A)[N][N], int (&piv)[N], bool& ok)
 {
     unsigned swaps = 0u;
     ok = true;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
+    for (int a = 0; a < NACT; ++a) {
+        const int k = P(a);
         double amax = fabs(A[k][k]);
-        int p = k;
+        int p = a;
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
-            const double v = fabs(A[i][k]);
+        for (int b = a + 1; b < NACT; ++b) {
+            const double v = fabs(A[P(b)][k]);
             const bool c = v > amax;
             amax = c ? v : amax;
-            p = c ? i : p;
+            p = c ? b : p;
         }
-        piv[k] = p;
+        piv[a] = p;
         ok = ok && (amax > 0.0);
-        if (__any(p != k)) {
-            swaps |= 1u << k;
+        if (__any(p != a)) {
+            swaps |= 1u << a;
 #pragma unroll
-            for (int i = k + 1; i < N; ++i) {
-                const bool s = (p == i);
+            for (int b = a + 1; b < NACT; ++b) {
+                const bool s = (p == b);
+                const int i = P(b);
 #pragma unroll
-                for (int j = k; j < N; ++j) {
+                for (int c = a; c < N; ++c) {
+                    const int j = P(c);
                     const double akj = A[k][j], aij = A[i][j];
                     A[k][j] = s ? aij : akj;
                     A[i][j] = s ? akj : aij;
                 }
             }
         }
-        const double rp = 1.0 / A[k][k];
+        const double rp = chem_math::recip(A[k][k]);
         A[k][k] = rp;
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) {
+        for (int b = a + 1; b < NACT; ++b) {
+            const int i = P(b);
             const double l = A[i][k] * rp;
             A[i][k] = l;
 #pragma unroll
-            for (int j = k + 1; j < N; ++j) A[i][j] = fma(-l, A[k][j], A[i][j]);
+            for (int c = a + 1; c < N; ++c) {
+                const int j = P(c);
+                A[i][j] = fma(-l, A[k][j], A[i][j]);
+            }
         }
+    }
+#pragma unroll
+    for (int a = NACT; a < N; ++a) {     // rows with the diagonal alone
+        const int k = P(a);
+        piv[a] = a;
+        ok = ok && (fabs(A[k][k]) > 0.0);
+        A[k][k] = chem_math::recip(A[k][k]);
     }
     return swaps;
 }
@@ -84,25 +110,34 @@ __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&pi
                                          double (&b)[N])
 {
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        if (swaps & (1u << k)) {
-            const int p = opaque_index(piv[k]);
+    for (int a = 0; a < NACT; ++a) {
+        const int k = P(a);
+        if (swaps & (1u << a)) {
+            const int p = opaque_index(piv[a]);
 #pragma unroll
-            for (int i = k + 1; i < N; ++i) {
-                const bool s = (p == i);
+            for (int c = a + 1; c < NACT; ++c) {
+                const bool s = (p == c);
+                const int i = P(c);
                 const double bk = b[k], bi = b[i];
                 b[k] = s ? bi : bk;
                 b[i] = s ? bk : bi;
             }
         }
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) b[i] = fma(-A[i][k], b[k], b[i]);
+        for (int c = a + 1; c < NACT; ++c) {
+            const int i = P(c);
+            b[i] = fma(-A[i][k], b[k], b[i]);
+        }
     }
 #pragma unroll
-    for (int i = N - 1; i >= 0; --i) {
-        b[i] *= A[i][i];
+    for (int a = N - 1; a >= 0; --a) {
+        const int k = P(a);
+        b[k] *= A[k][k];
 #pragma unroll
-        for (int r = 0; r < i; ++r) b[r] = fma(-A[r][i], b[i], b[r]);
+        for (int c = 0; c < (a < NACT ? a : NACT); ++c) {
+            const int r = P(c);
+            b[r] = fma(-A[r][k], b[k], b[r]);
+        }
     }
 }
 
@@ -118,8 +153,8 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
 {
     double M[N][N], f[N];
     mech::rhs_jac(par, p, ip, y, f, M);
-    const double ghinv = 1.0 / (h * Rodas4::gamma);
-    const double hinv = 1.0 / h;
+    const double hinv = chem_math::recip(h);
+    const double ghinv = hinv * (1.0 / Rodas4::gamma);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
 #pragma unroll
@@ -167,7 +202,7 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
     for (int k = 0; k < N; ++k) {
         ynew[k] += u[k];
         const double sc = atol + rtol * fmax(fabs(y[k]), fabs(ynew[k]));
-        const double e = u[k] / sc;
+        const double e = u[k] * chem_math::recip(sc);
         acc = fma(e, e, acc);
         ok = ok && finite(ynew[k]);
     }
@@ -203,6 +238,9 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
     c.done = bad;
 }
 
+// x^(-1/4) for the step-size controller, as the reciprocal of two square roots
+__device__ __forceinline__ double inv_root4(double x) { return chem_math::recip(sqrt(sqrt(x))); }
+
 // One attempted substep (accepted or rejected), with the controller:
 // accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
 // a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)
@@ -222,7 +260,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
 #pragma unroll
         for (int k = 0; k < N; ++k) c.y[k] = ynew[k];
         c.t = last ? a.dt : c.t + h;
-        double fac = 0.9 * pow(fmax(en, 1e-16), -0.25);
+        double fac = 0.9 * inv_root4(fmax(en, 1e-16));
         fac = fmin(6.0, fmax(0.2, fac));
         if (c.rej_last) fac = fmin(1.0, fac);
         c.h = h * fac;
@@ -232,7 +270,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
         return h;
     }
     ++c.nrej;
-    c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
+    c.h = h * (ok ? fmax(0.2, 0.9 * inv_root4(en)) : 0.2);
     c.rej_last = true;
     return 0.0;
 }
@@ -540,24 +578,36 @@ namespace chem {
 __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
                                            double (&b)[N])
 {
+    // U^T (only the first NACT rows of U have entries off the diagonal)
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int a = 0; a < N; ++a) {
+        const int i = P(a);
         double v = b[i];
 #pragma unroll
-        for (int j = 0; j < i; ++j) v = fma(-A[j][i], b[j], v);
+        for (int c = 0; c < (a < NACT ? a : NACT); ++c) {
+            const int j = P(c);
+            v = fma(-A[j][i], b[j], v);
+        }
         b[i] = v * A[i][i];
     }
+    // L^T and the interchanges in reverse (L has entries below the diagonal in
+    // the first NACT rows and columns only)
 #pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
+    for (int a = NACT - 1; a >= 0; --a) {
+        const int k = P(a);
         double v = b[k];
 #pragma unroll
-        for (int i = k + 1; i < N; ++i) v = fma(-A[i][k], b[i], v);
+        for (int c = a + 1; c < NACT; ++c) {
+            const int i = P(c);
+            v = fma(-A[i][k], b[i], v);
+        }
         b[k] = v;
-        if (swaps & (1u << k)) {
-            const int p = opaque_index(piv[k]);
+        if (swaps & (1u << a)) {
+            const int p = opaque_index(piv[a]);
 #pragma unroll
-            for (int i = k + 1; i < N; ++i) {
-                const bool s = (p == i);
+            for (int c = a + 1; c < NACT; ++c) {
+                const bool s = (p == c);
+                const int i = P(c);
                 const double bk = b[k], bi = b[i];
                 b[k] = s ? bi : bk;
                 b[i] = s ? bk : bi;
@@ -574,8 +624,8 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
     using chem_math::Dual;
     double M[N][N], f[N];
     mech::rhs_jac(par, p, ip, y, f, M);
-    const double ghinv = 1.0 / (h * Rodas4::gamma);
-    const double hinv = 1.0 / h;
+    const double hinv = chem_math::recip(h);
+    const double ghinv = hinv * (1.0 / Rodas4::gamma);
     for (int i = 0; i < N; ++i) {
         for (int j = 0; j < N; ++j) M[i][j] = -M[i][j];
         M[i][i] += ghinv;
