@@ -59,6 +59,26 @@ def recorded_traffic(mech_file: str):
     return None
 
 
+def recorded_counters(mech_file: str):
+    """SQ counters per launch of the headline kernel from the committed
+    rocprofv3 summary, or None if the kernel changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"kernel source hash: {kernel_source_hash(mech_file)}" not in text:
+        return None
+    out = {}
+    for line in text.splitlines():
+        parts = [x.strip() for x in line.strip().strip("|").split("|")]
+        if len(parts) == 2 and parts[0].startswith("SQ_"):
+            try:
+                out[parts[0]] = float(parts[1])
+            except ValueError:
+                pass
+    return out or None
+
+
 def flops_per_substep(ns: int, nr: int, s: int = RODAS4_STAGES) -> float:
     """Algorithmic FP64 flops of one RODAS4 substep attempt (FMA = 2 flops):
     Jacobian 50 nr + 4 n^2, LU (2/3) n^3, and per stage a source-term
@@ -96,7 +116,7 @@ def cpu_baseline(T, p, Y, w, frac, seed=7):
                       f"{el:.2f} s wall"}
 
 
-def amr_leg(chem, torch, dev, steps, plain_mechs=("m9", "m13")):
+def amr_leg(chem, torch, dev, steps, plain_mechs=("m9", "m13"), mechs=None):
     """64 independent fields of log-uniform 10k-2M cells (28.0 M cells in all),
     RDE-shaped states, for the 9- and the 13-species (third-body + Troe)
     mechanism: one persistent work-stealing launch over all fields against one
@@ -108,7 +128,7 @@ def amr_leg(chem, torch, dev, steps, plain_mechs=("m9", "m13")):
     sizes = amr_field_sizes(w["seed"], w["n_fields"])
     out = {"workload": "amr64", "fields": len(sizes), "cells": int(sum(sizes)), "dt": w["dt"],
            "rtol": w["rtol"], "atol": w["atol"]}
-    for name in w["mechs"]:
+    for name in (mechs or w["mechs"]):
         mech = chem.Mechanism(mech_path(name))
         text = mech_text(name)
         init, work = [], []
@@ -307,6 +327,8 @@ def main():
     ap.add_argument("--no-big", action="store_true")
     ap.add_argument("--big-only", action="store_true")
     ap.add_argument("--amr-only", action="store_true")
+    ap.add_argument("--amr-mechs", default="m9,m13", help="mechanisms of the batched leg (--amr-only)")
+    ap.add_argument("--amr-plain", default="m9,m13", help="mechanisms whose per-field plain launches are timed")
     ap.add_argument("--adjoint-only", action="store_true")
     ap.add_argument("--adjoint-cpu-cells", type=int, default=192)
     ap.add_argument("--adjoint-workload", default="adj256k")
@@ -337,7 +359,9 @@ def main():
         print(json.dumps({"big4m": big_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps))}))
         return
     if args.amr_only:
-        print(json.dumps({"amr64": amr_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps))}))
+        print(json.dumps({"amr64": amr_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps),
+                                           plain_mechs=tuple(x for x in args.amr_plain.split(",") if x),
+                                           mechs=[x for x in args.amr_mechs.split(",") if x])}))
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(chem, torch, torch.device("cuda:0"), max(1, args.steps),
@@ -446,6 +470,38 @@ def main():
         "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
     }
+    # the field's critical path: its most expensive cell integrated alone (one
+    # lane of one wave), which no schedule of the whole field can beat
+    tot = (na0 + nr0).cpu().numpy()
+    ci = int(np.argmax(tot))
+    Tc, pc, Yc = T0[ci:ci + 1].clone(), pg[ci:ci + 1].clone(), Y0[ci:ci + 1].clone()
+    chem.integrate(mech, Tc, pc, Yc, w["dt"], w["rtol"], w["atol"], form=chem.FORM_PLAIN)
+    solo = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        chem.integrate(mech, Tc, pc, Yc, w["dt"], w["rtol"], w["atol"], form=chem.FORM_PLAIN, stats=False)
+        b.record(stream)
+        torch.cuda.synchronize()
+        solo.append(a.elapsed_time(b))
+    solo_ms = float(np.median(solo))
+    line["critical_path"] = {"cell": ci, "substeps": int(tot[ci]), "solo_ms": solo_ms,
+                             "us_per_substep": 1e3 * solo_ms / max(1, int(tot[ci])),
+                             "of_kernel_ms": solo_ms / r["kernel_ms"]}
+    ctr = recorded_counters(os.path.relpath(mech_path(w["mech"]), ROOT)) if head == "persistent" else None
+    if ctr and "SQ_INSTS_VALU" in ctr:
+        wave_substeps = r["substeps"] / 64.0
+        c = {"profile": TRAFFIC_PROFILE, "SQ_INSTS_VALU": ctr["SQ_INSTS_VALU"],
+             "valu_per_wave_substep": ctr["SQ_INSTS_VALU"] / wave_substeps}
+        if "SQ_INSTS_VALU_FLOPS_FP64" in ctr:
+            # counted per wave instruction: x 64 lanes, inactive lanes and the
+            # exp/log sequences included
+            tf = ctr["SQ_INSTS_VALU_FLOPS_FP64"] * 64 / (r["kernel_ms"] * 1e-3) / 1e12
+            c["fp64_counter_tflops"] = tf
+            c["fp64_counter_frac"] = tf / (PEAK_FP64_VALU / 1e12)
+        if "SQ_THREAD_CYCLES_VALU" in ctr and "SQ_ACTIVE_INST_VALU" in ctr:
+            c["valu_utilization"] = ctr["SQ_THREAD_CYCLES_VALU"] / (64.0 * ctr["SQ_ACTIVE_INST_VALU"])
+        line["counters"] = c
     if "plain" in results and "persistent" in results:
         line["persistent_over_plain"] = results["plain"]["ms_per_step"] / results["persistent"]["ms_per_step"]
     if "persistent" in results:

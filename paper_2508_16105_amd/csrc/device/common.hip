@@ -37,6 +37,9 @@ struct StepArgs {
 
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
+// x^(-1/4) for the step-size controller, as the reciprocal of two square roots
+__device__ __forceinline__ double inv_root4(double x) { return chem_math::recip(sqrt(sqrt(x))); }
+
 struct IntegrateArgs {
     const double* par;
     double* T;

@@ -238,9 +238,6 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
     c.done = bad;
 }
 
-// x^(-1/4) for the step-size controller, as the reciprocal of two square roots
-__device__ __forceinline__ double inv_root4(double x) { return chem_math::recip(sqrt(sqrt(x))); }
-
 // One attempted substep (accepted or rejected), with the controller:
 // accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
 // a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)

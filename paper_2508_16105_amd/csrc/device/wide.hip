@@ -369,7 +369,7 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
     lds_sync();
     const S T = L[mech::L_Y];
     const S lnT = log(T);
-    const S iT = 1.0 / T;
+    const S iT = chem_math::recip(T);
     const S T2 = T * T, T3 = T2 * T, T4 = T2 * T2;
     S cpR = 0.0, HRT = 0.0, Gk = 0.0, dcpR = 0.0;
     if (sp) {
@@ -403,7 +403,7 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
     const double iW = sp ? MW[NS + k] : 0.0;
     const S yw = sp ? yi * iW : S(0.0);
     const S sig = gsum(yw);
-    const S Wbar = 1.0 / sig;
+    const S Wbar = chem_math::recip(sig);
     const S rho = p * Wbar * iT * (1.0 / mech::RU);
     const S irho = mech::RU * T * sig * ip;
     const S ctot = p * iT * (1.0 / mech::RU);
@@ -453,7 +453,7 @@ __device__ __forceinline__ S rhs(const double* __restrict__ par, double p, doubl
     }
     const S cpm = gsum(cpR * yw);
     const S hw = gsum(HRT * wdot);
-    const S icpm = 1.0 / cpm;
+    const S icpm = chem_math::recip(cpm);
     const S rcpinv = T * sig * ip * icpm;
     const S fT = -mech::RU * T * hw * rcpinv;
     const S fk = W * (irho * wdot);
@@ -626,7 +626,7 @@ __device__ __forceinline__ unsigned long long lu(double (&A)[N], bool& ok, doubl
             for (int j = k; j < N; ++j) prow[j] = PR[j];
             lds_sync();
         }
-        const double rp = 1.0 / prow[k];
+        const double rp = chem_math::recip(prow[k]);
         if (i == k) {
             A[k] = rp;
         } else if (i > k && i < N) {
@@ -674,8 +674,8 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
     double A[N];
     double g[ROUNDS][3];
     const double f0 = rhs<double, F_JAC>(par, p, ip, yi, L, A, 0.0, g);
-    const double ghinv = 1.0 / (h * Rodas4::gamma);
-    const double hinv = 1.0 / h;
+    const double hinv = chem_math::recip(h);
+    const double ghinv = hinv * (1.0 / Rodas4::gamma);
 #pragma unroll
     for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - A[j];
     bool ok;
@@ -706,7 +706,7 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
     }
     ynew += u[Rodas4::S - 1];
     const double sc = atol + rtol * fmax(fabs(yi), fabs(ynew));
-    const double e = u[Rodas4::S - 1] / sc;
+    const double e = u[Rodas4::S - 1] * chem_math::recip(sc);
     errn = sqrt(gsum(i < N ? e * e : 0.0) * (1.0 / N));
     const bool bad = gany(i < N && !finite(ynew));
     return ok && !bad && finite(errn);
@@ -762,7 +762,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
     if (ok && en <= 1.0) {
         c.y = ynew;
         c.t = last ? a.dt : c.t + h;
-        double fac = 0.9 * pow(fmax(en, 1e-16), -0.25);
+        double fac = 0.9 * chem::inv_root4(fmax(en, 1e-16));
         fac = fmin(6.0, fmax(0.2, fac));
         if (c.rej_last) fac = fmin(1.0, fac);
         c.h = h * fac;
@@ -772,7 +772,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
         return h;
     }
     ++c.nrej;
-    c.h = h * (ok ? fmax(0.2, 0.9 * pow(en, -0.25)) : 0.2);
+    c.h = h * (ok ? fmax(0.2, 0.9 * chem::inv_root4(en)) : 0.2);
     c.rej_last = true;
     return 0.0;
 }
@@ -876,8 +876,8 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
     const int i = gl_local();
     double J0[N], A[N], dummy[N];
     const double f0 = rhs<double, F_JAC>(par, p, ip, yi, L, J0, 0.0, g);
-    const double ghinv = 1.0 / (h * Rodas4::gamma);
-    const double hinv = 1.0 / h;
+    const double hinv = chem_math::recip(h);
+    const double ghinv = hinv * (1.0 / Rodas4::gamma);
 #pragma unroll
     for (int j = 0; j < N; ++j) A[j] = (j == i ? ghinv : 0.0) - J0[j];
     bool ok;
