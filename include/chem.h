@@ -199,6 +199,38 @@ int chem_integrate(const chem_mechanism *m, int64_t ncell, double *T, const doub
                    chem_stats *stats, int32_t *cell_status, int32_t *nacc, int32_t *nrej,
                    void *stream);
 
+/* Largest ncell of chem_integrate_noalloc: its scratch holds 17 bytes per
+   cell plus 4 KiB, about 36 MB per device. */
+#define CHEM_NOALLOC_MAX_CELLS 2097152
+
+/* chem_integrate without any device allocation, for callers that cannot
+   allocate: code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc.  It runs the persistent form (cells started most
+   expensive first, work-stealing waves) with every temporary -- queue heads,
+   cost histogram, field table, per-cell cost buckets and permutation, and
+   the status/substep counters the caller does not pass -- in a fixed scratch
+   area the library holds on each device (CHEM_NOALLOC_MAX_CELLS cells, kept
+   until the process ends), and calls no hipMalloc, hipFree or allocating
+   library routine.  Arguments as chem_integrate, without stats: T, Y (in/out)
+   and p are device arrays of ncell <= CHEM_NOALLOC_MAX_CELLS cells;
+   cell_status, nacc, nrej are nullable device outputs; opt may be NULL
+   (order, cost, block, refill, max_substeps and hmin_rel are used; form is
+   ignored; h0 must be NULL).  The work is enqueued on `stream` and the call
+   returns without waiting, so failed cells show only in cell_status.
+   Results are bitwise equal to chem_integrate with CHEM_FORM_PERSISTENT.
+   Set-up: the mechanism's device code must be loaded on the current device
+   beforehand -- chem_load_mechanism does it when a gfx950 device is current,
+   and any other entry point does it on first use on a device; otherwise
+   CHEM_E_INVAL.  After chem_set_params the next call copies the parameters
+   and waits for that copy.  Every call on one GPU shares that GPU's scratch
+   and leaves its contents behind (the kernels clear what must start at
+   zero): calls that overlap on one GPU -- on unordered streams, or from
+   different mechanism handles -- race.  Errors: CHEM_E_INVAL (bad argument,
+   ncell above the limit, device not set up; nothing launched), CHEM_E_HIP. */
+int chem_integrate_noalloc(const chem_mechanism *m, int64_t ncell, double *T, const double *p,
+                           double *Y, double dt, double rtol, double atol, const chem_options *opt,
+                           int32_t *cell_status, int32_t *nacc, int32_t *nrej, void *stream);
+
 /* Integrate every cell over [0, dt] as chem_integrate does and return the
    reaction terms a flow solver adds to its species and energy equations
    (Appendix A, eqs. (21) and (20)) for an operator-split step: the mean rates

@@ -15,7 +15,7 @@ import ctypes as C
 from . import _lib
 from ._lib import ChemError, FORM_AUTO, FORM_PERSISTENT, FORM_PLAIN, ORDER_COST, ORDER_NATURAL
 
-__all__ = ["Mechanism", "integrate", "integrate_source", "integrate_batched", "integrate_adjoint", "eval_source",
+__all__ = ["Mechanism", "integrate", "integrate_noalloc", "integrate_source", "integrate_batched", "integrate_adjoint", "eval_source",
            "step_fixed", "euler1d_init", "euler1d_step", "ChemIntegrate", "ChemError", "FORM_AUTO", "FORM_PLAIN",
            "FORM_PERSISTENT", "ORDER_COST", "ORDER_NATURAL", "version"]
 
@@ -124,6 +124,27 @@ def integrate(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stat
     _lib.check(rc, allow=(-6,) if allow_failed else ())
     out = (T, Y, s.as_dict() if s is not None else None)
     return out + (st, nacc, nrej) if return_counts else out
+
+
+def integrate_noalloc(mech: Mechanism, T, p, Y, dt, rtol, atol, *, status=None, nacc=None, nrej=None,
+                      stream=None, **opts):
+    """chem_integrate_noalloc: advance T [ncell] and Y [ncell, ns] in place
+    with no device allocation (persistent form, the library's fixed scratch);
+    status/nacc/nrej: optional int32 [ncell] GPU tensors.  Asynchronous."""
+    n = T.shape[0]
+    for t, nm, sh in ((T, "T", (n,)), (p, "p", (n,)), (Y, "Y", (n, mech.ns))):
+        _check_tensor(t, nm, sh)
+    torch = _torch()
+    for t, nm in ((status, "status"), (nacc, "nacc"), (nrej, "nrej")):
+        if t is not None:
+            _check_tensor(t, nm, (n,), torch.int32)
+    if opts.get("cost") is not None and not isinstance(opts["cost"], (list, tuple)):
+        opts["cost"] = [opts["cost"]]
+    o = _options(**opts)
+    _lib.check(_lib.lib().chem_integrate_noalloc(mech.h, n, _ptr(T), _ptr(p), _ptr(Y), float(dt), float(rtol),
+                                                  float(atol), C.byref(o), _ptr(status), _ptr(nacc), _ptr(nrej),
+                                                  _stream(stream)))
+    return T, Y
 
 
 def integrate_source(mech: Mechanism, T, p, Y, dt, rtol, atol, *, form=FORM_PLAIN, stats=True,

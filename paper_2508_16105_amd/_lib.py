@@ -7,6 +7,7 @@ import ctypes as C
 import pathlib
 
 LIB_PATH = pathlib.Path(__file__).resolve().parent / "libchemmi.so"
+NOALLOC_MAX_CELLS = 2097152        # CHEM_NOALLOC_MAX_CELLS
 
 CHEM_OK = 0
 ERRORS = {-1: "CHEM_E_INVAL", -2: "CHEM_E_PARSE", -3: "CHEM_E_MECH_INVALID", -4: "CHEM_E_HIP",
@@ -17,6 +18,7 @@ ORDER_COST, ORDER_NATURAL = 1, 2
 EXPORTS = ["chem_load_mechanism", "chem_load_chemkin", "chem_load_openfoam", "chem_free_mechanism", "chem_mechanism_info", "chem_get_params",
            "chem_set_params", "chem_eval_source", "chem_step_fixed", "chem_integrate",
            "chem_integrate_source", "chem_euler1d_init", "chem_euler1d_step", "chem_integrate_batched", "chem_integrate_adjoint",
+           "chem_integrate_noalloc",
            "chem_last_error", "chem_version"]
 
 
@@ -64,6 +66,8 @@ def lib():
         L.chem_step_fixed.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, vp, vp, vp, vp]
         L.chem_integrate.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, C.POINTER(Options),
                                      C.POINTER(Stats), vp, vp, vp, vp]
+        L.chem_integrate_noalloc.argtypes = [vp, i64, vp, vp, vp, dbl, dbl, dbl, C.POINTER(Options),
+                                             vp, vp, vp, vp]
         L.chem_euler1d_init.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.chem_euler1d_step.argtypes = [vp, i64, dbl, dbl, vp, vp, vp, dbl, dbl, C.POINTER(Options),
                                         C.POINTER(Stats), C.POINTER(dbl), vp]

@@ -26,7 +26,8 @@ PREBUILT = [("m9", None), ("m13", None), ("m32", None), ("m9", "0"), ("m13", "0"
 PREBUILT_CHEMKIN = ["m9", "m32x"]
 # OpenFOAM renderings the tests load
 PREBUILT_OPENFOAM = ["m9", "m32s"]
-HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "chemkin.cpp", "foam.cpp", "codegen.cpp"]
+HOST_SOURCES = ["capi.cpp", "runtime.cpp", "module.cpp", "mechanism.cpp", "chemkin.cpp", "foam.cpp", "codegen.cpp",
+                "noalloc.hip"]
 
 
 def embed_device_source():

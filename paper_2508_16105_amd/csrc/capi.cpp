@@ -134,6 +134,9 @@ int finish_load(std::unique_ptr<chem_mechanism> m, chem_mechanism** out)
         m->source = device_source(generate_wide_source(m->data, m->layout), true);
     }
     if (int rc = build_code_object(m->source, m->code, err, &m->cache_file)) return set_error(rc, err);
+    // with a gfx950 device current, load the code there now, so that the
+    // allocation-free entry point finds it set up
+    prepare_current_device(m.get());
     *out = m.release();
     return CHEM_OK;
 }
@@ -325,6 +328,30 @@ int chem_integrate(const chem_mechanism* mc, int64_t ncell, double* T, const dou
     }
     return run_plain(m, ncell, T, p, Y, dt, rtol, atol, o, stats, cell_status, nacc, nrej,
                      (hipStream_t)stream);
+}
+
+int chem_integrate_noalloc(const chem_mechanism* mc, int64_t ncell, double* T, const double* p, double* Y,
+                           double dt, double rtol, double atol, const chem_options* opt, int32_t* cell_status,
+                           int32_t* nacc, int32_t* nrej, void* stream)
+{
+    g_last_error.clear();
+    auto* m = const_cast<chem_mechanism*>(mc);
+    if (!m || ncell < 0) return set_error(CHEM_E_INVAL, "bad mechanism or ncell");
+    if (int rc = check_tolerances(dt, rtol, atol)) return rc;
+    if ((uint64_t)ncell > (uint64_t)CHEM_NOALLOC_MAX_CELLS)
+        return set_error(CHEM_E_INVAL, "ncell exceeds CHEM_NOALLOC_MAX_CELLS");
+    if (ncell == 0) return CHEM_OK;
+    if (int rc = check_device_ptrs({{T, "T"}, {p, "p"}, {Y, "Y"}})) return rc;
+    for (auto pr : {std::make_pair((const void*)cell_status, "cell_status"),
+                    std::make_pair((const void*)nacc, "nacc"), std::make_pair((const void*)nrej, "nrej")})
+        if (pr.first && !is_device_ptr(pr.first))
+            return set_error(CHEM_E_INVAL, std::string(pr.second) + " is not a device pointer");
+    Options o = resolve_options(opt);
+    if (o.h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the allocation-free (persistent) form");
+    if (o.cost && o.cost[0] && !is_device_ptr(o.cost[0])) return set_error(CHEM_E_INVAL, "cost[0] is not a device pointer");
+    std::lock_guard<std::mutex> lk(m->mu);
+    DoneMark mark{m, (hipStream_t)stream};
+    return run_noalloc(m, ncell, T, p, Y, dt, rtol, atol, o, cell_status, nacc, nrej, (hipStream_t)stream);
 }
 
 int chem_integrate_source(const chem_mechanism* mc, int64_t ncell, double* T, const double* p, double* Y,

@@ -61,6 +61,8 @@ int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hi
     return 0;
 }
 
+int state_ready(chem_mechanism* m, DeviceState& d, hipStream_t stream, DeviceState** out);
+
 int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
 {
     (void)stream;
@@ -107,8 +109,16 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
         HIPCHECK(hipEventCreate(&d.ev0), "hipEventCreate");
         HIPCHECK(hipEventCreate(&d.ev1), "hipEventCreate");
         HIPCHECK(hipEventCreateWithFlags(&d.done, hipEventDisableTiming), "hipEventCreate");
+        void* na = nullptr;
+        if (int rc2 = noalloc_scratch(dev, &na)) return rc2;
+        d.noalloc = static_cast<unsigned char*>(na);
         d.par_version = 0;
     }
+    return state_ready(m, d, stream, out);
+}
+
+int state_ready(chem_mechanism* m, DeviceState& d, hipStream_t stream, DeviceState** out)
+{
     // the previous call's work may still run on another stream
     if (d.done_recorded) HIPCHECK(hipStreamWaitEvent(stream, d.done, 0), "order after the previous call");
     if (d.par_version != m->params_version) {
@@ -121,6 +131,27 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
     }
     *out = &d;
     return 0;
+}
+
+void prepare_current_device(chem_mechanism* m)
+{
+    int count = 0, dev = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0 || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        std::string(prop.gcnArchName).rfind("gfx950", 0) != 0) {
+        (void)hipGetLastError();
+        return;
+    }
+    DeviceState* d;
+    if (device_state(m, nullptr, &d)) {
+        // left for the first call on the device to report
+        release_device_state(m);
+        (void)hipGetLastError();
+    }
 }
 
 void mark_done(chem_mechanism* m, hipStream_t stream)
@@ -501,6 +532,89 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
     *stats = tot;
     if (tot.failed) return set_error(CHEM_E_CELL_FAILED, std::to_string(tot.failed) + " cells failed");
     return 0;
+}
+
+// ---------------- allocation-free persistent launch ----------------
+
+int run_noalloc(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+                double rtol, double atol, const Options& o, int32_t* status, int32_t* nacc, int32_t* nrej,
+                hipStream_t stream)
+{
+    if ((uint64_t)ncell > kNoallocMaxCells)
+        return set_error(CHEM_E_INVAL, "ncell " + std::to_string(ncell) + " exceeds CHEM_NOALLOC_MAX_CELLS (" +
+                                           std::to_string(kNoallocMaxCells) + ")");
+    if (o.h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the persistent form");
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev), "hipGetDevice");
+    auto it = m->devices.find(dev);
+    if (it == m->devices.end() || !it->second.module || !it->second.noalloc)
+        return set_error(CHEM_E_INVAL, "the mechanism's device code is not set up on device " + std::to_string(dev) +
+                                           " (load the mechanism with that device current, or call another entry "
+                                           "point on it first)");
+    DeviceState* d;
+    if (int rc = state_ready(m, it->second, stream, &d)) return rc;
+    unsigned char* base = d->noalloc;
+    auto* heads = reinterpret_cast<unsigned long long*>(base + kNoallocHeadsOff);
+    auto* hist = reinterpret_cast<unsigned*>(base + kNoallocHistOff);
+    char* blk = reinterpret_cast<char*>(base + kNoallocBlockOff);
+    auto* counters = reinterpret_cast<int32_t*>(base + kNoallocCountersOff);
+    FieldDesc f;
+    f.T = T;
+    f.p = p;
+    f.Y = Y;
+    f.status = status ? status : counters;
+    f.nacc = nacc ? nacc : counters + kNoallocMaxCells;
+    f.nrej = nrej ? nrej : counters + 2 * kNoallocMaxCells;
+    f.cost = o.cost ? o.cost[0] : nullptr;
+    f.ncell = (long)ncell;
+    f.start = 0;
+    const StepArgs s = step_args(dt, rtol, atol, o);
+    LaunchConfig c;
+    if (m->wide) {
+        c = LaunchConfig{64, 1, 1};
+    } else if (o.block && o.refill) {
+        c = LaunchConfig{o.block, std::max(1, o.waves_per_simd), o.refill};
+    } else {
+        auto t = d->tuned.find(size_bucket(ncell));   // a shape the tuner chose earlier, else the default
+        if (t != d->tuned.end()) c = t->second;
+    }
+    if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
+    if (!m->wide && d->stage_lds(c.block) > d->lds_per_block)
+        return set_error(CHEM_E_INVAL, "block too large for the stage vectors in LDS");
+    PersistHeader h = header_for(*d, ncell, 1, c, s, m->wide ? CHEM_ORDER_NATURAL : o.order);
+    h.bucket = base + kNoallocBucketOff;
+    h.perm = reinterpret_cast<int*>(base + kNoallocPermOff);
+    h.hist = hist;
+    h.cursor = hist + kCostBuckets;
+    if (int rc = noalloc_write_block(blk, h, f, stream)) return rc;
+    struct { const char* blk; unsigned long long* h; } ra{blk, heads};
+    struct { const char* blk; unsigned long long* heads; const double* par; } pa{blk, heads, d->par};
+    if (m->wide) {
+        if (int rc = launch_1d(d->f_reset, 256, 256, &ra, sizeof ra, stream, "chem_reset_heads")) return rc;
+        const unsigned per_cu = std::max<unsigned>(
+            1u, std::min<unsigned>(8u, (unsigned)(160u * 1024u / std::max(1u, m->layout.lds_bytes()))));
+        const int64_t waves = std::min<int64_t>((int64_t)d->num_cu * per_cu,
+                                                (ncell + m->layout.cells_per_wave() - 1) / m->layout.cells_per_wave());
+        return launch_1d(d->f_persistent, waves * 64, 64, &pa, sizeof pa, stream, "chem_persistent",
+                         m->layout.lds_bytes());
+    }
+    auto launch = [&](hipFunction_t fn, unsigned grid, unsigned block, unsigned shmem, void* args, size_t size,
+                      const char* what) {
+        void* cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
+                       HIP_LAUNCH_PARAM_END};
+        const hipError_t e = hipModuleLaunchKernel(fn, grid, 1, 1, block, 1, 1, shmem, stream, nullptr, cfg);
+        return e == hipSuccess ? 0 : hip_error(e, what);
+    };
+    struct { const char* blk; const double* par; } ka{blk, d->par};
+    struct { const char* blk; } sa{blk};
+    const unsigned sweep = (unsigned)d->num_cu * 4;
+    int rc = launch(d->f_reset, 1, 256, 0, &ra, sizeof ra, "chem_reset_heads");
+    if (!rc) rc = launch(d->f_okey, sweep, 256, 0, &ka, sizeof ka, "chem_order_key");
+    if (!rc) rc = launch(d->f_oscan, 1, kCostBuckets, 0, &sa, sizeof sa, "chem_order_scan");
+    if (!rc) rc = launch(d->f_oscatter, sweep, 256, 0, &sa, sizeof sa, "chem_order_scatter");
+    if (!rc) rc = launch(d->f_persistent, grid_of(*d, c), c.block, d->stage_lds(c.block), &pa, sizeof pa,
+                         "chem_persistent");
+    return rc;
 }
 
 // ---------------- discrete adjoint ----------------

@@ -113,6 +113,21 @@ struct PersistHeader {
     unsigned* cursor;
 };
 
+// Scratch of the allocation-free entry point (noalloc.hip), per device:
+// queue heads (64 u64), cost histogram and cursors (2 x 256 u32), the field
+// table (header + one field), then per cell the status and substep counters
+// (3 int32, used when the caller passes none), the cost permutation (int32)
+// and the cost bucket (uint8), for up to kNoallocMaxCells cells.
+constexpr size_t kNoallocMaxCells = CHEM_NOALLOC_MAX_CELLS;
+constexpr int kNoallocMaxDevices = 64;
+constexpr size_t kNoallocHeadsOff = 0;
+constexpr size_t kNoallocHistOff = 512;
+constexpr size_t kNoallocBlockOff = 2560;
+constexpr size_t kNoallocCountersOff = 4096;
+constexpr size_t kNoallocPermOff = kNoallocCountersOff + 12 * kNoallocMaxCells;
+constexpr size_t kNoallocBucketOff = kNoallocPermOff + 4 * kNoallocMaxCells;
+constexpr size_t kNoallocBytes = kNoallocBucketOff + kNoallocMaxCells;
+
 struct Options {
     int form = CHEM_FORM_AUTO;
     int max_substeps = 100000;
@@ -182,6 +197,7 @@ struct DeviceState {
     hipEvent_t done = nullptr;
     bool done_recorded = false;
     size_t lds_per_block = 65536;
+    unsigned char* noalloc = nullptr;    // this device's allocation-free scratch (see noalloc.hip)
     int n = 0;                           // state size ns + 1
     // LDS for the RODAS4 stage vectors u_1..u_5 of every lane of a workgroup
     unsigned stage_lds(int block) const { return (unsigned)(block * 5 * n * sizeof(double)); }
@@ -216,6 +232,21 @@ void release_device_state(chem_mechanism* m);
 
 int launch_1d(hipFunction_t f, int64_t n, int block, void* args, size_t size, hipStream_t stream,
               const char* what, unsigned shmem = 0);
+
+// Device address of this device's allocation-free scratch (hipGetSymbolAddress
+// once per device, with `device` current), and the field-table writer.
+int noalloc_scratch(int device, void** out);
+int noalloc_write_block(char* dst, const PersistHeader& h, const FieldDesc& f, hipStream_t stream);
+
+// chem_integrate_noalloc: the persistent form with every temporary in the
+// device's fixed scratch; needs the device state set up already.
+int run_noalloc(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
+                double rtol, double atol, const Options& o, int32_t* status, int32_t* nacc, int32_t* nrej,
+                hipStream_t stream);
+
+// Set up the device state on the current device if a gfx950 device is
+// current (at mechanism load); no effect without a usable device.
+void prepare_current_device(chem_mechanism* m);
 
 int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
               double rtol, double atol, const Options& o, chem_stats* stats, int32_t* status,
