@@ -64,7 +64,9 @@ enum chem_cell_status {
     CHEM_CELL_OK = 0,
     CHEM_CELL_MAXSTEPS = 1,     /* max_substeps attempts without reaching dt */
     CHEM_CELL_HMIN = 2,         /* step size fell below hmin_rel * dt */
-    CHEM_CELL_NONFINITE = 3,    /* reserved */
+    CHEM_CELL_NONFINITE = 3,    /* adjoint only: the checkpointed rerun of a cell took more
+                                   accepted steps than its sizing pass (not expected: both
+                                   run the same code on the same input) */
     CHEM_CELL_BADINPUT = 4      /* T <= 0, p <= 0 or a non-finite input */
 };
 
@@ -192,8 +194,9 @@ int chem_step_fixed(const chem_mechanism *m, int64_t ncell, const double *T, con
    p in; cell_status[ncell] (nullable, out); nacc/nrej[ncell] (nullable, out:
    accepted and rejected substeps per cell).  opt and stats are host pointers
    and may be NULL.  dt > 0, rtol > 0, atol >= 0 or CHEM_E_INVAL.  Returns
-   CHEM_E_CELL_FAILED when stats is given and a cell failed (without stats the
-   call does not wait for the result and returns CHEM_OK). */
+   CHEM_E_CELL_FAILED when stats is given and a cell failed.  Without stats
+   the call does not wait for the result and returns CHEM_OK: a failed cell
+   then shows only in cell_status (keep it, or pass stats, to detect one). */
 int chem_integrate(const chem_mechanism *m, int64_t ncell, double *T, const double *p,
                    double *Y, double dt, double rtol, double atol, const chem_options *opt,
                    chem_stats *stats, int32_t *cell_status, int32_t *nacc, int32_t *nrej,
@@ -272,16 +275,21 @@ int chem_euler1d_init(const chem_mechanism *m, int64_t ncell, const double *T, c
    e_s).  rtol, atol, opt: as chem_integrate (opt->h0 must be NULL).  stats:
    the chemistry step's.  max_cfl: NULL, or receives max over cells of
    (|u| + c) dt / dx with the frozen sound speed c (the step is taken whatever
-   its value; it is stable for max_cfl <= 1).  Synchronises the stream.
-   Errors: CHEM_E_INVAL for bad arguments or a cell whose state gives no
-   temperature (nothing written then); CHEM_E_CELL_FAILED if a cell's
-   chemistry failed (its U_out entries are NaN). */
+   its value; it is stable for max_cfl <= 1).  The step keeps its checks on
+   the device and synchronises the stream once, at its end, for one 16-byte
+   readback (the bad-state flag and the largest CFL number).  Errors:
+   CHEM_E_INVAL for bad arguments (nothing launched) or a cell whose state
+   gives no temperature (U_out is then not written; T holds the Newton
+   iterates); CHEM_E_CELL_FAILED if a cell's chemistry failed (its U_out
+   entries are NaN). */
 int chem_euler1d_step(const chem_mechanism *m, int64_t ncell, double dx, double dt, const double *U,
                       double *U_out, double *T, double rtol, double atol, const chem_options *opt,
                       chem_stats *stats, double *max_cfl, void *stream);
 
 /* Integrate nfield independent fields (e.g. the cell sets of different mesh
-   refinement levels) of sizes ncell[f] in one launch.  T, p, Y are host
+   refinement levels) of sizes ncell[f] in one launch: the single-GPU analogue
+   of the paper's dynamic load balancing on measured compute time
+   (Sec. 3.3.1), with cells rather than subdomains as the unit of balance.  T, p, Y are host
    arrays of nfield device pointers.  With CHEM_FORM_PERSISTENT (the default
    here) one persistent work-stealing kernel processes all fields: waves pull
    cells from per-XCD queues, steal from the others when theirs is empty, and

@@ -129,7 +129,10 @@ struct UpdateArgs {
     long ncell;
     double dt, dx;
     double* Unew;
-    double* cfl;          // per cell (|u| + c) dt / dx
+    unsigned long long* cflmax;   // max over cells of (|u| + c) dt / dx, as the bits of a
+                                  // non-negative double (integer order = numeric order);
+                                  // cleared by chem_euler_prim
+    const int* bad;               // set by chem_euler_prim: write nothing if any cell is bad
 };
 
 // Rusanov flux between the states (UL, pL, uL, cL) and (UR, ...): the mean of
@@ -156,7 +159,17 @@ __device__ __forceinline__ void flux(const double* __restrict__ UL, double pL, d
 extern "C" __global__ void __launch_bounds__(256) chem_euler_update(UpdateArgs a)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ncell) return;
+    // the block's largest CFL number, one atomic per block
+    __shared__ double smax[256];
+    const double cfl = i < a.ncell ? (fabs(a.u[i]) + a.c[i]) * (a.dt / a.dx) : 0.0;
+    smax[threadIdx.x] = cfl;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(a.cflmax, (unsigned long long)__double_as_longlong(smax[0]));
+    if (i >= a.ncell || *a.bad) return;
     const double* Ui = a.U + i * NV;
     double mir[NV];
     const long l = i - 1, r = i + 1;
@@ -184,7 +197,6 @@ extern "C" __global__ void __launch_bounds__(256) chem_euler_update(UpdateArgs a
         if (v >= 3) src = a.wdot[i * mech::NS + (v - 3)];
         a.Unew[i * NV + v] = Ui[v] - r_dt * (Fr - Fl) + a.dt * src;
     }
-    a.cfl[i] = (fabs(a.u[i]) + a.c[i]) * r_dt;
 }
 
 }  // namespace chem_euler

@@ -173,7 +173,8 @@ void release_device_state(chem_mechanism* m)
         for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
         if (d.capture_stream) (void)hipStreamDestroy(d.capture_stream);
         for (void* p : {(void*)d.par, (void*)d.stats, (void*)d.heads, (void*)d.block_buf,
-                        (void*)d.cells_i32, (void*)d.sample, (void*)d.bucket, (void*)d.perm, (void*)d.hist})
+                        (void*)d.cells_i32, (void*)d.sample, (void*)d.bucket, (void*)d.perm, (void*)d.hist,
+                        (void*)d.euler, (void*)d.euler_flags})
             if (p) (void)hipFree(p);
         if (d.ev0) (void)hipEventDestroy(d.ev0);
         if (d.ev1) (void)hipEventDestroy(d.ev1);
@@ -690,41 +691,44 @@ int run_euler1d(chem_mechanism* m, int64_t ncell, double dx, double dt, const do
     DeviceState* d;
     if (int rc = device_state(m, stream, &d)) return rc;
     const int ns = m->data.ns();
-    Scratch s(stream);
-    double *p, *Y, *u, *c, *wdot, *qdot, *cfl, *Tc;
-    int* bad;
-    if (int rc = s.alloc(&p, ncell, "euler p")) return rc;
-    if (int rc = s.alloc(&Y, (size_t)ncell * ns, "euler Y")) return rc;
-    if (int rc = s.alloc(&u, ncell, "euler u")) return rc;
-    if (int rc = s.alloc(&c, ncell, "euler c")) return rc;
-    if (int rc = s.alloc(&wdot, (size_t)ncell * ns, "euler wdot")) return rc;
-    if (int rc = s.alloc(&qdot, ncell, "euler qdot")) return rc;
-    if (int rc = s.alloc(&cfl, ncell, "euler cfl")) return rc;
-    if (int rc = s.alloc(&Tc, ncell, "euler T")) return rc;
-    if (int rc = s.alloc(&bad, 1, "euler flag")) return rc;
-    HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), stream), "clear flag");
+    // buffers kept per device between steps: p, Y, u, c, wdot, qdot, T (chemistry copy)
+    const size_t per = 2 * (size_t)ns + 5;
+    if (int rc = grow(&d->euler, &d->euler_cap, per * (size_t)ncell, "1D driver buffers")) return rc;
+    if (!d->euler_flags) HIPCHECK(hipMalloc((void**)&d->euler_flags, 2 * sizeof(unsigned long long)), "1D driver flags");
+    double* p = d->euler;
+    double* Y = p + ncell;
+    double* u = Y + (size_t)ncell * ns;
+    double* c = u + ncell;
+    double* wdot = c + ncell;
+    double* qdot = wdot + (size_t)ncell * ns;
+    double* Tc = qdot + ncell;
+    unsigned long long* flags = d->euler_flags;   // [0]: bad (int in the low word), [1]: max CFL bits
+    int* bad = reinterpret_cast<int*>(flags);
+    struct { unsigned long long* p; int n; } za{flags, 2};
+    if (int rc = launch_1d(d->f_zero, 2, 64, &za, sizeof za, stream, "chem_zero_u64")) return rc;
     struct {
         const double* U; long n; double *T, *p, *Y, *u, *c; int* bad;
     } pa{U, (long)ncell, T, p, Y, u, c, bad};
     if (int rc = launch_1d(d->f_euler_prim, ncell, 256, &pa, sizeof pa, stream, "chem_euler_prim")) return rc;
-    int hbad = 0;
-    HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag copy");
-    HIPCHECK(hipStreamSynchronize(stream), "flag sync");
-    if (hbad) return set_error(CHEM_E_INVAL, "a cell's conserved state gives no temperature (rho <= 0 or no root)");
     // the chemistry advances its own copy of T; Y is a scratch copy already
     HIPCHECK(hipMemcpyAsync(Tc, T, sizeof(double) * ncell, hipMemcpyDeviceToDevice, stream), "copy T");
     const int rc = run_source(m, ncell, Tc, p, Y, dt, rtol, atol, o, stats, nullptr, wdot, qdot, stream);
     if (rc && rc != CHEM_E_CELL_FAILED) return rc;
+    // the update writes nothing if a cell had no valid state
     struct {
-        const double *U, *p, *u, *c, *wdot, *qdot; long n; double dt, dx; double *Unew, *cfl;
-    } ua{U, p, u, c, wdot, qdot, (long)ncell, dt, dx, U_out, cfl};
+        const double *U, *p, *u, *c, *wdot, *qdot; long n; double dt, dx; double* Unew;
+        unsigned long long* cflmax; const int* bad;
+    } ua{U, p, u, c, wdot, qdot, (long)ncell, dt, dx, U_out, flags + 1, bad};
     if (int rc2 = launch_1d(d->f_euler_update, ncell, 256, &ua, sizeof ua, stream, "chem_euler_update")) return rc2;
+    // one small readback: the bad flag and the largest CFL number
+    unsigned long long h[2] = {0ull, 0ull};
+    HIPCHECK(hipMemcpyAsync(h, flags, sizeof h, hipMemcpyDeviceToHost, stream), "flag copy");
+    HIPCHECK(hipStreamSynchronize(stream), "flag sync");
+    if ((int)(h[0] & 0xffffffffull))
+        return set_error(CHEM_E_INVAL, "a cell's conserved state gives no temperature (rho <= 0 or no root)");
     if (max_cfl) {
-        std::vector<double> h(ncell);
-        HIPCHECK(hipMemcpyAsync(h.data(), cfl, sizeof(double) * ncell, hipMemcpyDeviceToHost, stream), "cfl copy");
-        HIPCHECK(hipStreamSynchronize(stream), "cfl sync");
-        double mx = 0.0;
-        for (double x : h) mx = std::max(mx, x);
+        double mx;
+        std::memcpy(&mx, &h[1], sizeof mx);
         *max_cfl = mx;
     }
     return rc;

@@ -198,6 +198,9 @@ struct DeviceState {
     bool done_recorded = false;
     size_t lds_per_block = 65536;
     unsigned char* noalloc = nullptr;    // this device's allocation-free scratch (see noalloc.hip)
+    double* euler = nullptr;             // 1D driver buffers, [cap][2 ns + 7] doubles
+    size_t euler_cap = 0;                // cells
+    unsigned long long* euler_flags = nullptr;   // 1D driver: bad flag, max CFL (bits)
     int n = 0;                           // state size ns + 1
     // LDS for the RODAS4 stage vectors u_1..u_5 of every lane of a workgroup
     unsigned stage_lds(int block) const { return (unsigned)(block * 5 * n * sizeof(double)); }

@@ -35,6 +35,8 @@ template <class T> static inline T __shfl(T v, int) { return v; }
 template <class T, class U> static inline T atomicAdd(T* p, U v) { T o = *p; *p = (T)(o + (T)v); return o; }
 template <class T, class U> static inline T atomicMax(T* p, U v) { T o = *p; if ((T)v > o) *p = (T)v; return o; }
 static inline void __syncthreads() {}
+static inline long long __double_as_longlong(double x) { long long b; __builtin_memcpy(&b, &x, sizeof b); return b; }
+static inline double __longlong_as_double(long long b) { double x; __builtin_memcpy(&x, &b, sizeof x); return x; }
 template <class T> static inline T min(T a, T b) { return b < a ? b : a; }
 template <class T> static inline T max(T a, T b) { return a < b ? b : a; }
 static inline long min(long a, int b) { return b < a ? b : a; }

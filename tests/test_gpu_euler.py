@@ -10,6 +10,8 @@ recovered T, both converged to round-off); rho Y_k to 1e-8 rho and rho E_s to
 1e-8 of the cell's chemical-energy scale (sum_k |h_k(298)| rho), since they
 take the chemistry's Delta Y, which agrees to the integration parity bar of
 1e-8."""
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -73,6 +75,9 @@ def test_step_matches_oracle(m9, dev):
         Uo, To, w, q = E.step(om, U, dx, dt, T_guess=T)
         Ug, Tg = Ug.cpu().numpy(), Tg.cpu().numpy()
         assert st["failed"] == 0 and 0.0 < cfl < 1.0
+        # the device-side maximum of (|u| + c) dt / dx
+        _, _, _, uo, co = E.primitives(om, U, T_guess=T)
+        assert abs(cfl - np.max((np.abs(uo) + co) * dt / dx)) <= 1e-12 * cfl
         assert np.allclose(Tg, To, rtol=1e-11, atol=0)
         for v in (0, 1):
             assert np.all(np.abs(Ug[:, v] - Uo[:, v]) <= 1e-10 * np.abs(Uo[:, 0:3]).max(axis=1)), (k, v)
@@ -164,6 +169,13 @@ def test_argument_and_state_errors(m9, dev):
     bad[3, 0] = -1.0                                                               # negative density
     with pytest.raises(chem.ChemError):
         chem.euler1d_step(gm, _g(bad, dev), 1e-4, 1e-9)
+    # the check is made on the device: U_out is left as it was
+    out = torch.full_like(Ug, 7.0)
+    cfl = C.c_double(-1.0)
+    rc = L.chem_euler1d_step(gm.h, 8, 1e-4, 1e-9, _g(bad, dev).data_ptr(), out.data_ptr(), Tg.data_ptr(), 1e-8,
+                             1e-12, None, None, C.byref(cfl), None)
+    torch.cuda.synchronize()
+    assert rc == -1 and bool(torch.all(out == 7.0))
 
 
 def test_step_in_the_wave_cooperative_form(dev, oracle_lib):
