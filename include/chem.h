@@ -76,9 +76,12 @@ enum chem_form {
     CHEM_FORM_PERSISTENT = 2    /* persistent work-stealing launch in a HIP graph */
 };
 
-/* Order in which the persistent form starts cells. */
+/* Order in which the persistent form starts cells (results are bitwise the
+   same in every order; only the time differs). */
 enum chem_order {
-    CHEM_ORDER_COST = 1,        /* default: most expensive first (caller's cost, else predicted) */
+    CHEM_ORDER_AUTO = 0,        /* default: whichever of the two below measured faster on a
+                                   sample of a field of this size (the launch-shape tuner) */
+    CHEM_ORDER_COST = 1,        /* most expensive first (caller's cost, else predicted) */
     CHEM_ORDER_NATURAL = 2      /* index order */
 };
 
@@ -91,7 +94,7 @@ typedef struct {
     int block;                  /* persistent: lanes per workgroup (64..256); 0 = tuned */
     int waves_per_simd;         /* persistent: resident waves per SIMD (1..2); 0 = tuned */
     int refill;                 /* persistent: idle lanes that trigger a refill; 0 = tuned */
-    int order;                  /* persistent: enum chem_order; 0 = CHEM_ORDER_COST */
+    int order;                  /* persistent: enum chem_order; 0 = CHEM_ORDER_AUTO */
     const int32_t *const *cost; /* nullable host array [nfield] of nullable device int32 [ncell]
                                    per-cell cost hints (e.g. nacc + nrej of the previous call);
                                    fields without one get a cost predicted from their state:

@@ -106,7 +106,7 @@ Options resolve_options(const chem_options* o)
         r.block = o->block;
         r.waves_per_simd = o->waves_per_simd;
         r.refill = o->refill;
-        if (o->order) r.order = o->order;
+        r.order = o->order;
         r.cost = o->cost;
     }
     return r;

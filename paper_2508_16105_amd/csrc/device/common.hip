@@ -165,13 +165,15 @@ struct AdjointArgs {
     const double* gY;
     double* gT0;
     double* gY0;
-    double* gpar;          // [ncell][3 NR]: per-cell parameter gradients (ln A, b, Ea)
+    double* gpar;          // [nslot][3 NR]: parameter gradients (ln A, b, Ea) summed over the
+                           // cells of each lane (lane form) or lane group (wave-cooperative form)
+    long nslot;            // lanes (groups) of the launch: slot s takes cells s, s + nslot, ...
     double* Tend;
     double* Yend;
     const long* off_h;     // first step size of each cell in hs
     const long* off_ck;    // first checkpoint of each cell (in states of N doubles)
     const int* nacc_fwd;   // accepted steps of the sizing pass
-    const int* order;      // cells by descending accepted steps (lane g takes cell order[g])
+    const int* order;      // cells by descending accepted steps (slot g takes cell order[g])
     const double* h0;      // nullable: per-cell first step, else dt
     double* hs;
     double* ck;
@@ -182,8 +184,10 @@ struct AdjointArgs {
     int K;                 // accepted steps per checkpoint
 };
 
-// Parameter gradients summed over cells in a fixed order: one workgroup per
-// parameter; thread t adds cells t, t + 256, ... in turn, then a fixed tree.
+// Parameter gradients summed in a fixed order: one workgroup per parameter;
+// thread t adds rows t, t + 256, ... in turn, then a fixed tree.  The rows are
+// the partial sums of the adjoint kernel's lanes (groups), each over its cells
+// in its own fixed order, so the result is bitwise reproducible.
 extern "C" __global__ void __launch_bounds__(256) chem_reduce_params(const double* __restrict__ gpar, long ncell,
                                                                     int nparam, double* __restrict__ gA,
                                                                     double* __restrict__ gb, double* __restrict__ gE)

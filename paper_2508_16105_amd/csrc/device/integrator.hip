@@ -681,66 +681,70 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
 
 
 
+// Lane s (of a.nslot) takes the cells in positions s, s + nslot, ... of the
+// cost order (descending accepted steps), so the lanes of a wave always work
+// on cells of similar cost, and keeps the parameter gradients of all its cells
+// in registers: one row of partial sums per lane instead of one per cell.
 extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
 {
     using namespace chem;
-    const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.ncell) return;
-    // cells of similar cost share a wave, so no lane waits long for the slowest
-    const long cell = a.order[slot];
+    const long lane = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= a.nslot) return;
     extern __shared__ double lds[];
     double* ul = lds + threadIdx.x;
     const int ls = blockDim.x;
-    Cell c;
-    cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
-    double* hs = a.hs + a.off_h[cell];
-    double* ck = a.ck + a.off_ck[cell] * N;
-    const int cap = a.nacc_fwd[cell];
-    int stored = -1;
-    while (!c.done) {
-        if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
-            for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
-            stored = c.nacc;
-        }
-        const double hacc = cell_attempt(c, a.par, a.step, ul, ls);
-        if (hacc > 0.0) {
-            if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
-            hs[c.nacc - 1] = hacc;
-        }
-    }
-    cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
-    if (c.status == CELL_BADINPUT) {
-        a.Tend[cell] = a.T0[cell];
-        for (int k = 0; k < NS; ++k) a.Yend[cell * NS + k] = a.Y0[cell * NS + k];
-    }
-    double* g = a.gpar + cell * 3 * mech::NR;
     double gA[mech::NR], gb[mech::NR], gE[mech::NR];
     for (int j = 0; j < mech::NR; ++j) { gA[j] = 0.0; gb[j] = 0.0; gE[j] = 0.0; }
-    double lam[N];
-    lam[0] = a.gT[cell];
-    for (int k = 0; k < NS; ++k) lam[1 + k] = a.gY[cell * NS + k];
-    if (c.status != CELL_OK) {
-        a.gT0[cell] = __builtin_nan("");
-        for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = __builtin_nan("");
-        for (int j = 0; j < 3 * mech::NR; ++j) g[j] = 0.0;
-        return;
-    }
-    const int na = c.nacc;
-    const double p = c.p, ip = c.ip;
-    for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
-        const int first = seg * a.K;
-        const int last = min(na, first + a.K) - 1;
-        double ys[16][N];                     // the segment's states (K <= 16)
-        for (int k = 0; k < N; ++k) ys[0][k] = ck[seg * N + k];
-        for (int i = first; i < last; ++i) {
-            double yn[N], en;
-            ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
-            for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+    for (long slot = lane; slot < a.ncell; slot += a.nslot) {
+        const long cell = a.order[slot];
+        Cell c;
+        cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
+        double* hs = a.hs + a.off_h[cell];
+        double* ck = a.ck + a.off_ck[cell] * N;
+        const int cap = a.nacc_fwd[cell];
+        int stored = -1;
+        while (!c.done) {
+            if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
+                for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
+                stored = c.nacc;
+            }
+            const double hacc = cell_attempt(c, a.par, a.step, ul, ls);
+            if (hacc > 0.0) {
+                if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
+                hs[c.nacc - 1] = hacc;
+            }
         }
-        for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE);
+        cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
+        if (c.status == CELL_BADINPUT) {
+            a.Tend[cell] = a.T0[cell];
+            for (int k = 0; k < NS; ++k) a.Yend[cell * NS + k] = a.Y0[cell * NS + k];
+        }
+        if (c.status != CELL_OK) {
+            a.gT0[cell] = __builtin_nan("");
+            for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = __builtin_nan("");
+            continue;                   // adds nothing to the parameter gradients
+        }
+        double lam[N];
+        lam[0] = a.gT[cell];
+        for (int k = 0; k < NS; ++k) lam[1 + k] = a.gY[cell * NS + k];
+        const int na = c.nacc;
+        const double p = c.p, ip = c.ip;
+        for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
+            const int first = seg * a.K;
+            const int last = min(na, first + a.K) - 1;
+            double ys[16][N];                     // the segment's states (K <= 16)
+            for (int k = 0; k < N; ++k) ys[0][k] = ck[seg * N + k];
+            for (int i = first; i < last; ++i) {
+                double yn[N], en;
+                ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
+                for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+            }
+            for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE);
+        }
+        a.gT0[cell] = lam[0];
+        for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = lam[1 + k];
     }
-    a.gT0[cell] = lam[0];
-    for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = lam[1 + k];
+    double* g = a.gpar + lane * 3 * mech::NR;
     for (int j = 0; j < mech::NR; ++j) {
         g[j] = gA[j];
         g[mech::NR + j] = gb[j];

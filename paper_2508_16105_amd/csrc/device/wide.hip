@@ -1081,79 +1081,84 @@ extern "C" __global__ void __launch_bounds__(64, 2) chem_persistent(const Persis
 // every K accepted steps; then the reverse sweep recomputes each segment from
 // its checkpoint and applies the step adjoints backwards.  Per-cell parameter
 // gradients go to gpar for the fixed-order reduction.
+// Group s (of a.nslot) takes the cells in positions s, s + nslot, ... of the
+// cost order and keeps the parameter gradients of all its cells in its lanes'
+// registers (lane i holds those of its reaction slots): one row of partial
+// sums per group instead of one per cell.
 extern "C" __global__ void __launch_bounds__(64) chem_adjoint(AdjointArgs a)
 {
     using namespace chemw;
     extern __shared__ double lds[];
     const int grp = (int)threadIdx.x / G;
-    const long slot = (long)blockIdx.x * CPW + grp;
-    if (slot >= a.ncell) return;
-    const long cell = a.order[slot];
+    const long gslot = (long)blockIdx.x * CPW + grp;
+    if (gslot >= a.nslot) return;
     double* L = lds + grp * mech::ADJ_LDS_CELL;
     double* PV = L + 2 * mech::LDS_CELL;
     const int i = gl();
-    Cell c;
-    cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, a.h0 ? a.h0[cell] : a.step.dt);
-    double* hs = a.hs + a.off_h[cell];
-    double* ck = a.ck + a.off_ck[cell] * N;
-    const int cap = a.nacc_fwd[cell];
-    int stored = -1;
-    while (!c.done) {
-        if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
-            if (i < N) ck[(c.nacc / a.K) * N + i] = c.y;
-            stored = c.nacc;
-        }
-        const double hacc = cell_attempt(c, a.par, a.step, L, PV);
-        if (hacc > 0.0) {
-            if (c.nacc > cap) {
-                c.status = chem::CELL_NONFINITE;
-                c.done = true;
-                break;
-            }
-            if (i == 0) hs[c.nacc - 1] = hacc;
-        }
-    }
-    cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
-    if (c.status == chem::CELL_BADINPUT) {
-        if (i == 0) a.Tend[cell] = a.T0[cell];
-        else if (i <= NS) a.Yend[cell * NS + i - 1] = a.Y0[cell * NS + i - 1];
-    }
-    double* gp = a.gpar + cell * 3 * NR;
-    if (c.status != chem::CELL_OK) {
-        if (i == 0) a.gT0[cell] = __builtin_nan("");
-        else if (i <= NS) a.gY0[cell * NS + i - 1] = __builtin_nan("");
-        for (int j = i; j < 3 * NR; j += G) gp[j] = 0.0;
-        return;
-    }
-    double lam = i == 0 ? a.gT[cell] : (i <= NS ? a.gY[cell * NS + i - 1] : 0.0);
     double g[ROUNDS][3];
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) g[r][0] = g[r][1] = g[r][2] = 0.0;
-    const int na = c.nacc;
-    const double p = c.p, ip = c.ip;
-    for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
-        const int first = seg * a.K;
-        const int last = min(na, first + a.K) - 1;
-        double ys[16];                        // the segment's states (K <= 16), component i
-        ys[0] = i < N ? ck[seg * N + i] : 0.0;
-        for (int s = first; s < last; ++s) {
-            double yn, en;
-            double yc = ys[0];
-#pragma unroll
-            for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
-            ros_step(a.par, p, ip, yc, hs[s], a.step.rtol, a.step.atol, L, PV, yn, en);
-#pragma unroll
-            for (int q = 1; q < 16; ++q) ys[q] = (q == s - first + 1) ? yn : ys[q];
+    for (long slot = gslot; slot < a.ncell; slot += a.nslot) {
+        const long cell = a.order[slot];
+        Cell c;
+        cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, a.h0 ? a.h0[cell] : a.step.dt);
+        double* hs = a.hs + a.off_h[cell];
+        double* ck = a.ck + a.off_ck[cell] * N;
+        const int cap = a.nacc_fwd[cell];
+        int stored = -1;
+        while (!c.done) {
+            if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
+                if (i < N) ck[(c.nacc / a.K) * N + i] = c.y;
+                stored = c.nacc;
+            }
+            const double hacc = cell_attempt(c, a.par, a.step, L, PV);
+            if (hacc > 0.0) {
+                if (c.nacc > cap) {
+                    c.status = chem::CELL_NONFINITE;
+                    c.done = true;
+                    break;
+                }
+                if (i == 0) hs[c.nacc - 1] = hacc;
+            }
         }
-        for (int s = last; s >= first; --s) {
-            double yc = ys[0];
-#pragma unroll
-            for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
-            step_adjoint(a.par, p, ip, yc, hs[s], lam, g, L, PV);
+        cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
+        if (c.status == chem::CELL_BADINPUT) {
+            if (i == 0) a.Tend[cell] = a.T0[cell];
+            else if (i <= NS) a.Yend[cell * NS + i - 1] = a.Y0[cell * NS + i - 1];
         }
+        if (c.status != chem::CELL_OK) {
+            if (i == 0) a.gT0[cell] = __builtin_nan("");
+            else if (i <= NS) a.gY0[cell * NS + i - 1] = __builtin_nan("");
+            continue;                   // adds nothing to the parameter gradients
+        }
+        double lam = i == 0 ? a.gT[cell] : (i <= NS ? a.gY[cell * NS + i - 1] : 0.0);
+        const int na = c.nacc;
+        const double p = c.p, ip = c.ip;
+        for (int seg = (na - 1) / a.K; seg >= 0 && na > 0; --seg) {
+            const int first = seg * a.K;
+            const int last = min(na, first + a.K) - 1;
+            double ys[16];                        // the segment's states (K <= 16), component i
+            ys[0] = i < N ? ck[seg * N + i] : 0.0;
+            for (int s = first; s < last; ++s) {
+                double yn, en;
+                double yc = ys[0];
+#pragma unroll
+                for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
+                ros_step(a.par, p, ip, yc, hs[s], a.step.rtol, a.step.atol, L, PV, yn, en);
+#pragma unroll
+                for (int q = 1; q < 16; ++q) ys[q] = (q == s - first + 1) ? yn : ys[q];
+            }
+            for (int s = last; s >= first; --s) {
+                double yc = ys[0];
+#pragma unroll
+                for (int q = 1; q < 16; ++q) yc = (q == s - first) ? ys[q] : yc;
+                step_adjoint(a.par, p, ip, yc, hs[s], lam, g, L, PV);
+            }
+        }
+        if (i == 0) a.gT0[cell] = lam;
+        else if (i <= NS) a.gY0[cell * NS + i - 1] = lam;
     }
-    if (i == 0) a.gT0[cell] = lam;
-    else if (i <= NS) a.gY0[cell * NS + i - 1] = lam;
+    double* gp = a.gpar + gslot * 3 * NR;
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int j = r * G + i;

@@ -11,6 +11,10 @@
 #include <sstream>
 #include <tuple>
 
+#include <unistd.h>
+
+#include "module.hpp"
+
 namespace chemmi {
 
 namespace {
@@ -77,6 +81,7 @@ int device_state(chem_mechanism* m, hipStream_t stream, DeviceState** out)
             return set_error(CHEM_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName +
                                                      "; this library is built for gfx950");
         d.num_cu = prop.multiProcessorCount;
+        d.arch = prop.gcnArchName;
         d.lds_per_block = prop.sharedMemPerBlock;
         d.n = m->data.ns() + 1;
         HIPCHECK(hipModuleLoadData(&d.module, m->code.data()), "hipModuleLoadData");
@@ -171,6 +176,7 @@ void release_device_state(chem_mechanism* m)
         DeviceState& d = kv.second;
         (void)hipSetDevice(d.device);
         for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
+        for (auto& g : d.wide_graphs) (void)hipGraphExecDestroy(g.second);
         if (d.capture_stream) (void)hipStreamDestroy(d.capture_stream);
         for (void* p : {(void*)d.par, (void*)d.stats, (void*)d.heads, (void*)d.block_buf,
                         (void*)d.cells_i32, (void*)d.sample, (void*)d.bucket, (void*)d.perm, (void*)d.hist,
@@ -265,6 +271,8 @@ int write_block(DeviceState& d, const std::vector<FieldDesc>& fields, const Pers
         // graphs hold the old address
         for (auto& g : d.graphs) (void)hipGraphExecDestroy(g.second);
         d.graphs.clear();
+        for (auto& g : d.wide_graphs) (void)hipGraphExecDestroy(g.second);
+        d.wide_graphs.clear();
         const size_t cap = std::max<size_t>(bytes, sizeof(PersistHeader) + 64 * sizeof(FieldDesc));
         HIPCHECK(hipMalloc((void**)&d.block_buf, cap), "hipMalloc field table");
         d.block_cap = cap;
@@ -282,7 +290,7 @@ int grid_of(const DeviceState& d, const LaunchConfig& c)
 {
     // resident workgroups: CUs x 4 SIMDs x waves per SIMD, 64-lane waves
     const int waves = d.num_cu * 4 * c.waves_per_simd;
-    return std::max(1, waves * 64 / c.block);
+    return std::max(1, waves * 64 / c.block / std::max(1, c.div));
 }
 
 // Launch [reset -> cost keys -> bucket offsets -> permutation -> persistent
@@ -370,15 +378,100 @@ PersistHeader header_for(const DeviceState& d, int64_t total, int nfield, const 
     return h;
 }
 
-// Time candidate launch shapes on a strided sample of the input (copied, so
-// the caller's data is untouched) and keep the fastest per size bucket.
+// The on-disk record of a tuning result: one line "block refill order" in
+// $CHEM_TUNE_CACHE (else the kernel cache folder) under a name that hashes the
+// mechanism's code object (which names its source, options and compiler), the
+// device's architecture and compute-unit count, the size bucket and any shape
+// the caller fixed.
+std::string tune_file(const chem_mechanism* m, const DeviceState& d, int64_t bucket, const Options& o)
+{
+    std::ostringstream k;
+    const std::string& cf = m->cache_file;
+    k << cf.substr(cf.find_last_of('/') + 1) << ' ' << d.arch << ' ' << d.num_cu << ' ' << bucket << ' ' << o.block
+      << ' ' << o.refill << ' ' << o.order;
+    char name[48];
+    std::snprintf(name, sizeof name, "/tune-%016llx.txt", (unsigned long long)fnv1a(k.str()));
+    const char* env = std::getenv("CHEM_TUNE_CACHE");
+    return (env && *env ? std::string(env) : cache_dir()) + name;
+}
+
+bool read_tuned(const std::string& path, LaunchConfig* c, int* order)
+{
+    std::ifstream in(path);
+    int b = 0, r = 0, od = 0;
+    if (!(in >> b >> r >> od)) return false;
+    if (b < 64 || b > 256 || b % 64 || r < 1 || r > 64 || (od != CHEM_ORDER_COST && od != CHEM_ORDER_NATURAL))
+        return false;
+    *c = LaunchConfig{b, 1, r};
+    *order = od;
+    return true;
+}
+
+void write_tuned(const std::string& path, const LaunchConfig& c, int order, float ms)
+{
+    const std::string tmp = path + ".tmp" + std::to_string(getpid());
+    {
+        std::ofstream out(tmp);
+        if (!out) return;
+        out << c.block << ' ' << c.refill << ' ' << order << '\n' << "# sample time " << ms << " ms\n";
+        if (!out) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+// The wave-cooperative persistent launch [reset -> persistent kernel] as a
+// graph built once per grid size (everything call-specific is in the field
+// table, whose device address is fixed).
+int launch_graph_wide(DeviceState& d, const chem_mechanism* m, int64_t waves, hipStream_t stream)
+{
+    auto it = d.wide_graphs.find(waves);
+    if (it == d.wide_graphs.end()) {
+        if (!d.capture_stream) HIPCHECK(hipStreamCreateWithFlags(&d.capture_stream, hipStreamNonBlocking), "stream");
+        hipGraph_t g;
+        HIPCHECK(hipStreamBeginCapture(d.capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        struct { const char* blk; unsigned long long* h; } ra{d.block_buf, d.heads};
+        struct { const char* blk; unsigned long long* heads; const double* par; } pa{d.block_buf, d.heads, d.par};
+        size_t rs = sizeof ra, ps = sizeof pa;
+        void* rcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &ra, HIP_LAUNCH_PARAM_BUFFER_SIZE, &rs, HIP_LAUNCH_PARAM_END};
+        void* pcfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &pa, HIP_LAUNCH_PARAM_BUFFER_SIZE, &ps, HIP_LAUNCH_PARAM_END};
+        hipError_t e = hipModuleLaunchKernel(d.f_reset, 1, 1, 1, 256, 1, 1, 0, d.capture_stream, nullptr, rcfg);
+        if (e == hipSuccess)
+            e = hipModuleLaunchKernel(d.f_persistent, (unsigned)waves, 1, 1, 64, 1, 1, m->layout.lds_bytes(),
+                                      d.capture_stream, nullptr, pcfg);
+        hipError_t e2 = hipStreamEndCapture(d.capture_stream, &g);
+        if (e != hipSuccess) return hip_error(e, "capture wave-cooperative launch");
+        if (e2 != hipSuccess) return hip_error(e2, "end capture");
+        hipGraphExec_t ex;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return hip_error(e3, "graph instantiate");
+        it = d.wide_graphs.emplace(waves, ex).first;
+    }
+    HIPCHECK(hipGraphLaunch(it->second, stream), "graph launch");
+    return 0;
+}
+
+// Time candidate launch shapes and cell orders on a strided sample of the input
+// (copied, so the caller's data is untouched) and keep the fastest per size
+// bucket, in memory and on disk.  Every candidate gives bitwise the same
+// results; only the time differs.  The order is a candidate only when the
+// caller left it to the tuner (CHEM_ORDER_AUTO).
 int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fields, int64_t total,
-             const StepArgs& s, const Options& o, hipStream_t stream, LaunchConfig* best)
+             const StepArgs& s, const Options& o, hipStream_t stream, LaunchConfig* best, int* best_order)
 {
     const int64_t bucket = size_bucket(total);
     auto hit = d.tuned.find(bucket);
     if (hit != d.tuned.end()) {
-        *best = hit->second;
+        *best = hit->second.first;
+        *best_order = hit->second.second;
+        return 0;
+    }
+    const std::string record = tune_file(m, d, bucket, o);
+    if (read_tuned(record, best, best_order)) {
+        if (std::getenv("CHEM_LOG"))
+            std::fprintf(stderr, "[chem] autotune cache hit %s: block=%d refill=%d order=%d\n", record.c_str(),
+                         best->block, best->refill, *best_order);
+        d.tuned[bucket] = {*best, *best_order};
         return 0;
     }
     const int ns = m->data.ns();
@@ -391,44 +484,59 @@ int autotune(chem_mechanism* m, DeviceState& d, const std::vector<FieldDesc>& fi
     double* sp = sT + count;
     double* sY = sp + count;
     double* wT = d.sample + per;                      // working copy
-    PersistHeader h = header_for(d, total, (int)fields.size(), LaunchConfig{}, s, o.order);
+    PersistHeader h = header_for(d, total, (int)fields.size(), LaunchConfig{}, s, CHEM_ORDER_NATURAL);
     if (int rc = write_block(d, fields, h, stream)) return rc;
     struct { const char* blk; long stride; long count; double* T; double* p; double* Y; } ga{
         d.block_buf, (long)stride, (long)count, sT, sp, sY};
     if (int rc = launch_1d(d.f_gather, count, 256, &ga, sizeof ga, stream, "chem_gather_sample")) return rc;
 
+    // the sample runs on 1/stride of the workgroups, so its lanes take as many
+    // cells each as the whole field's will (the cell order matters only then)
+    // (a sample run then takes about as long as the whole field, so the shapes
+    // are a short list: the block sizes at one refill threshold and the
+    // thresholds at one block size; the other order is tried with the best shape)
     std::vector<LaunchConfig> cands;
-    for (int block : {64, 128, 256})
-        for (int refill : {4, 16, 32})
-            if (d.stage_lds(block) <= d.lds_per_block) cands.push_back(LaunchConfig{block, 1, refill});
+    for (auto br : {std::make_pair(64, 16), std::make_pair(128, 16), std::make_pair(256, 16), std::make_pair(64, 4),
+                    std::make_pair(64, 32)})
+        if (d.stage_lds(br.first) <= d.lds_per_block) cands.push_back(LaunchConfig{br.first, 1, br.second, (int)stride});
     if (o.block) for (auto& c : cands) c.block = o.block;
     if (o.refill) for (auto& c : cands) c.refill = o.refill;
+    const int first_order = o.order == CHEM_ORDER_AUTO ? CHEM_ORDER_COST : o.order;
     float best_ms = 1e30f;
     *best = cands[0];
+    *best_order = first_order;
     // count <= total, so the per-cell workspace (3 * total) already fits the sample
     std::vector<FieldDesc> sf(1);
     sf[0] = FieldDesc{wT, sp, wT + count, d.cells_i32, d.cells_i32 + count, d.cells_i32 + 2 * count,
                       nullptr, (long)count, 0};
-    for (const auto& c : cands) {
-        HIPCHECK(hipMemcpyAsync(wT, sT, sizeof(double) * count, hipMemcpyDeviceToDevice, stream), "sample copy");
-        HIPCHECK(hipMemcpyAsync(wT + count, sY, sizeof(double) * count * ns, hipMemcpyDeviceToDevice, stream),
-                 "sample copy");
-        PersistHeader hs = header_for(d, count, 1, c, s, o.order);
-        if (int rc = write_block(d, sf, hs, stream)) return rc;
-        HIPCHECK(hipEventRecord(d.ev0, stream), "event");
-        if (int rc = launch_graph(d, c, stream)) return rc;
-        HIPCHECK(hipEventRecord(d.ev1, stream), "event");
-        HIPCHECK(hipEventSynchronize(d.ev1), "event sync");
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, d.ev0, d.ev1), "elapsed");
-        if (std::getenv("CHEM_LOG"))
-            std::fprintf(stderr, "[chem] autotune block=%d refill=%d: %.3f ms\n", c.block, c.refill, ms);
-        if (ms < best_ms) {
-            best_ms = ms;
-            *best = c;
+    for (int pass = 0; pass < (o.order == CHEM_ORDER_AUTO ? 2 : 1); ++pass) {
+        const int od = pass == 0 ? first_order : CHEM_ORDER_NATURAL;
+        const std::vector<LaunchConfig> these = pass == 0 ? cands : std::vector<LaunchConfig>{*best};
+        for (const auto& c : these) {
+            HIPCHECK(hipMemcpyAsync(wT, sT, sizeof(double) * count, hipMemcpyDeviceToDevice, stream), "sample copy");
+            HIPCHECK(hipMemcpyAsync(wT + count, sY, sizeof(double) * count * ns, hipMemcpyDeviceToDevice, stream),
+                     "sample copy");
+            PersistHeader hs = header_for(d, count, 1, c, s, od);
+            if (int rc = write_block(d, sf, hs, stream)) return rc;
+            HIPCHECK(hipEventRecord(d.ev0, stream), "event");
+            if (int rc = launch_graph(d, c, stream)) return rc;
+            HIPCHECK(hipEventRecord(d.ev1, stream), "event");
+            HIPCHECK(hipEventSynchronize(d.ev1), "event sync");
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, d.ev0, d.ev1), "elapsed");
+            if (std::getenv("CHEM_LOG"))
+                std::fprintf(stderr, "[chem] autotune block=%d refill=%d order=%d: %.3f ms\n", c.block, c.refill,
+                             od, ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                *best = c;
+                *best_order = od;
+            }
         }
     }
-    d.tuned[bucket] = *best;
+    best->div = 1;
+    d.tuned[bucket] = {*best, *best_order};
+    write_tuned(record, *best, *best_order, best_ms);
     return 0;
 }
 
@@ -451,15 +559,10 @@ int run_persistent_wide(chem_mechanism* m, const FieldView* fv, int nfield, doub
     LaunchConfig c{64, 1, 1};
     if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, CHEM_ORDER_NATURAL), stream)) return rc;
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
-    struct { const char* blk; unsigned long long* h; } ra{d->block_buf, d->heads};
-    if (int rc = launch_1d(d->f_reset, 256, 256, &ra, sizeof ra, stream, "chem_reset_heads")) return rc;
-    struct { const char* blk; unsigned long long* heads; const double* par; } pa{d->block_buf, d->heads, d->par};
     // resident waves: as many as the LDS scratch allows, at most 8 per CU
     const unsigned per_cu = std::max<unsigned>(1u, std::min<unsigned>(8u, (unsigned)(160u * 1024u / std::max(1u, m->layout.lds_bytes()))));
     const int64_t waves = std::min<int64_t>((int64_t)d->num_cu * per_cu, (total + m->layout.cells_per_wave() - 1) / m->layout.cells_per_wave());
-    if (int rc = launch_1d(d->f_persistent, waves * 64, 64, &pa, sizeof pa, stream, "chem_persistent",
-                           m->layout.lds_bytes()))
-        return rc;
+    if (int rc = launch_graph_wide(*d, m, waves, stream)) return rc;
     if (!stats) return 0;
     HIPCHECK(hipEventRecord(d->ev1, stream), "event");
     HIPCHECK(hipEventSynchronize(d->ev1), "event sync");
@@ -495,15 +598,17 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
     if (int rc = fill_fields(*d, fv, nfield, fields, total)) return rc;
     const StepArgs s = step_args(dt, rtol, atol, o);
     LaunchConfig c;
-    if (o.block && o.refill) {
+    int order = o.order;
+    if (o.block && o.refill && o.order != CHEM_ORDER_AUTO) {
         c = LaunchConfig{o.block, std::max(1, o.waves_per_simd), o.refill};
-    } else if (int rc = autotune(m, *d, fields, total, s, o, stream, &c)) {
+    } else if (int rc = autotune(m, *d, fields, total, s, o, stream, &c, &order)) {
         return rc;
     }
+    if (o.order != CHEM_ORDER_AUTO) order = o.order;   // the caller's order, whatever a cached tuning chose
     if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
     if (d->stage_lds(c.block) > d->lds_per_block)
         return set_error(CHEM_E_INVAL, "block too large for the stage vectors in LDS");
-    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, o.order), stream)) return rc;
+    if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, order), stream)) return rc;
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     if (int rc = launch_graph(*d, c, stream)) return rc;
     if (!stats) return 0;
@@ -571,18 +676,22 @@ int run_noalloc(chem_mechanism* m, int64_t ncell, double* T, const double* p, do
     f.start = 0;
     const StepArgs s = step_args(dt, rtol, atol, o);
     LaunchConfig c;
+    int order = o.order == CHEM_ORDER_AUTO ? CHEM_ORDER_COST : o.order;
     if (m->wide) {
         c = LaunchConfig{64, 1, 1};
-    } else if (o.block && o.refill) {
-        c = LaunchConfig{o.block, std::max(1, o.waves_per_simd), o.refill};
     } else {
-        auto t = d->tuned.find(size_bucket(ncell));   // a shape the tuner chose earlier, else the default
-        if (t != d->tuned.end()) c = t->second;
+        // the shape and order the tuner chose earlier for this size, else the defaults
+        auto t = d->tuned.find(size_bucket(ncell));
+        if (t != d->tuned.end()) {
+            c = t->second.first;
+            if (o.order == CHEM_ORDER_AUTO) order = t->second.second;
+        }
+        if (o.block && o.refill) c = LaunchConfig{o.block, std::max(1, o.waves_per_simd), o.refill};
     }
     if (c.block < 64 || c.block > 256 || c.block % 64) return set_error(CHEM_E_INVAL, "block must be 64..256, a multiple of 64");
     if (!m->wide && d->stage_lds(c.block) > d->lds_per_block)
         return set_error(CHEM_E_INVAL, "block too large for the stage vectors in LDS");
-    PersistHeader h = header_for(*d, ncell, 1, c, s, m->wide ? CHEM_ORDER_NATURAL : o.order);
+    PersistHeader h = header_for(*d, ncell, 1, c, s, m->wide ? CHEM_ORDER_NATURAL : order);
     h.bucket = base + kNoallocBucketOff;
     h.perm = reinterpret_cast<int*>(base + kNoallocPermOff);
     h.hist = hist;
@@ -802,20 +911,31 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     if (int rc = s.alloc(&order_d, (size_t)ncell, "adjoint order")) return rc;
     HIPCHECK(hipMemcpyAsync(order_d, order.data(), sizeof(int32_t) * ncell, hipMemcpyHostToDevice, stream),
              "copy order");
+    // as many lanes (lane groups) as the device keeps resident; each takes the
+    // cells s, s + nslot, ... of the cost order and keeps one row of partial
+    // parameter sums, reduced in a fixed order afterwards
+    int64_t nslot;
+    unsigned ashmem;
+    if (m->wide) {
+        ashmem = m->layout.adj_lds_bytes();
+        const int64_t waves_per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / std::max(1u, ashmem)));
+        nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * waves_per_cu * m->layout.cells_per_wave());
+    } else {
+        ashmem = d->stage_lds(64);
+        nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * 4 * 64);
+    }
     long* off_d;
     double *hs, *ck, *gpar;
     if (int rc = s.alloc(&off_d, 2 * (size_t)ncell, "adjoint offsets")) return rc;
     if (int rc = s.alloc(&hs, (size_t)th, "adjoint step sizes")) return rc;
     if (int rc = s.alloc(&ck, (size_t)tc * n, "adjoint checkpoints")) return rc;
-    if (int rc = s.alloc(&gpar, (size_t)ncell * 3 * nr, "adjoint parameter gradients")) return rc;
+    if (int rc = s.alloc(&gpar, (size_t)nslot * 3 * nr, "adjoint parameter partial sums")) return rc;
     HIPCHECK(hipMemcpyAsync(off_d, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, stream),
              "copy offsets");
-    AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, T_end, Y_end, off_d,
+    AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, (long)nslot, T_end, Y_end, off_d,
                    off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
-    // one lane per cell, or one group of G lanes per cell (with room for dual numbers)
-    const int64_t alanes = m->wide ? ncell * m->layout.G : ncell;
-    const unsigned ashmem = m->wide ? m->layout.adj_lds_bytes() : d->stage_lds(64);
+    const int64_t alanes = m->wide ? nslot * m->layout.G : nslot;
     if (int rc = launch_1d(d->f_adjoint, alanes, 64, &aa, sizeof aa, stream, "chem_adjoint", ashmem)) return rc;
     HIPCHECK(hipEventRecord(d->ev1, stream), "event");
     struct {
@@ -823,7 +943,7 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         long n;
         int np;
         double *a, *b, *e;
-    } rp{gpar, (long)ncell, 3 * nr, g_lnA, g_b, g_Ea};
+    } rp{gpar, (long)nslot, 3 * nr, g_lnA, g_b, g_Ea};
     if (int rc = launch_1d(d->f_rparams, (int64_t)3 * nr * 256, 256, &rp, sizeof rp, stream,
                            "chem_reduce_params"))
         return rc;

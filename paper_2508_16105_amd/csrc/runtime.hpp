@@ -69,7 +69,8 @@ struct AdjointArgs {
     const double* gY;
     double* gT0;
     double* gY0;
-    double* gpar;
+    double* gpar;      // [nslot][3 nr] partial sums of the parameter gradients
+    long nslot;        // lanes (groups) of the adjoint launch
     double* Tend;
     double* Yend;
     const long* off_h;
@@ -137,7 +138,7 @@ struct Options {
     int block = 0;
     int waves_per_simd = 0;
     int refill = 0;
-    int order = CHEM_ORDER_COST;
+    int order = CHEM_ORDER_AUTO;
     const int32_t* const* cost = nullptr;
 };
 
@@ -158,9 +159,12 @@ struct LaunchConfig {
     int block = 64;            // lanes per workgroup
     int waves_per_simd = 1;
     int refill = 16;
+    int div = 1;               // launch 1/div of the resident workgroups (the tuner's
+                               // sample runs, so a 1/div sample sees the lanes per cell
+                               // of the whole field)
     bool operator<(const LaunchConfig& o) const
     {
-        return std::tie(block, waves_per_simd, refill) < std::tie(o.block, o.waves_per_simd, o.refill);
+        return std::tie(block, waves_per_simd, refill, div) < std::tie(o.block, o.waves_per_simd, o.refill, o.div);
     }
 };
 
@@ -190,7 +194,11 @@ struct DeviceState {
     unsigned* hist = nullptr;            // [2 * kCostBuckets]: histogram, cursors
     hipStream_t capture_stream = nullptr;
     std::map<LaunchConfig, hipGraphExec_t> graphs;
-    std::map<int64_t, LaunchConfig> tuned;  // by log2 bucket of the total cell count
+    std::map<int64_t, hipGraphExec_t> wide_graphs;   // wave-cooperative launch, by grid size
+    // by log2 bucket of the total cell count: the tuned launch shape and cell
+    // order (CHEM_ORDER_COST or CHEM_ORDER_NATURAL)
+    std::map<int64_t, std::pair<LaunchConfig, int>> tuned;
+    std::string arch;                    // gcnArchName
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // recorded after every API call's work: the next call's stream waits on
     // it, so the shared workspace is reused in order even across streams

@@ -121,16 +121,19 @@ int main(int argc, char** argv)
         }
         double* hs = (double*)calloc(th + 1, sizeof(double));
         double* ck = (double*)calloc(tc * N + 1, sizeof(double));
-        double* gpar = (double*)calloc(n * 3 * nr + 1, sizeof(double));
+        // fewer lanes than cells, so each lane takes several cells in turn and
+        // keeps one row of partial parameter sums, as on the GPU for large fields
+        const long nslot = (n + 2) / 3;
+        double* gpar = (double*)calloc(nslot * 3 * nr + 1, sizeof(double));
         double* gT0 = (double*)calloc(n + 1, sizeof(double));
         double* gY0 = (double*)calloc(n * ns + 1, sizeof(double));
         double* Te = (double*)calloc(n + 1, sizeof(double));
         double* Ye = (double*)calloc(n * ns + 1, sizeof(double));
-        g_aa = AdjointArgs{par, T, p, Y, n, gT, gY, gT0, gY0, gpar, Te, Ye, off, off + n, na_fwd, order,
+        g_aa = AdjointArgs{par, T, p, Y, n, gT, gY, gT0, gY0, gpar, nslot, Te, Ye, off, off + n, na_fwd, order,
                            nullptr, hs, ck, st, na, nj, step, K};
-        launch_lanes(n, [] { chem_adjoint(g_aa); });
+        launch_lanes(nslot, [] { chem_adjoint(g_aa); });
         double* gp = (double*)calloc(3 * nr, sizeof(double));
-        for (long c = 0; c < n; ++c)
+        for (long c = 0; c < nslot; ++c)
             for (int j = 0; j < 3 * nr; ++j) gp[j] += gpar[c * 3 * nr + j];
         wr(out, gT0, n);
         wr(out, gY0, n * ns);
