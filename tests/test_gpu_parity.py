@@ -350,3 +350,29 @@ def test_source_mode_failed_cells_are_nan(chem, mechs, dev):
     assert np.all(np.isnan(wg[3])) and np.isnan(qg[3])
     ok = [i for i in range(8) if i != 3]
     assert np.all(np.isfinite(wg[ok])) and np.all(np.isfinite(qg[ok]))
+
+
+@pytest.mark.parametrize("name,hr,nfail", [("m9", 0.01, 32), ("m32", 0.9, 8)])
+def test_step_size_floor_status_matches_oracle(chem, dev, oracle_lib, name, hr, nfail):
+    """CHEM_CELL_HMIN: with a step-size floor of hmin_rel dt many cells need a
+    step below it (m9 at 0.01: 113 of 256; m32, whose cells take one or two
+    steps, at 0.9: 11).  The status of every cell matches the oracle's, except
+    where the decision sits on the floor itself (the oracle's own status
+    changes when the floor moves by 1e-6 of itself); a failed cell keeps its
+    last accepted state, to the parity bar.  m32 runs in the wave-cooperative
+    form."""
+    gm = chem.Mechanism(mech_path(name))
+    om = oracle_lib.Mechanism(mech_path(name))
+    T, p, Y = uniform_cells(mech_text(name), 256, 81)
+    Tg, Yg, stats, st, na, nr = chem.integrate(gm, _g(T, dev), _g(p, dev), _g(Y, dev), 1e-8, RTOL, ATOL,
+                                               hmin_rel=hr, return_counts=True, allow_failed=True)
+    st = st.cpu().numpy()
+    To, Yo, nao, nro, sto = om.integrate(T, p, Y, 1e-8, RTOL, ATOL, hmin_rel=hr)
+    edge = np.zeros(len(T), dtype=bool)
+    for f in (1.0 - 1e-6, 1.0 + 1e-6):
+        edge |= om.integrate(T, p, Y, 1e-8, RTOL, ATOL, hmin_rel=hr * f)[4] != sto
+    assert (sto == 2).sum() >= nfail and (sto == 0).sum() >= 32
+    assert np.all((st == sto) | edge), np.where((st != sto) & ~edge)[0]
+    assert stats["failed"] == int((st != 0).sum())
+    same = st == sto
+    _assert_state_parity(Tg.cpu().numpy()[same], Yg.cpu().numpy()[same], To[same], Yo[same], f"{name} hmin")
