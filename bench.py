@@ -260,7 +260,8 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
            "forward_ms": fwd, "adjoint_over_forward": {k: adj_ms / v for k, v in fwd.items()},
            "cell_steps_per_s": n / (adj_ms * 1e-3),
            "accepted": st["accepted"], "max_substeps_cell": st["max_substeps"],
-           "checkpoint_every": 4}
+           "checkpoint_every": "auto (densest interval whose arena fits a quarter of free memory)",
+           "lane_groups": "cells >= 0.6 x the largest step count on 8-lane groups (one cell per lane form)"}
     if cpu_cells:
         import oracle
         om = oracle.Mechanism(mech_path(w["mech"]))

@@ -90,7 +90,9 @@ typedef struct {
     int max_substeps;           /* attempts per cell; <= 0 means 100000 */
     double hmin_rel;            /* fail below hmin_rel * dt; <= 0 means 1e-20 */
     const double *h0;           /* nullable device [ncell]: first trial step; else dt */
-    int checkpoint_every;       /* adjoint: accepted steps per checkpoint; <= 0 means 4 */
+    int checkpoint_every;       /* adjoint: accepted steps per checkpoint (1..16); <= 0: the
+                                   smallest of 1, 2, 4, 8, 16 whose arena fits a quarter of
+                                   the free device memory (16 if none does) */
     int block;                  /* persistent: lanes per workgroup (64..256); 0 = tuned */
     int waves_per_simd;         /* persistent: resident waves per SIMD (1..2); 0 = tuned */
     int refill;                 /* persistent: idle lanes that trigger a refill; 0 = tuned */
@@ -317,15 +319,21 @@ int chem_integrate_batched(const chem_mechanism *m, int nfield, double *const *T
    summed over cells in a fixed order (bitwise reproducible).  T_end/Y_end
    (device, both or neither) receive the forward result, bitwise equal to
    chem_integrate's.  The call first runs a sizing pass, then stores each
-   cell's state every opt->checkpoint_every (1..16, default 4) accepted steps
-   and recomputes in between; it allocates its arena (8 bytes per accepted
-   step plus one state per checkpoint per cell, and 24 n_reactions bytes per
-   cell) for the call and synchronises the stream.  Returns
+   cell's state every opt->checkpoint_every accepted steps (see chem_options;
+   by default every step whenever memory allows) and recomputes in between;
+   it allocates its arena (8 bytes per accepted step plus one state per
+   checkpoint per cell, and 24 n_reactions bytes per resident lane) for the
+   call and synchronises the stream.  Returns
    CHEM_E_CELL_FAILED if a cell failed (stats or not): such cells get NaN
    gT0/gY0 and add nothing to the parameter gradients.  Both kernel forms
    provide it: one cell per lane, or one group of lanes per cell for the
    wave-cooperative form (mechanisms above 13 species), whose transposed
-   solves and Jacobian-transpose products are group reductions. */
+   solves and Jacobian-transpose products are group reductions.  In the one
+   cell per lane form the most expensive cells (at least 0.6 of the largest
+   accepted-step count; CHEM_ADJOINT_GROUP_FRAC in the environment overrides
+   the fraction, 0 turns it off) run on groups of 8 lanes that evaluate the
+   six second-order terms of each step side by side: the same derivative up
+   to the order of that six-term sum. */
 int chem_integrate_adjoint(const chem_mechanism *m, int64_t ncell, const double *T0,
                            const double *p, const double *Y0, double dt, double rtol,
                            double atol, const double *gT, const double *gY, double *gT0,

@@ -182,7 +182,16 @@ struct AdjointArgs {
     int* nrej;
     chem::StepArgs step;
     int K;                 // accepted steps per checkpoint
+    // one cell per lane form: the first kAdjGroup * ngroup lanes form ngroup
+    // groups of kAdjGroup lanes that take the order positions [0, gcells) (the
+    // most expensive cells), group g the positions g, g + ngroup, ...; the
+    // other lanes take the positions from gcells on, one cell per lane
+    long ngroup;
+    long gcells;
 };
+
+// lanes per group of the grouped adjoint (a power of two >= the RODAS4 stages)
+constexpr int kAdjGroup = 8;
 
 // Parameter gradients summed in a fixed order: one workgroup per parameter;
 // thread t adds rows t, t + 256, ... in turn, then a fixed tree.  The rows are

@@ -570,6 +570,11 @@ extern "C" __global__ void __launch_bounds__(256) chem_gather_sample(const Persi
 //     theta-bar += f_theta(Y_s)^T w_s,
 // and, through J(y) inside M, y-bar += sum_s D_{u_s}[J(y)^T w_s] and
 // theta-bar += sum_s D_{u_s}[f_theta(y)^T w_s] (dual numbers along u_s).
+// Those six second-order terms are independent of one another once every w_s
+// is known, so a group of kAdjGroup lanes holding the same cell (all of them
+// repeating the rest of the step) evaluates one direction per lane and sums
+// the group's results; on the critical path of the most expensive cells that
+// replaces six evaluations by one.
 namespace chem {
 
 __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
@@ -613,10 +618,13 @@ __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&
     }
 }
 
+// jd: -1 for a lane of its own (all six directions), else this lane's place
+// in its group (direction jd; lanes 6 and 7 evaluate a zero direction); only
+// lanes with jd <= 0 add the first-order parameter products.
 __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double p, double ip,
                                           const double (&y)[N], double h, double (&lam)[N],
                                           double* __restrict__ gA, double* __restrict__ gb,
-                                          double* __restrict__ gE)
+                                          double* __restrict__ gE, int jd)
 {
     using chem_math::Dual;
     double M[N][N], f[N];
@@ -656,35 +664,65 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
         yb[k] = lam[k];
         for (int s = 0; s < Rodas4::S; ++s) ub[s][k] = mw[s] * lam[k];
     }
+    const double gsc = jd <= 0 ? 1.0 : 0.0;
     for (int s = Rodas4::S - 1; s >= 0; --s) {
         for (int k = 0; k < N; ++k) w[s][k] = ub[s][k];
         lu_solve_t(M, piv, swaps, w[s]);
         double Yb[N];
-        mech::jtv_param(par, p, ip, Ys[s], w[s], Yb, gA, gb, gE);
+        mech::jtv_param(par, p, ip, Ys[s], w[s], Yb, gA, gb, gE, gsc);
         for (int k = 0; k < N; ++k) yb[k] += Yb[k];
         for (int j = 0; j < s; ++j)
             for (int k = 0; k < N; ++k) ub[j][k] = fma(RA[s][j], Yb[k], fma(RC[s][j] * hinv, w[s][k], ub[j][k]));
     }
     // second-order terms at y (J(y) inside M): D_{u_s}[J(y)^T w_s] and the
     // parameter products' derivative, one dual evaluation per stage direction
-    // (the parameter products add only their tangent, see param_acc)
-    for (int s = 0; s < Rodas4::S; ++s) {
+    // (the parameter products add only their tangent, see param_acc), all six
+    // on a lane of its own, direction jd on a lane of a group
+    double sec[N];
+    for (int k = 0; k < N; ++k) sec[k] = 0.0;
+    const int nd = jd < 0 ? Rodas4::S : 1;
+    for (int t = 0; t < nd; ++t) {
         Dual yd[N], vd[N];
-        for (int k = 0; k < N; ++k) yd[k] = Dual(y[k], u[s][k]);
-        mech::jtv_param(par, p, ip, yd, w[s], vd, gA, gb, gE);
-        for (int k = 0; k < N; ++k) yb[k] += vd[k].d;
+        double wd[N];
+        if (jd < 0) {
+            for (int k = 0; k < N; ++k) { yd[k] = Dual(y[k], u[t][k]); wd[k] = w[t][k]; }
+        } else {
+            for (int k = 0; k < N; ++k) {
+                double ud = 0.0, ws = 0.0;
+#pragma unroll
+                for (int s = 0; s < Rodas4::S; ++s) {
+                    ud = jd == s ? u[s][k] : ud;
+                    ws = jd == s ? w[s][k] : ws;
+                }
+                yd[k] = Dual(y[k], ud);
+                wd[k] = ws;
+            }
+        }
+        mech::jtv_param(par, p, ip, yd, wd, vd, gA, gb, gE, 1.0);
+        for (int k = 0; k < N; ++k) sec[k] += vd[k].d;
     }
-    for (int k = 0; k < N; ++k) lam[k] = yb[k];
+    if (jd >= 0) {
+        // butterfly over the group: every lane adds the same pairs, so all
+        // lanes of the group hold the same sums, bit for bit
+#pragma unroll
+        for (int m = 1; m < kAdjGroup; m <<= 1)
+            for (int k = 0; k < N; ++k) sec[k] += __shfl_xor(sec[k], m, kAdjGroup);
+    }
+    for (int k = 0; k < N; ++k) lam[k] = yb[k] + sec[k];
 }
 
 }  // namespace chem
 
 
 
-// Lane s (of a.nslot) takes the cells in positions s, s + nslot, ... of the
-// cost order (descending accepted steps), so the lanes of a wave always work
-// on cells of similar cost, and keeps the parameter gradients of all its cells
-// in registers: one row of partial sums per lane instead of one per cell.
+// The cells in cost order (descending accepted steps): the first a.gcells go
+// to the a.ngroup lane groups (group g: positions g, g + ngroup, ...), whose
+// lanes all run the cell and split the second-order terms of each step (see
+// step_adjoint); the others to the remaining lanes, lane s taking the
+// positions gcells + s, gcells + s + nlane, ...  The lanes of a wave thus work
+// on cells of similar cost, and each keeps the parameter gradients of all its
+// cells in registers: one row of partial sums per lane instead of one per
+// cell.  Within a group only the first lane writes the cell's results.
 extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
 {
     using namespace chem;
@@ -695,7 +733,23 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
     const int ls = blockDim.x;
     double gA[mech::NR], gb[mech::NR], gE[mech::NR];
     for (int j = 0; j < mech::NR; ++j) { gA[j] = 0.0; gb[j] = 0.0; gE[j] = 0.0; }
-    for (long slot = lane; slot < a.ncell; slot += a.nslot) {
+    const long glanes = (long)kAdjGroup * a.ngroup;
+    int jd;
+    long pos0, pstride, pend;
+    if (lane < glanes) {
+        jd = (int)(lane % kAdjGroup);
+        pos0 = lane / kAdjGroup;
+        pstride = a.ngroup;
+        pend = a.gcells;
+    } else {
+        jd = -1;
+        pos0 = a.gcells + (lane - glanes);
+        pstride = a.nslot - glanes;
+        pend = a.ncell;
+    }
+    if (pstride <= 0) pend = pos0;      // no lanes of this kind (the host never launches so)
+    const bool lead = jd <= 0;
+    for (long slot = pos0; slot < pend; slot += pstride) {
         const long cell = a.order[slot];
         Cell c;
         cell_begin(c, a.T0[cell], a.p[cell], a.Y0 + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
@@ -705,23 +759,28 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
         int stored = -1;
         while (!c.done) {
             if (c.nacc % a.K == 0 && c.nacc != stored && c.nacc < cap) {
-                for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
+                if (lead)
+                    for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
                 stored = c.nacc;
             }
             const double hacc = cell_attempt(c, a.par, a.step, ul, ls);
             if (hacc > 0.0) {
                 if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
-                hs[c.nacc - 1] = hacc;
+                if (lead) hs[c.nacc - 1] = hacc;
             }
         }
-        cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
-        if (c.status == CELL_BADINPUT) {
-            a.Tend[cell] = a.T0[cell];
-            for (int k = 0; k < NS; ++k) a.Yend[cell * NS + k] = a.Y0[cell * NS + k];
+        if (lead) {
+            cell_store(c, a.Tend, a.Yend, cell, a.status, a.nacc, a.nrej);
+            if (c.status == CELL_BADINPUT) {
+                a.Tend[cell] = a.T0[cell];
+                for (int k = 0; k < NS; ++k) a.Yend[cell * NS + k] = a.Y0[cell * NS + k];
+            }
         }
         if (c.status != CELL_OK) {
-            a.gT0[cell] = __builtin_nan("");
-            for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = __builtin_nan("");
+            if (lead) {
+                a.gT0[cell] = __builtin_nan("");
+                for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = __builtin_nan("");
+            }
             continue;                   // adds nothing to the parameter gradients
         }
         double lam[N];
@@ -739,10 +798,12 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
                 ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
                 for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
             }
-            for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE);
+            for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE, jd);
         }
-        a.gT0[cell] = lam[0];
-        for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = lam[1 + k];
+        if (lead) {
+            a.gT0[cell] = lam[0];
+            for (int k = 0; k < NS; ++k) a.gY0[cell * NS + k] = lam[1 + k];
+        }
     }
     double* g = a.gpar + lane * 3 * mech::NR;
     for (int j = 0; j < mech::NR; ++j) {

@@ -129,9 +129,11 @@ __device__ __forceinline__ Dual recip(Dual x)
 __device__ __forceinline__ Dual log(Dual x) { return {::log(x.v), x.d / x.v}; }
 __device__ __forceinline__ Dual log10(Dual x) { return {::log10(x.v), x.d / (x.v * 2.302585092994045684)}; }
 
-// Accumulate a parameter product: the value itself, or for a dual number its
-// derivative along the evaluation's direction (the second-order term).
-__device__ __forceinline__ void param_acc(double& a, double g) { a += g; }
-__device__ __forceinline__ void param_acc(double& a, const Dual& g) { a += g.d; }
+// Accumulate a parameter product: the value itself times sc (1, or 0 on the
+// lanes of a lane group that only repeat its leader's first-order terms), or
+// for a dual number its derivative along the evaluation's direction (the
+// second-order term, whatever sc).
+__device__ __forceinline__ void param_acc(double& a, double g, double sc) { a = ::fma(g, sc, a); }
+__device__ __forceinline__ void param_acc(double& a, const Dual& g, double) { a += g.d; }
 
 }  // namespace chem_math

@@ -753,6 +753,21 @@ struct Scratch {
     }
 };
 
+// Cells with at least this fraction of the largest accepted-step count run
+// the adjoint in lane groups (one cell per lane form).  0.6: a grouped step
+// costs about 0.7 of a lane's, so cells below 0.6 of the maximum finish
+// before the grouped ones anyway.  CHEM_ADJOINT_GROUP_FRAC overrides it (0
+// turns the groups off).
+double adjoint_group_fraction()
+{
+    if (const char* e = std::getenv("CHEM_ADJOINT_GROUP_FRAC")) {
+        char* end = nullptr;
+        const double v = std::strtod(e, &end);
+        if (end != e && v >= 0.0 && v <= 1.0) return v;
+    }
+    return 0.6;
+}
+
 }  // namespace
 
 int run_source(chem_mechanism* m, int64_t ncell, double* T, const double* p, double* Y, double dt,
@@ -851,8 +866,8 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     DeviceState* d;
     if (int rc = device_state(m, stream, &d)) return rc;
     const int ns = m->data.ns(), n = ns + 1, nr = m->data.nr();
-    const int K = o.checkpoint_every;
-    if (K < 1 || K > 16) return set_error(CHEM_E_INVAL, "checkpoint_every must be 1..16");
+    int K = o.checkpoint_every;
+    if (K < 0 || K > 16) return set_error(CHEM_E_INVAL, "checkpoint_every must be 1..16");
     if (ncell == 0) {   // parameter gradients are zero; nothing else to do
         struct {
             const double* g;
@@ -888,6 +903,21 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     HIPCHECK(hipMemcpyAsync(nacc_h.data(), na_fwd, sizeof(int32_t) * ncell, hipMemcpyDeviceToHost, stream),
              "copy step counts");
     HIPCHECK(hipStreamSynchronize(stream), "sync sizing pass");
+    if (K == 0) {
+        // the densest checkpoints whose arena fits a quarter of the free device
+        // memory: every step stored means no recomputation in the reverse sweep
+        size_t freeb = 0, totalb = 0;
+        HIPCHECK(hipMemGetInfo(&freeb, &totalb), "device memory info");
+        K = 16;
+        for (int k : {1, 2, 4, 8, 16}) {
+            double bytes = 0.0;
+            for (int64_t c = 0; c < ncell; ++c) bytes += (double)((std::max<int32_t>(nacc_h[c], 0) + k - 1) / k);
+            if (bytes * n * sizeof(double) <= 0.25 * (double)freeb) {
+                K = k;
+                break;
+            }
+        }
+    }
     std::vector<long> off(2 * (size_t)ncell);
     long th = 0, tc = 0;
     for (int64_t c = 0; c < ncell; ++c) {
@@ -924,6 +954,27 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         ashmem = d->stage_lds(64);
         nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * 4 * 64);
     }
+    // One cell per lane: the most expensive cells (those within a fraction of
+    // the largest step count) go to groups of kAdjGroupLanes lanes, which split
+    // the six second-order evaluations of each step and so shorten the
+    // kernel's critical path; whole waves of groups, at most a quarter of the
+    // resident waves, the rest of the lanes one cell each.
+    long ngroup = 0, gcells = 0;
+    if (!m->wide && ncell > 0) {
+        const int64_t cap = (int64_t)d->num_cu * 4 * 64;
+        const double frac = adjoint_group_fraction();
+        const int32_t top = std::max<int32_t>(nacc_h[order[0]], 0);
+        int64_t cand = 0;
+        if (frac > 0.0 && top > 0)
+            while (cand < ncell && std::max<int32_t>(nacc_h[order[cand]], 0) >= frac * top) ++cand;
+        const int64_t per_wave = 64 / kAdjGroupLanes;
+        const int64_t gw = std::min<int64_t>((cand + per_wave - 1) / per_wave, cap / 64 / 4);
+        if (gw > 0) {
+            ngroup = (long)(gw * per_wave);
+            gcells = (long)std::min<int64_t>(ncell, ngroup);
+            nslot = gw * 64 + std::min<int64_t>(ncell - gcells, cap - gw * 64);
+        }
+    }
     long* off_d;
     double *hs, *ck, *gpar;
     if (int rc = s.alloc(&off_d, 2 * (size_t)ncell, "adjoint offsets")) return rc;
@@ -933,7 +984,7 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     HIPCHECK(hipMemcpyAsync(off_d, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, stream),
              "copy offsets");
     AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, (long)nslot, T_end, Y_end, off_d,
-                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K};
+                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K, ngroup, gcells};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     const int64_t alanes = m->wide ? nslot * m->layout.G : nslot;
     if (int rc = launch_1d(d->f_adjoint, alanes, 64, &aa, sizeof aa, stream, "chem_adjoint", ashmem)) return rc;

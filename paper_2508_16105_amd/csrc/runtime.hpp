@@ -85,7 +85,12 @@ struct AdjointArgs {
     int* nrej;
     StepArgs step;
     int K;
+    long ngroup;       // lane groups of the one-cell-per-lane adjoint (see kAdjGroup)
+    long gcells;       // cells (first positions of the cost order) the groups take
 };
+
+// lanes per group of the grouped one-cell-per-lane adjoint (device: kAdjGroup)
+constexpr int kAdjGroupLanes = 8;
 
 struct FieldDesc {
     double* T;
@@ -134,7 +139,7 @@ struct Options {
     int max_substeps = 100000;
     double hmin_rel = 1e-20;
     const double* h0 = nullptr;
-    int checkpoint_every = 4;
+    int checkpoint_every = 0;   // adjoint: 0 = chosen per call (see run_adjoint)
     int block = 0;
     int waves_per_simd = 0;
     int refill = 0;

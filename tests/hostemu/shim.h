@@ -32,6 +32,9 @@ static inline unsigned long long __ballot(bool p) { return p ? 1ull : 0ull; }
 static inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 static inline int __ffsll(long long x) { return __builtin_ffsll(x); }
 template <class T> static inline T __shfl(T v, int) { return v; }
+// lanes run one at a time here, so nothing across lanes can be emulated; the
+// grouped adjoint (the only user) is never launched by the driver
+template <class T> static inline T __shfl_xor(T, int, int) { __builtin_trap(); }
 template <class T, class U> static inline T atomicAdd(T* p, U v) { T o = *p; *p = (T)(o + (T)v); return o; }
 template <class T, class U> static inline T atomicMax(T* p, U v) { T o = *p; if ((T)v > o) *p = (T)v; return o; }
 static inline void __syncthreads() {}

@@ -198,6 +198,42 @@ def test_wide_adjoint_m32_sample(chem, oracle_lib, dev):
     assert np.array_equal(a[5], Ti.cpu().numpy()) and np.array_equal(a[6], Yi.cpu().numpy())
 
 
+@pytest.mark.parametrize("name", ["m9", "m13"])
+def test_adjoint_lane_groups_match_single_lanes(chem, mechs, dev, monkeypatch, name):
+    """The grouped adjoint (the most expensive cells on groups of 8 lanes that
+    split each step's six second-order evaluations) computes the same
+    derivative as one lane per cell, up to the order of that six-term sum:
+    every cell run grouped (fraction 1e-9: all cells qualify), none grouped
+    (0) and the default split agree to 1e-11 relative, and the all-grouped
+    run meets the oracle bar."""
+    gm, om = mechs[name]
+    if name == "m9":
+        T, p, Y, w = _adj256k_sample(per_region=16, seed=9)
+        dt = w["dt"]
+    else:
+        T, p, Y = uniform_cells(mech_text(name), 40, 66)
+        dt = 1e-8
+    gT, gY = _loss_weights(name, len(T), True, seed=15)
+    runs = {}
+    for frac in ("0", "1e-9", None):
+        if frac is None:
+            monkeypatch.delenv("CHEM_ADJOINT_GROUP_FRAC", raising=False)
+        else:
+            monkeypatch.setenv("CHEM_ADJOINT_GROUP_FRAC", frac)
+        runs[frac] = _run(chem, gm, T, p, Y, dt, gT, gY, dev)
+        assert runs[frac][7]["failed"] == 0
+    base = runs["0"]
+    for frac in ("1e-9", None):
+        r = runs[frac]
+        assert np.array_equal(r[5], base[5]) and np.array_equal(r[6], base[6])   # forward states
+        assert np.all(np.abs(r[0] - base[0]) <= 1e-11 * np.abs(base[0])), frac
+        sc = np.max(np.abs(base[1]), axis=1, keepdims=True)
+        assert np.all(np.abs(r[1] - base[1]) <= 1e-11 * sc), frac
+        for i in (2, 3, 4):
+            assert np.max(np.abs(r[i] - base[i])) <= 1e-11 * np.max(np.abs(base[i])), (frac, i)
+    _assert_grad_parity(*runs["1e-9"][:5], *_oracle_adjoint(om, T, p, Y, dt, gT, gY), f"{name} grouped")
+
+
 def test_adjoint_forward_result_equals_integrate(chem, mechs, dev):
     gm, _ = mechs["m9"]
     T, p, Y = uniform_cells(mech_text("m9"), 300, 62)
