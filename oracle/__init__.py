@@ -15,7 +15,7 @@ import numpy as np
 HERE = pathlib.Path(__file__).resolve().parent
 LIB = HERE / "liboracle.so"
 SOURCES = [HERE / "oracle.c", HERE / "chem_generic.inc", HERE / "oracle.h", HERE / "oracle_internal.h",
-           HERE / "count.cpp"]
+           HERE / "count.cpp", HERE / "abi.c", HERE / "oracle_abi.h"]
 
 RODAS4 = 0
 ROS4 = 1
@@ -30,19 +30,22 @@ class Opts(C.Structure):
 
 
 def build(force: bool = True) -> pathlib.Path:
-    """Compile liboracle.so: oracle.c with gcc (plain C11 + OpenMP) and the
-    counted instantiation count.cpp with g++, linked into one library."""
+    """Compile liboracle.so: oracle.c with gcc (plain C11 + OpenMP), the
+    counted instantiation count.cpp with g++ and the C ABI layer abi.c,
+    linked into one library."""
     if not force and LIB.exists() and all(LIB.stat().st_mtime >= s.stat().st_mtime for s in SOURCES):
         return LIB
     import tempfile
     tmp = LIB.with_suffix(".so.tmp")
     with tempfile.TemporaryDirectory() as d:
-        co, cc = os.path.join(d, "oracle.o"), os.path.join(d, "count.o")
+        co, cc, ca = os.path.join(d, "oracle.o"), os.path.join(d, "count.o"), os.path.join(d, "abi.o")
         subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-fcx-limited-range", "-Wall",
                         "-c", str(HERE / "oracle.c"), "-o", co], check=True)
+        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-Wall", "-c", str(HERE / "abi.c"), "-o", ca],
+                       check=True)
         subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
                         "-c", str(HERE / "count.cpp"), "-o", cc], check=True)
-        subprocess.run(["g++", "-shared", "-fopenmp", "-o", str(tmp), co, cc, "-lm"], check=True)
+        subprocess.run(["g++", "-shared", "-fopenmp", "-o", str(tmp), co, cc, ca, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
