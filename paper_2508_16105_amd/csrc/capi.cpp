@@ -123,7 +123,12 @@ int finish_load(std::unique_ptr<chem_mechanism> m, chem_mechanism** out)
         return set_error(CHEM_E_UNSUPPORTED, "more than " + std::to_string(CHEM_MAX_SPECIES) + " species");
     m->params = pack_params(m->data);
     if (m->data.ns() <= lane_max_species()) {
-        m->source = device_source(generate_mechanism_source(m->data), false);
+        // the exponent conversion that saves two instructions per exp also
+        // changes register allocation: in the one-cell-per-lane kernels of
+        // mechanisms above 9 species, which spill, it raised the spill
+        // (13 species: 1,392 -> 1,604 B per lane) and the run time (+18 %),
+        // so those keep the clamped conversion
+        m->source = device_source(generate_mechanism_source(m->data), false, m->data.ns() + 1 <= 10);
     } else {
         m->layout = wide_layout(m->data);
         if (m->layout.G == 0)
@@ -131,7 +136,7 @@ int finish_load(std::unique_ptr<chem_mechanism> m, chem_mechanism** out)
                                                      "coefficient over 3 on a reaction side, |dnu| over 4, or over "
                                                      "511 third-body or falloff reactions, or over 511 PLOG reactions)");
         m->wide = true;
-        m->source = device_source(generate_wide_source(m->data, m->layout), true);
+        m->source = device_source(generate_wide_source(m->data, m->layout), true, true);
     }
     if (int rc = build_code_object(m->source, m->code, err, &m->cache_file)) return set_error(rc, err);
     // with a gfx950 device current, load the code there now, so that the

@@ -439,8 +439,11 @@ struct Emitter {
         if (r.kind != RxnKind::Elementary && !plog) o << "    const S Mc = " << third_body_sum(r) << ";\n";
         if (!falloff) {
             o << "    const S kf = chem_math::exp_poly(lnk);\n";
-            if (pform) o << "    const S kr = kf * ikc;\n";
-            else if (rev_on) o << "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
+            if (pform) {
+                if (jac) o << "    const S kr = kf * ikc;\n";
+            } else if (rev_on) {
+                o << "    const S kr = chem_math::exp_poly(lnk - lnKc);\n";
+            }
         } else {
             // P_r = k0 [M] / k_inf, one exponential for the ratio
             o << "    const S kinf = chem_math::exp_poly(lnk);\n"
@@ -500,14 +503,21 @@ struct Emitter {
             }
             o << "    const S ipr1 = chem_math::recip(1.0 + Pr);\n"
                  "    const S kf = kinf * Pr * ipr1 * Fb;\n";
-            if (pform)
-                o << "    const S iKc = ikc;\n"
-                     "    const S kr = kf * iKc;\n";
-            else if (rev_on)
+            if (pform) {
+                if (jac)
+                    o << "    const S iKc = ikc;\n"
+                         "    const S kr = kf * iKc;\n";
+            } else if (rev_on)
                 o << "    const S iKc = chem_math::exp_poly(-lnKc);\n"
                      "    const S kr = kf * iKc;\n";
         }
-        if (rev_on)
+        if (pform && !jac) {
+            // source terms alone: q = k_f (prod_reac C - prod_prod C / K_c),
+            // one rounding for the difference
+            o << "    const S pf = " << side_product(r.reac) << ";\n"
+                 "    const S pr = " << side_product(r.prod) << ";\n"
+                 "    const S q = " << (r.kind == RxnKind::ThirdBody ? "Mc * " : "") << "(kf * fma(-ikc, pr, pf));\n";
+        } else if (rev_on)
             o << "    const S pf = " << side_product(r.reac) << ";\n"
                  "    const S pr = " << side_product(r.prod) << ";\n"
                  "    const S fwd = kf * pf;\n"
@@ -516,8 +526,10 @@ struct Emitter {
             o << "    const S pf = " << side_product(r.reac) << ";\n"
                  "    const S fwd = kf * pf;\n";
         const std::string net = rev_on ? "(fwd - rev)" : "fwd";
-        if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * " << net << ";\n";
-        else o << "    const S q = " << (rev_on ? "fwd - rev" : "fwd") << ";\n";
+        if (!(pform && !jac)) {
+            if (r.kind == RxnKind::ThirdBody) o << "    const S q = Mc * " << net << ";\n";
+            else o << "    const S q = " << (rev_on ? "fwd - rev" : "fwd") << ";\n";
+        }
         // production rates
         std::vector<int> nu(ns, 0);
         for (auto& t : r.reac) nu[t.sp] -= t.nu;

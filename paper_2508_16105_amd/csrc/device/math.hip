@@ -13,8 +13,8 @@
 // exp_poly_coeffs.py in the package directory).  No lookup table, so no LDS read
 // whose latency a single wave per SIMD would have to wait out.  NaN
 // propagates, arguments beyond the double range give 0 or inf through ldexp
-// (the exponent is clamped before its conversion to int), +-inf give NaN (a
-// failed step for the caller).
+// (the exponent's conversion to int saturates or is clamped), +-inf give NaN
+// (a failed step for the caller).
 
 namespace chem_math {
 
@@ -24,11 +24,18 @@ __device__ __forceinline__ double exp_poly(double x)
     constexpr double kLn2Hi = 0.6931471805599453;           // ln 2 rounded to double
     constexpr double kLn2Lo = 2.3190468138462996e-17;       // ln 2 - kLn2Hi
     const double nd = __builtin_rint(x * kLog2e);
-    // The exponent as an int, clamped first: converting a NaN or an
-    // out-of-range double to int is undefined behaviour (LLVM turns it into
-    // poison, which the optimiser may propagate anywhere).  2^+-2100 already
-    // saturates ldexp to inf or 0, and a NaN x still gives NaN through r.
-    const int n = (int)fmin(fmax(nd, -2100.0), 2100.0);
+    // The exponent as an int.  A C++ conversion is undefined behaviour for NaN
+    // and out-of-range values (LLVM turns it into poison, which the optimiser
+    // may propagate anywhere), so either the hardware conversion, which is
+    // defined for every input (beyond the int range INT_MIN or INT_MAX, NaN 0),
+    // or a clamp to [-2100, 2100] first (two more instructions); either way
+    // ldexp then gives 0 or inf where the result needs it, and a NaN x still
+    // gives NaN through r.  The choice is the generator's (chem_config).
+    int n;
+    if constexpr (chem_config::kExpSaturatingConvert)
+        asm("v_cvt_i32_f64 %0, %1" : "=v"(n) : "v"(nd));
+    else
+        n = (int)fmin(fmax(nd, -2100.0), 2100.0);
     double r = fma(-nd, kLn2Hi, x);
     r = fma(-nd, kLn2Lo, r);
     double q = fma(2.5110037605963777e-08, r, 2.763263963904103e-07);

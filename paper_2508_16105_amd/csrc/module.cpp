@@ -21,9 +21,11 @@ namespace chemmi {
 
 #include "_device_source.inc"   // kMathSource, kCommonSource, kIntegratorSource, kWideSource, kEulerSource
 
-std::string device_source(const std::string& mechanism_code, bool wide)
+std::string device_source(const std::string& mechanism_code, bool wide, bool exp_saturating)
 {
-    return std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kCommonSource) + "\n" +
+    const std::string config = std::string("namespace chem_config {\nconstexpr bool kExpSaturatingConvert = ") +
+                               (exp_saturating ? "true" : "false") + ";\n}\n";
+    return config + std::string(kMathSource) + "\n" + mechanism_code + "\n" + std::string(kCommonSource) + "\n" +
            std::string(wide ? kWideSource : kIntegratorSource) + "\n" + std::string(kEulerSource);
 }
 

@@ -12,7 +12,10 @@ namespace chemmi {
 // Full device source for a mechanism: the generated mechanism code followed by
 // the hand-written integrator and kernels (one cell per lane, or with `wide`
 // the wave-cooperative form).
-std::string device_source(const std::string& mechanism_code, bool wide);
+// The complete device source of a mechanism: the math, the generated
+// mechanism code, the shared and form-specific kernels.  exp_saturating picks
+// how exp_poly converts its exponent to int (see math.hip).
+std::string device_source(const std::string& mechanism_code, bool wide, bool exp_saturating);
 
 // Compile options used for every device build (gfx950, FP64, contraction of
 // a*b+c into FMA only within an expression, no packed-FP32 instructions).

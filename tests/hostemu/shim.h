@@ -38,6 +38,14 @@ template <class T> static inline T __shfl_xor(T, int, int) { __builtin_trap(); }
 template <class T, class U> static inline T atomicAdd(T* p, U v) { T o = *p; *p = (T)(o + (T)v); return o; }
 template <class T, class U> static inline T atomicMax(T* p, U v) { T o = *p; if ((T)v > o) *p = (T)v; return o; }
 static inline void __syncthreads() {}
+// the hardware's double-to-int conversion: saturating, NaN to 0
+static inline int emu_cvt_i32_sat(double x)
+{
+    if (x != x) return 0;
+    if (x >= 2147483647.0) return 2147483647;
+    if (x <= -2147483648.0) return -2147483647 - 1;
+    return (int)x;
+}
 static inline long long __double_as_longlong(double x) { long long b; __builtin_memcpy(&b, &x, sizeof b); return b; }
 static inline double __longlong_as_double(long long b) { double x; __builtin_memcpy(&x, &b, sizeof x); return x; }
 template <class T> static inline T min(T a, T b) { return b < a ? b : a; }

@@ -42,6 +42,7 @@ def host_source(text: str) -> str:
     text = re.sub(r'asm volatile\(""[^;]*\);', "", text)
     text = text.replace("__builtin_amdgcn_readfirstlane(", "(")
     text = text.replace("__builtin_amdgcn_rcp(", "1.0 / (")
+    text = text.replace('asm("v_cvt_i32_f64 %0, %1" : "=v"(n) : "v"(nd));', "n = emu_cvt_i32_sat(nd);")
     text = text.replace("__attribute__((address_space(4)))", "")
     text = text.replace("extern __shared__ double lds[];", "double* lds = emu_lds;")
     assert "asm" not in re.sub(r"//.*", "", text).replace("__asm", ""), "unhandled inline asm"

@@ -35,11 +35,12 @@ def _fma(a, b, c):
 
 
 def _exp_poly(x, named, poly):
-    """The device sequence: rint, the exponent clamped to [-2100, 2100]
-    (fmax then fmin, so NaN gives -2100) and converted to int, two-part
-    reduction, Horner, ldexp."""
+    """The device sequence: rint, the exponent converted to int as the
+    hardware does (saturating at the int range, NaN to 0; the clamped
+    conversion the generator may choose instead gives the same results),
+    two-part reduction, Horner, ldexp."""
     nd = float(np.rint(x * named["kLog2e"]))
-    n = -2100 if math.isnan(nd) else int(min(max(nd, -2100.0), 2100.0))
+    n = 0 if math.isnan(nd) else int(min(max(nd, -2.0**31), 2.0**31 - 1))
     r = _fma(-nd, named["kLn2Hi"], x)
     r = _fma(-nd, named["kLn2Lo"], r)
     q = _fma(poly[0], r, poly[1])
