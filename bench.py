@@ -34,6 +34,15 @@ KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
 TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
 
 
+_T_START = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr as each part of the run ends (the JSON line alone
+    goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash(mech_file: str) -> str:
     import hashlib
     h = hashlib.sha256()
@@ -436,6 +445,7 @@ def main():
         wall = time.perf_counter() - t0
         kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         subs = st["accepted"] + st["rejected"]
+        progress(f"{args.workload} {name}: {1e3 * wall / args.steps:.2f} ms per step")
         results[name] = dict(ms_per_step=1e3 * wall / args.steps, kernel_ms=kms,
                              cell_steps_per_s=ncell * args.steps / wall,
                              substeps=subs, accepted=st["accepted"], rejected=st["rejected"],
@@ -524,16 +534,22 @@ def main():
                                "over_integrate": sms / results["persistent"]["ms_per_step"]}
     if not args.no_euler:
         line["euler1d"] = euler_leg(chem, torch, dev)
+        progress("1D driver leg done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(T, p, Y, w, args.cpu_sample)
+        progress("CPU baseline done")
     if not args.no_amr:   # the 13-species per-field plain launches (~80 s) only with --amr-only
         line["amr64"] = amr_leg(chem, torch, dev, 1, plain_mechs=("m9",))
+        progress("64-field leg done")
     if not args.no_big:
         line["big4m"] = big_leg(chem, torch, dev, 2)
+        progress("32-species field done")
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else args.adjoint_cpu_cells)
+        progress("adjoint done")
         if not args.no_big:
             line["adjoint_big4m"] = adjoint_leg(chem, torch, dev, 1, 0 if args.no_cpu else 16, "big4m")
+            progress("32-species adjoint done")
     print(json.dumps(line))
 
 
