@@ -30,7 +30,8 @@ KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
                   "paper_2508_16105_amd/csrc/device/math.hip",
                   "paper_2508_16105_amd/csrc/device/euler.hip",
                   "paper_2508_16105_amd/csrc/codegen.cpp",
-                  "paper_2508_16105_amd/csrc/module.cpp"]
+                  "paper_2508_16105_amd/csrc/module.cpp",
+                  "paper_2508_16105_amd/csrc/capi.cpp"]
 TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
 
 
