@@ -254,15 +254,25 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
         for _ in range(steps):
             chem.integrate(*args, form=form)
         fwd[name] = 1e3 * (time.perf_counter() - t0) / steps
-    chem.integrate_adjoint(*args, gTd, gYd)                            # warm
+    # the workload's checkpoint interval: every 4th accepted substep
+    chem.integrate_adjoint(*args, gTd, gYd, checkpoint_every=4)       # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kms = []
     for _ in range(steps):
-        out = chem.integrate_adjoint(*args, gTd, gYd)
+        out = chem.integrate_adjoint(*args, gTd, gYd, checkpoint_every=4)
         kms.append(out[7]["kernel_ms"])
     adj_ms = 1e3 * (time.perf_counter() - t0) / steps
     st = out[7]
+    # the library's default interval (every step when the arena fits), one call
+    auto = None
+    if workload == "adj256k":
+        chem.integrate_adjoint(*args, gTd, gYd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        oa = chem.integrate_adjoint(*args, gTd, gYd)
+        auto = {"ms_per_call": 1e3 * (time.perf_counter() - t0), "adjoint_kernel_ms": oa[7]["kernel_ms"],
+                "checkpoint_every": "densest interval whose arena fits a quarter of free memory (1 here)"}
     res = {"workload": workload, "cells": n,
            "mechanism": f"{w['mech']} ({mech.ns} species, {mech.nr} reactions)",
            "dt": w["dt"], "params": 3 * mech.nr,
@@ -270,8 +280,10 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
            "forward_ms": fwd, "adjoint_over_forward": {k: adj_ms / v for k, v in fwd.items()},
            "cell_steps_per_s": n / (adj_ms * 1e-3),
            "accepted": st["accepted"], "max_substeps_cell": st["max_substeps"],
-           "checkpoint_every": "auto (densest interval whose arena fits a quarter of free memory)",
+           "checkpoint_every": 4,
            "lane_groups": "cells >= 0.6 x the largest step count on 8-lane groups (one cell per lane form)"}
+    if auto:
+        res["default_checkpoints"] = auto
     if cpu_cells:
         import oracle
         om = oracle.Mechanism(mech_path(w["mech"]))
