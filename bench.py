@@ -264,9 +264,26 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
         kms.append(out[7]["kernel_ms"])
     adj_ms = 1e3 * (time.perf_counter() - t0) / steps
     st = out[7]
-    # the library's default interval (every step when the arena fits), one call
-    auto = None
+    # the library's default interval (every step when the arena fits), one call;
+    # and the workload's interval given the step counts of a forward
+    # integration of the same field (as in autograd, where the forward ran
+    # first), which spares the sizing pass
+    auto = hinted = None
     if workload == "adj256k":
+        nacc = chem.integrate(*args, form=chem.FORM_PERSISTENT, return_counts=True)[4]
+        chem.integrate_adjoint(*args, gTd, gYd, checkpoint_every=4, forward_nacc=nacc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            oh = chem.integrate_adjoint(*args, gTd, gYd, checkpoint_every=4, forward_nacc=nacc)
+        hinted = {"ms_per_call": 1e3 * (time.perf_counter() - t0) / steps,
+                  "adjoint_kernel_ms": oh[7]["kernel_ms"], "checkpoint_every": 4}
+        # what ChemIntegrate's backward runs: the forward's counts, the default interval
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ob = chem.integrate_adjoint(*args, gTd, gYd, forward_nacc=nacc)
+        hinted["default_checkpoints_ms_per_call"] = 1e3 * (time.perf_counter() - t0)
+        hinted["default_checkpoints_kernel_ms"] = ob[7]["kernel_ms"]
         chem.integrate_adjoint(*args, gTd, gYd)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -284,6 +301,8 @@ def adjoint_leg(chem, torch, dev, steps, cpu_cells, workload="adj256k"):
            "lane_groups": "cells >= 0.6 x the largest step count on 8-lane groups (one cell per lane form)"}
     if auto:
         res["default_checkpoints"] = auto
+    if hinted:
+        res["with_forward_step_counts"] = hinted
     if cpu_cells:
         import oracle
         om = oracle.Mechanism(mech_path(w["mech"]))

@@ -65,8 +65,9 @@ enum chem_cell_status {
     CHEM_CELL_MAXSTEPS = 1,     /* max_substeps attempts without reaching dt */
     CHEM_CELL_HMIN = 2,         /* step size fell below hmin_rel * dt */
     CHEM_CELL_NONFINITE = 3,    /* adjoint only: the checkpointed rerun of a cell took more
-                                   accepted steps than its sizing pass (not expected: both
-                                   run the same code on the same input) */
+                                   accepted steps than its sizing pass or the caller's
+                                   adjoint_nacc entry allows (the sizing pass runs the same
+                                   code on the same input, so only a wrong entry does it) */
     CHEM_CELL_BADINPUT = 4      /* T <= 0, p <= 0 or a non-finite input */
 };
 
@@ -102,6 +103,12 @@ typedef struct {
                                    fields without one get a cost predicted from their state:
                                    the mean over the components of
                                    log2(1 + |f_k(y)| dt / (atol + rtol |y_k|)) */
+    const int32_t *adjoint_nacc; /* adjoint: nullable device int32 [ncell], the accepted
+                                   substeps of every cell in a forward integration of the same
+                                   input with the same tolerances and limits (chem_integrate's
+                                   nacc, either form); given, the adjoint skips its own sizing
+                                   pass.  A cell whose rerun takes more steps than its entry
+                                   fails with CHEM_CELL_NONFINITE (NaN gradients) */
 } chem_options;
 
 typedef struct {

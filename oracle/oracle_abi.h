@@ -18,8 +18,9 @@
  *
  * The method is the oracle's RODAS4 integration (oracle.h); the GPU-only
  * launch knobs of the options (form, block, waves per SIMD, refill, order,
- * cost, checkpoint interval) change no result and are accepted and ignored,
- * except that a checkpoint interval above 16 is a bad argument as there.
+ * cost, checkpoint interval, a forward's step counts) change no result and
+ * are accepted and ignored, except that a checkpoint interval above 16 is a
+ * bad argument as there.
  */
 #ifndef CHEM_ORACLE_ABI_H
 #define CHEM_ORACLE_ABI_H
@@ -47,6 +48,7 @@ typedef struct {
     int checkpoint_every;        /* adjoint: 0..16 accepted, no effect here */
     int block, waves_per_simd, refill, order;
     const int32_t *const *cost;
+    const int32_t *adjoint_nacc;  /* a forward's step counts: no effect here */
 } oracle_options;
 
 typedef struct {

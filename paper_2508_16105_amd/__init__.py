@@ -89,14 +89,15 @@ class Mechanism:
 
 
 def _options(form=FORM_AUTO, max_substeps=0, hmin_rel=0.0, h0=None, checkpoint_every=0, block=0,
-             waves_per_simd=0, refill=0, order=0, cost=None):
+             waves_per_simd=0, refill=0, order=0, cost=None, adjoint_nacc=None):
     """cost: None, or a list with one int32 GPU tensor (or None) per field."""
     carr = None
     if cost is not None:
         carr = (C.c_void_p * max(len(cost), 1))(*[None if c is None else c.data_ptr() for c in cost])
     o = _lib.Options(form, max_substeps, hmin_rel, None if h0 is None else h0.data_ptr(),
                      checkpoint_every, block, waves_per_simd, refill, order,
-                     C.cast(carr, C.POINTER(C.c_void_p)) if carr is not None else None)
+                     C.cast(carr, C.POINTER(C.c_void_p)) if carr is not None else None,
+                     None if adjoint_nacc is None else adjoint_nacc.data_ptr())
     o._keep = carr
     return o
 
@@ -264,10 +265,13 @@ def step_fixed(mech: Mechanism, T, p, Y, h, rtol=1e-8, atol=1e-12, stream=None):
 
 
 def integrate_adjoint(mech: Mechanism, T0, p, Y0, dt, rtol, atol, gT, gY, *, stats=True,
-                      stream=None, checkpoint_every=0, allow_failed=False, **opts):
+                      stream=None, checkpoint_every=0, allow_failed=False, forward_nacc=None, **opts):
     """Discrete adjoint of the frozen-step map.  Returns
     (gT0, gY0, g_lnA, g_b, g_Ea, T_end, Y_end, stats).  Failed cells (with
-    allow_failed) get NaN gT0/gY0 and add nothing to the parameter gradients."""
+    allow_failed) get NaN gT0/gY0 and add nothing to the parameter gradients.
+    forward_nacc: the int32 per-cell accepted steps of a forward integration
+    of the same input (integrate's nacc), which spares the adjoint its own
+    sizing pass."""
     torch = _torch()
     n = T0.shape[0]
     for t, nm, sh in ((T0, "T0", (n,)), (p, "p", (n,)), (Y0, "Y0", (n, mech.ns)),
@@ -280,7 +284,9 @@ def integrate_adjoint(mech: Mechanism, T0, p, Y0, dt, rtol, atol, gT, gY, *, sta
     Te = torch.empty(n, dtype=torch.float64, device=dev)
     Ye = torch.empty((n, mech.ns), dtype=torch.float64, device=dev)
     s = _lib.Stats() if stats else None
-    o = _options(checkpoint_every=checkpoint_every, **opts)
+    if forward_nacc is not None:
+        _check_tensor(forward_nacc, "forward_nacc", (n,), dtype=torch.int32)
+    o = _options(checkpoint_every=checkpoint_every, adjoint_nacc=forward_nacc, **opts)
     rc = _lib.lib().chem_integrate_adjoint(
         mech.h, n, _ptr(T0), _ptr(p), _ptr(Y0), float(dt), float(rtol), float(atol), _ptr(gT),
         _ptr(gY), _ptr(gT0), _ptr(gY0), _ptr(ga), _ptr(gb), _ptr(ge), _ptr(Te), _ptr(Ye),
@@ -304,9 +310,10 @@ def _make_autograd():
             # with stats the call waits for the result and raises ChemError
             # (CHEM_E_CELL_FAILED) if a cell failed, instead of handing back a
             # failed cell's last accepted partial state
-            Te, Ye, _ = integrate(mech, T.detach(), p.detach(), Y.detach(), dt, rtol, atol,
-                                  stats=True)
+            Te, Ye, _, _, nacc, _ = integrate(mech, T.detach(), p.detach(), Y.detach(), dt, rtol, atol,
+                                              stats=True, return_counts=True)
             ctx.mech, ctx.dt, ctx.rtol, ctx.atol = mech, dt, rtol, atol
+            ctx.nacc = nacc                  # spares the backward its sizing pass
             ctx.save_for_backward(T.detach(), p.detach(), Y.detach())
             ctx.params = (lnA.detach().cpu().numpy(), b.detach().cpu().numpy(), Ea.detach().cpu().numpy())
             return Te, Ye
@@ -319,7 +326,8 @@ def _make_autograd():
             gTe = torch.zeros_like(T) if gTe is None else gTe.contiguous().to(torch.float64)
             gYe = torch.zeros_like(Y) if gYe is None else gYe.contiguous().to(torch.float64)
             gT0, gY0, ga, gb, ge, _, _, _ = integrate_adjoint(mech, T, p, Y, ctx.dt, ctx.rtol,
-                                                              ctx.atol, gTe, gYe, stats=False)
+                                                              ctx.atol, gTe, gYe, stats=False,
+                                                              forward_nacc=ctx.nacc)
             return None, gT0, None, gY0, ga, gb, ge, None, None, None
 
     return ChemIntegrate

@@ -26,7 +26,7 @@ class Options(C.Structure):
     _fields_ = [("form", C.c_int), ("max_substeps", C.c_int), ("hmin_rel", C.c_double),
                 ("h0", C.c_void_p), ("checkpoint_every", C.c_int), ("block", C.c_int),
                 ("waves_per_simd", C.c_int), ("refill", C.c_int), ("order", C.c_int),
-                ("cost", C.POINTER(C.c_void_p))]
+                ("cost", C.POINTER(C.c_void_p)), ("adjoint_nacc", C.c_void_p)]
 
 
 class Stats(C.Structure):

@@ -108,6 +108,7 @@ Options resolve_options(const chem_options* o)
         r.refill = o->refill;
         r.order = o->order;
         r.cost = o->cost;
+        r.adjoint_nacc = o->adjoint_nacc;
     }
     return r;
 }
@@ -489,6 +490,8 @@ int chem_integrate_adjoint(const chem_mechanism* mc, int64_t ncell, const double
         return set_error(CHEM_E_INVAL, "T_end/Y_end is not a device pointer");
     if (!T_end != !Y_end) return set_error(CHEM_E_INVAL, "give both T_end and Y_end or neither");
     Options o = resolve_options(opt);
+    if (o.adjoint_nacc && ncell > 0 && !is_device_ptr(o.adjoint_nacc))
+        return set_error(CHEM_E_INVAL, "adjoint_nacc is not a device pointer");
     if (o.h0 && !is_device_ptr(o.h0)) return set_error(CHEM_E_INVAL, "h0 is not a device pointer");
     std::lock_guard<std::mutex> lk(m->mu);
     DoneMark mark{m, (hipStream_t)stream};

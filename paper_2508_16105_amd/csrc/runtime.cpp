@@ -888,7 +888,10 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     HIPCHECK(hipMemcpyAsync(Tw, T0, sizeof(double) * ncell, hipMemcpyDeviceToDevice, stream), "copy T0");
     HIPCHECK(hipMemcpyAsync(Yw, Y0, sizeof(double) * ncell * ns, hipMemcpyDeviceToDevice, stream), "copy Y0");
     const StepArgs step = step_args(dt, rtol, atol, o);
-    if (o.h0) {
+    if (o.adjoint_nacc) {   // the caller's forward already counted the steps
+        HIPCHECK(hipMemcpyAsync(na_fwd, o.adjoint_nacc, sizeof(int32_t) * ncell, hipMemcpyDeviceToDevice, stream),
+                 "copy the forward's step counts");
+    } else if (o.h0) {
         IntegrateArgs ia{d->par, Tw, p, Yw, (long)ncell, o.h0, st, na_fwd, nj, step};
         const int64_t lanes = m->wide ? ncell * m->layout.G : ncell;
         const unsigned shmem = m->wide ? m->layout.lds_bytes() : d->stage_lds(64);

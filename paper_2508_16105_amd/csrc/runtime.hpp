@@ -140,6 +140,7 @@ struct Options {
     double hmin_rel = 1e-20;
     const double* h0 = nullptr;
     int checkpoint_every = 0;   // adjoint: 0 = chosen per call (see run_adjoint)
+    const int32_t* adjoint_nacc = nullptr;   // adjoint: a forward's accepted steps (skips the sizing pass)
     int block = 0;
     int waves_per_simd = 0;
     int refill = 0;

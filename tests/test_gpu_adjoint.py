@@ -234,6 +234,37 @@ def test_adjoint_lane_groups_match_single_lanes(chem, mechs, dev, monkeypatch, n
     _assert_grad_parity(*runs["1e-9"][:5], *_oracle_adjoint(om, T, p, Y, dt, gT, gY), f"{name} grouped")
 
 
+def test_adjoint_with_the_forward_step_counts(chem, mechs, dev):
+    """Given the per-cell accepted steps of a forward integration of the same
+    input, the adjoint skips its sizing pass and returns bitwise the same
+    results; an entry too small for its cell's rerun fails that cell alone
+    (CHEM_CELL_NONFINITE: NaN gradients, nothing added to the parameter sums)."""
+    gm, _ = mechs["m9"]
+    T, p, Y, w = _adj256k_sample(per_region=12, seed=21)
+    gT, gY = _loss_weights("m9", len(T), True, seed=16)
+    Tg, pg, Yg = _g(T, dev), _g(p, dev), _g(Y, dev)
+    _, _, _, st, nacc, _ = chem.integrate(gm, Tg, pg, Yg, w["dt"], RTOL, ATOL, return_counts=True)
+    assert torch.all(st == 0)
+    base = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev)
+    hinted = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev, forward_nacc=nacc)
+    for a, b in zip(base[:7], hinted[:7]):
+        assert np.array_equal(a, b)
+    assert hinted[7]["accepted"] == base[7]["accepted"] and hinted[7]["failed"] == 0
+    i = int(torch.argmax(nacc))
+    short = nacc.clone()
+    short[i] -= 1
+    with pytest.raises(chem.ChemError) as err:
+        _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev, forward_nacc=short)
+    assert err.value.code == -6
+    bad = _run(chem, gm, T, p, Y, w["dt"], gT, gY, dev, forward_nacc=short, allow_failed=True)
+    keep = np.array([k for k in range(len(T)) if k != i])
+    assert np.isnan(bad[0][i]) and np.all(np.isnan(bad[1][i])) and bad[7]["failed"] == 1
+    assert np.allclose(bad[0][keep], base[0][keep], rtol=1e-11, atol=0)
+    only = _run(chem, gm, T[keep], p[keep], Y[keep], w["dt"], gT[keep], gY[keep], dev)
+    for k in (2, 3, 4):
+        assert np.allclose(bad[k], only[k], rtol=1e-11, atol=0)
+
+
 def test_adjoint_forward_result_equals_integrate(chem, mechs, dev):
     gm, _ = mechs["m9"]
     T, p, Y = uniform_cells(mech_text("m9"), 300, 62)
