@@ -23,34 +23,37 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6e12          # MI355X FP64 vector peak, FLOP/s
 RODAS4_STAGES = 6
-# The device code of a mechanism is generated from these files; HBM traffic
-# recorded under profiles/ applies only while their hash is unchanged.
-KERNEL_SOURCES = ["paper_2508_16105_amd/csrc/device/integrator.hip",
-                  "paper_2508_16105_amd/csrc/device/common.hip",
-                  "paper_2508_16105_amd/csrc/device/math.hip",
-                  "paper_2508_16105_amd/csrc/device/euler.hip",
-                  "paper_2508_16105_amd/csrc/codegen.cpp",
-                  "paper_2508_16105_amd/csrc/module.cpp",
-                  "paper_2508_16105_amd/csrc/capi.cpp"]
 TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
 
 
-_T_START = time.perf_counter()
-
-
-def progress(msg: str) -> None:
-    """One line on stderr as each part of the run ends (the JSON line alone
-    goes to stdout)."""
-    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
-
-
 def kernel_source_hash(mech_file: str) -> str:
+    """Identity of a mechanism's device code: the complete source the library
+    generates and compiles for it (dumped through CHEM_DUMP_SOURCE while a
+    handle is loaded) plus the file that holds the compile options.  HBM
+    traffic and counters recorded under profiles/ apply only while it is
+    unchanged."""
     import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES + [mech_file]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    import tempfile
+
+    from paper_2508_16105_amd import _lib
+    with tempfile.TemporaryDirectory() as d:
+        dump = os.path.join(d, "source.hip")
+        old = os.environ.get("CHEM_DUMP_SOURCE")
+        os.environ["CHEM_DUMP_SOURCE"] = dump
+        try:
+            h = _lib.load_mechanism_handle(os.path.join(ROOT, mech_file))
+            _lib.lib().chem_free_mechanism(h)
+        finally:
+            if old is None:
+                del os.environ["CHEM_DUMP_SOURCE"]
+            else:
+                os.environ["CHEM_DUMP_SOURCE"] = old
+        with open(dump, "rb") as fh:
+            src = fh.read()
+    hh = hashlib.sha256(src)
+    with open(os.path.join(ROOT, "paper_2508_16105_amd/csrc/module.cpp"), "rb") as fh:
+        hh.update(fh.read())
+    return hh.hexdigest()[:16]
 
 
 def recorded_traffic(mech_file: str):
