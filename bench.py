@@ -24,6 +24,13 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VALU = 78.6e12          # MI355X FP64 vector peak, FLOP/s
 RODAS4_STAGES = 6
 TRAFFIC_PROFILE = "profiles/chem_persistent_rde1m_counters.md"
+_T_START = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr as each part of the run ends (the JSON line alone
+    goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash(mech_file: str) -> str:
