@@ -50,8 +50,7 @@ def lib():
     global _lib
     if _lib is None:
         if not LIB_PATH.exists():
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                              f"python -m paper_2508_16105_amd.build")
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2508_16105_amd.build")
         L = C.CDLL(str(LIB_PATH))
         vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
         L.chem_load_mechanism.argtypes = [C.c_char_p, C.POINTER(vp)]

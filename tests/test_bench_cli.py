@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused(n):
 
 def test_bench_names_resolve():
     """Every global name a bench.py function reads exists at module level or in
-    builtins (the GPU legs only run on the GPU machine, so a missing helper would
+    builtins (the GPU legs run only where a GPU is, so a missing helper would
     otherwise show there first)."""
     import builtins
     import symtable
