@@ -325,9 +325,11 @@ int chem_integrate_batched(const chem_mechanism *m, int nfield, double *const *T
    with respect to each reaction's ln A, b and Ea (J/mol) of the main rate,
    summed over cells in a fixed order (bitwise reproducible).  T_end/Y_end
    (device, both or neither) receive the forward result, bitwise equal to
-   chem_integrate's.  The call first runs a sizing pass, then stores each
-   cell's state every opt->checkpoint_every accepted steps (see chem_options;
-   by default every step whenever memory allows) and recomputes in between;
+   chem_integrate's.  The call first runs a sizing pass (unless
+   opt->adjoint_nacc gives the step counts), then stores each cell's state
+   every opt->checkpoint_every accepted steps (see chem_options; by default
+   every step whenever memory allows) and recomputes in between, keeping what
+   a replayed step's adjoint needs in a per-lane buffer of that many steps;
    it allocates its arena (8 bytes per accepted step plus one state per
    checkpoint per cell, and 24 n_reactions bytes per resident lane) for the
    call and synchronises the stream.  Returns

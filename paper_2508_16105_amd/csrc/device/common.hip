@@ -188,6 +188,10 @@ struct AdjointArgs {
     // other lanes take the positions from gcells on, one cell per lane
     long ngroup;
     long gcells;
+    // nullable: K steps' worth of per-lane stash (one cell per lane form), so
+    // a segment's replay leaves each step's factors and stage vectors for its
+    // adjoint instead of the adjoint forming them again
+    double* stash;
 };
 
 // lanes per group of the grouped adjoint (a power of two >= the RODAS4 stages)

@@ -142,14 +142,29 @@ __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&pi
 }
 
 
+// What one step leaves for its adjoint, per lane and step: the factors of M
+// (N x N, as lu_factor leaves them), the pivot positions, the swap mask, and
+// the stage vectors u_1..u_6.
+struct StashLayout {
+    static constexpr int WORDS = N * N + N + 1 + Rodas4::S * N;
+    __device__ static constexpr int lu(int i, int j) { return i * N + j; }
+    __device__ static constexpr int piv(int a) { return N * N + a; }
+    __device__ static constexpr int swaps() { return N * N + N; }
+    __device__ static constexpr int u(int s, int k) { return N * N + N + 1 + s * N + k; }
+};
+
 // One RODAS4 step from y with step h.  Returns false if the step matrix is
 // singular or anything is not finite; otherwise ynew and the RMS error norm.
 // The stage vectors u_1..u_5 live in LDS (ul[(s*N + k) * ls], one column per
 // lane); the matrix factors, y and the current stage stay in registers.
-__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip,
-                                         const double (&y)[N], double h, double rtol,
-                                         double atol, double (&ynew)[N], double& errn,
-                                         double* __restrict__ ul, int ls)
+// With STASH the step also leaves what its adjoint needs in `stash` (one
+// lane's own words, see StashLayout): the factors of M, the pivots, the swap
+// mask and u_1..u_6, bitwise the values the adjoint would recompute.
+template <bool STASH>
+__device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, double p, double ip,
+                                              const double (&y)[N], double h, double rtol,
+                                              double atol, double (&ynew)[N], double& errn,
+                                              double* __restrict__ ul, int ls, double* __restrict__ stash)
 {
     double M[N][N], f[N];
     mech::rhs_jac(par, p, ip, y, f, M);
@@ -164,10 +179,23 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
     int piv[N];
     bool ok;
     const unsigned swaps = lu_factor(M, piv, ok);
+    if constexpr (STASH) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) stash[StashLayout::lu(i, j)] = M[i][j];
+#pragma unroll
+        for (int a = 0; a < N; ++a) stash[StashLayout::piv(a)] = (double)piv[a];
+        stash[StashLayout::swaps()] = (double)swaps;
+    }
 
     lu_solve(M, piv, swaps, f);
 #pragma unroll
     for (int k = 0; k < N; ++k) ul[k * ls] = f[k];
+    if constexpr (STASH) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) stash[StashLayout::u(0, k)] = f[k];
+    }
     double u[N];
 #pragma unroll
     for (int s = 1; s < Rodas4::S; ++s) {
@@ -196,6 +224,10 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
 #pragma unroll
             for (int k = 0; k < N; ++k) ul[(s * N + k) * ls] = u[k];
         }
+        if constexpr (STASH) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) stash[StashLayout::u(s, k)] = u[k];
+        }
     }
     double acc = 0.0;
 #pragma unroll
@@ -208,6 +240,14 @@ __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double 
     }
     errn = sqrt(acc * (1.0 / N));
     return ok && finite(errn);
+}
+
+__device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip,
+                                         const double (&y)[N], double h, double rtol,
+                                         double atol, double (&ynew)[N], double& errn,
+                                         double* __restrict__ ul, int ls)
+{
+    return ros_step_impl<false>(par, p, ip, y, h, rtol, atol, ynew, errn, ul, ls, nullptr);
 }
 
 // Per-lane integration state.
@@ -621,40 +661,62 @@ __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&
 // jd: -1 for a lane of its own (all six directions), else this lane's place
 // in its group (direction jd; lanes 6 and 7 evaluate a zero direction); only
 // lanes with jd <= 0 add the first-order parameter products.
+// FROM_STASH: the factors, pivots and stage vectors of the step come from
+// what ros_step_impl<true> left for it (the same values, bitwise), and only
+// the stage states are formed again from them.
+template <bool FROM_STASH>
 __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double p, double ip,
                                           const double (&y)[N], double h, double (&lam)[N],
                                           double* __restrict__ gA, double* __restrict__ gb,
-                                          double* __restrict__ gE, int jd)
+                                          double* __restrict__ gE, int jd, const double* __restrict__ stash)
 {
     using chem_math::Dual;
-    double M[N][N], f[N];
-    mech::rhs_jac(par, p, ip, y, f, M);
-    const double hinv = chem_math::recip(h);
-    const double ghinv = hinv * (1.0 / Rodas4::gamma);
-    for (int i = 0; i < N; ++i) {
-        for (int j = 0; j < N; ++j) M[i][j] = -M[i][j];
-        M[i][i] += ghinv;
-    }
+    double M[N][N];
     int piv[N];
-    bool ok;
-    const unsigned swaps = lu_factor(M, piv, ok);
+    unsigned swaps;
+    const double hinv = chem_math::recip(h);
     double u[Rodas4::S][N], Ys[Rodas4::S][N];
-    for (int k = 0; k < N; ++k) { Ys[0][k] = y[k]; u[0][k] = f[k]; }
-    lu_solve(M, piv, swaps, u[0]);
-    for (int s = 1; s < Rodas4::S; ++s) {
-        double acc[N], fs[N];
-        for (int k = 0; k < N; ++k) {
-            double v = y[k], w = 0.0;
-            for (int j = 0; j < s; ++j) {
-                v = fma(RA[s][j], u[j][k], v);
-                w = fma(RC[s][j], u[j][k], w);
+    if constexpr (FROM_STASH) {
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) M[i][j] = stash[StashLayout::lu(i, j)];
+        for (int a = 0; a < N; ++a) piv[a] = (int)stash[StashLayout::piv(a)];
+        swaps = (unsigned)stash[StashLayout::swaps()];
+        for (int s = 0; s < Rodas4::S; ++s)
+            for (int k = 0; k < N; ++k) u[s][k] = stash[StashLayout::u(s, k)];
+        for (int k = 0; k < N; ++k) Ys[0][k] = y[k];
+        for (int s = 1; s < Rodas4::S; ++s)
+            for (int k = 0; k < N; ++k) {
+                double v = y[k];
+                for (int j = 0; j < s; ++j) v = fma(RA[s][j], u[j][k], v);
+                Ys[s][k] = v;
             }
-            Ys[s][k] = v;
-            acc[k] = w;
+    } else {
+        double f[N];
+        mech::rhs_jac(par, p, ip, y, f, M);
+        const double ghinv = hinv * (1.0 / Rodas4::gamma);
+        for (int i = 0; i < N; ++i) {
+            for (int j = 0; j < N; ++j) M[i][j] = -M[i][j];
+            M[i][i] += ghinv;
         }
-        mech::rhs(par, p, ip, Ys[s], fs);
-        for (int k = 0; k < N; ++k) u[s][k] = fma(acc[k], hinv, fs[k]);
-        lu_solve(M, piv, swaps, u[s]);
+        bool ok;
+        swaps = lu_factor(M, piv, ok);
+        for (int k = 0; k < N; ++k) { Ys[0][k] = y[k]; u[0][k] = f[k]; }
+        lu_solve(M, piv, swaps, u[0]);
+        for (int s = 1; s < Rodas4::S; ++s) {
+            double acc[N], fs[N];
+            for (int k = 0; k < N; ++k) {
+                double v = y[k], w = 0.0;
+                for (int j = 0; j < s; ++j) {
+                    v = fma(RA[s][j], u[j][k], v);
+                    w = fma(RC[s][j], u[j][k], w);
+                }
+                Ys[s][k] = v;
+                acc[k] = w;
+            }
+            mech::rhs(par, p, ip, Ys[s], fs);
+            for (int k = 0; k < N; ++k) u[s][k] = fma(acc[k], hinv, fs[k]);
+            lu_solve(M, piv, swaps, u[s]);
+        }
     }
     // reverse over the stages: Ybar_s = J(Y_s)^T w_s and the parameter products
     // in one pass of the generated Jacobian-transpose product
@@ -793,12 +855,29 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
             const int last = min(na, first + a.K) - 1;
             double ys[16][N];                     // the segment's states (K <= 16)
             for (int k = 0; k < N; ++k) ys[0][k] = ck[seg * N + k];
-            for (int i = first; i < last; ++i) {
-                double yn[N], en;
-                ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
-                for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+            if (a.stash) {
+                // replay every step of the segment, leaving each step's factors
+                // and stage vectors for its adjoint in this lane's stash
+                double* st = a.stash + lane * (long)a.K * StashLayout::WORDS;
+                for (int i = first; i <= last; ++i) {
+                    double yn[N], en;
+                    ros_step_impl<true>(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls,
+                                        st + (i - first) * StashLayout::WORDS);
+                    if (i < last)
+                        for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+                }
+                for (int i = last; i >= first; --i)
+                    step_adjoint<true>(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE, jd,
+                                       st + (i - first) * StashLayout::WORDS);
+            } else {
+                for (int i = first; i < last; ++i) {
+                    double yn[N], en;
+                    ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
+                    for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
+                }
+                for (int i = last; i >= first; --i)
+                    step_adjoint<false>(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE, jd, nullptr);
             }
-            for (int i = last; i >= first; --i) step_adjoint(a.par, p, ip, ys[i - first], hs[i], lam, gA, gb, gE, jd);
         }
         if (lead) {
             a.gT0[cell] = lam[0];

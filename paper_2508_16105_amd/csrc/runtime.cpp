@@ -986,8 +986,21 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
     if (int rc = s.alloc(&gpar, (size_t)nslot * 3 * nr, "adjoint parameter partial sums")) return rc;
     HIPCHECK(hipMemcpyAsync(off_d, off.data(), sizeof(long) * off.size(), hipMemcpyHostToDevice, stream),
              "copy offsets");
+    // one cell per lane with checkpoints K > 1 apart: each lane's stash for
+    // the K steps of a segment (see StashLayout), unless it would take more
+    // than an eighth of the free device memory or CHEM_ADJOINT_STASH=0
+    double* stash = nullptr;
+    if (!m->wide && K > 1) {
+        const char* e = std::getenv("CHEM_ADJOINT_STASH");
+        const size_t words = (size_t)n * n + n + 1 + 6 * (size_t)n;
+        const size_t bytes = (size_t)nslot * K * words * sizeof(double);
+        size_t freeb = 0, totalb = 0;
+        HIPCHECK(hipMemGetInfo(&freeb, &totalb), "device memory info");
+        if (!(e && std::atoi(e) == 0) && bytes <= freeb / 8)
+            if (int rc = s.alloc(&stash, (size_t)nslot * K * words, "adjoint stash")) return rc;
+    }
     AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, (long)nslot, T_end, Y_end, off_d,
-                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K, ngroup, gcells};
+                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K, ngroup, gcells, stash};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     const int64_t alanes = m->wide ? nslot * m->layout.G : nslot;
     if (int rc = launch_1d(d->f_adjoint, alanes, 64, &aa, sizeof aa, stream, "chem_adjoint", ashmem)) return rc;

@@ -87,6 +87,7 @@ struct AdjointArgs {
     int K;
     long ngroup;       // lane groups of the one-cell-per-lane adjoint (see kAdjGroup)
     long gcells;       // cells (first positions of the cost order) the groups take
+    double* stash;     // nullable: [nslot][K][stash words] (see StashLayout)
 };
 
 // lanes per group of the grouped one-cell-per-lane adjoint (device: kAdjGroup)

@@ -129,8 +129,10 @@ int main(int argc, char** argv)
         double* gY0 = (double*)calloc(n * ns + 1, sizeof(double));
         double* Te = (double*)calloc(n + 1, sizeof(double));
         double* Ye = (double*)calloc(n * ns + 1, sizeof(double));
+        // the K-step stash of every lane, as the library gives the lane form
+        double* stash = (double*)calloc((size_t)nslot * K * chem::StashLayout::WORDS, sizeof(double));
         g_aa = AdjointArgs{par, T, p, Y, n, gT, gY, gT0, gY0, gpar, nslot, Te, Ye, off, off + n, na_fwd, order,
-                           nullptr, hs, ck, st, na, nj, step, K, 0, 0};
+                           nullptr, hs, ck, st, na, nj, step, K, 0, 0, stash};
         launch_lanes(nslot, [] { chem_adjoint(g_aa); });
         double* gp = (double*)calloc(3 * nr, sizeof(double));
         for (long c = 0; c < nslot; ++c)
