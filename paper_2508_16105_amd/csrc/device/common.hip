@@ -192,6 +192,10 @@ struct AdjointArgs {
     // a segment's replay leaves each step's factors and stage vectors for its
     // adjoint instead of the adjoint forming them again
     double* stash;
+    // nullable, K = 1 only: every accepted step's factors and stage vectors
+    // from the forward rerun, slot off_h[cell] + cell + step (one spare slot
+    // per cell for an attempt past its count)
+    double* trail;
 };
 
 // lanes per group of the grouped adjoint (a power of two >= the RODAS4 stages)

@@ -157,8 +157,8 @@ struct StashLayout {
 // singular or anything is not finite; otherwise ynew and the RMS error norm.
 // The stage vectors u_1..u_5 live in LDS (ul[(s*N + k) * ls], one column per
 // lane); the matrix factors, y and the current stage stay in registers.
-// With STASH the step also leaves what its adjoint needs in `stash` (one
-// lane's own words, see StashLayout): the factors of M, the pivots, the swap
+// With STASH the step also leaves what its adjoint needs in `stash` (see
+// StashLayout; nothing if it is null): the factors of M, the pivots, the swap
 // mask and u_1..u_6, bitwise the values the adjoint would recompute.
 template <bool STASH>
 __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, double p, double ip,
@@ -180,6 +180,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
     bool ok;
     const unsigned swaps = lu_factor(M, piv, ok);
     if constexpr (STASH) {
+        if (stash) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -187,14 +188,16 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
 #pragma unroll
         for (int a = 0; a < N; ++a) stash[StashLayout::piv(a)] = (double)piv[a];
         stash[StashLayout::swaps()] = (double)swaps;
+        }
     }
 
     lu_solve(M, piv, swaps, f);
 #pragma unroll
     for (int k = 0; k < N; ++k) ul[k * ls] = f[k];
     if constexpr (STASH) {
+        if (stash)
 #pragma unroll
-        for (int k = 0; k < N; ++k) stash[StashLayout::u(0, k)] = f[k];
+            for (int k = 0; k < N; ++k) stash[StashLayout::u(0, k)] = f[k];
     }
     double u[N];
 #pragma unroll
@@ -225,8 +228,9 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
             for (int k = 0; k < N; ++k) ul[(s * N + k) * ls] = u[k];
         }
         if constexpr (STASH) {
+            if (stash)
 #pragma unroll
-            for (int k = 0; k < N; ++k) stash[StashLayout::u(s, k)] = u[k];
+                for (int k = 0; k < N; ++k) stash[StashLayout::u(s, k)] = u[k];
         }
     }
     double acc = 0.0;
@@ -282,8 +286,11 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
 // accept if err <= 1; h <- h * clip(0.9 err^-1/4, 0.2, 6), no growth right after
 // a rejection; a rejected or failed step shrinks h by max(0.2, 0.9 err^-1/4)
 // or 0.2; the final step is truncated to land on dt.
+// STASH: the attempt also leaves its step's factors and stage vectors in
+// `stash` (nullable), see ros_step_impl.
+template <bool STASH = false>
 __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
-                                               double* __restrict__ ul, int ls)
+                                               double* __restrict__ ul, int ls, double* __restrict__ stash = nullptr)
 {
     if (c.done) return 0.0;
     if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return 0.0; }
@@ -292,7 +299,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
     double h = c.h;
     if (h >= a.dt - c.t) { h = a.dt - c.t; last = true; }
     double ynew[N], en;
-    const bool ok = ros_step(par, c.p, c.ip, c.y, h, a.rtol, a.atol, ynew, en, ul, ls);
+    const bool ok = ros_step_impl<STASH>(par, c.p, c.ip, c.y, h, a.rtol, a.atol, ynew, en, ul, ls, stash);
     if (ok && en <= 1.0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) c.y[k] = ynew[k];
@@ -825,7 +832,13 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
                     for (int k = 0; k < N; ++k) ck[(c.nacc / a.K) * N + k] = c.y[k];
                 stored = c.nacc;
             }
-            const double hacc = cell_attempt(c, a.par, a.step, ul, ls);
+            // with a trail, the attempt leaves its factors and stage vectors
+            // in the slot of the step it would be (the lanes of a group write
+            // the same values to the same words and each reads back its own)
+            double* slot = a.trail && c.nacc <= cap
+                               ? a.trail + (a.off_h[cell] + cell + c.nacc) * (long)StashLayout::WORDS
+                               : nullptr;
+            const double hacc = cell_attempt<true>(c, a.par, a.step, ul, ls, slot);
             if (hacc > 0.0) {
                 if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
                 if (lead) hs[c.nacc - 1] = hacc;
@@ -855,7 +868,12 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
             const int last = min(na, first + a.K) - 1;
             double ys[16][N];                     // the segment's states (K <= 16)
             for (int k = 0; k < N; ++k) ys[0][k] = ck[seg * N + k];
-            if (a.stash) {
+            if (a.trail) {
+                // checkpoints at every step (K = 1): the forward rerun left each
+                // step's factors and stage vectors in the trail
+                step_adjoint<true>(a.par, p, ip, ys[0], hs[first], lam, gA, gb, gE, jd,
+                                   a.trail + (a.off_h[cell] + cell + first) * (long)StashLayout::WORDS);
+            } else if (a.stash) {
                 // replay every step of the segment, leaving each step's factors
                 // and stage vectors for its adjoint in this lane's stash
                 double* st = a.stash + lane * (long)a.K * StashLayout::WORDS;

@@ -999,8 +999,21 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         if (!(e && std::atoi(e) == 0) && bytes <= freeb / 8)
             if (int rc = s.alloc(&stash, (size_t)nslot * K * words, "adjoint stash")) return rc;
     }
+    // checkpoints at every step: the forward rerun keeps every step's factors
+    // and stage vectors (a trail), so the reverse sweep forms none of them
+    // again, if that fits an eighth of the free device memory
+    double* trail = nullptr;
+    if (!m->wide && K == 1) {
+        const char* e = std::getenv("CHEM_ADJOINT_STASH");
+        const size_t words = (size_t)n * n + n + 1 + 6 * (size_t)n;
+        const size_t slots = (size_t)th + (size_t)ncell;
+        size_t freeb = 0, totalb = 0;
+        HIPCHECK(hipMemGetInfo(&freeb, &totalb), "device memory info");
+        if (!(e && std::atoi(e) == 0) && slots * words * sizeof(double) <= freeb / 8)
+            if (int rc = s.alloc(&trail, slots * words, "adjoint trail")) return rc;
+    }
     AdjointArgs aa{d->par, T0, p, Y0, (long)ncell, gT, gY, gT0, gY0, gpar, (long)nslot, T_end, Y_end, off_d,
-                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K, ngroup, gcells, stash};
+                   off_d + ncell, na_fwd, order_d, o.h0, hs, ck, st, na, nj, step, K, ngroup, gcells, stash, trail};
     HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     const int64_t alanes = m->wide ? nslot * m->layout.G : nslot;
     if (int rc = launch_1d(d->f_adjoint, alanes, 64, &aa, sizeof aa, stream, "chem_adjoint", ashmem)) return rc;

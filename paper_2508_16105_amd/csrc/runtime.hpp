@@ -88,6 +88,7 @@ struct AdjointArgs {
     long ngroup;       // lane groups of the one-cell-per-lane adjoint (see kAdjGroup)
     long gcells;       // cells (first positions of the cost order) the groups take
     double* stash;     // nullable: [nslot][K][stash words] (see StashLayout)
+    double* trail;     // nullable, K = 1: [accepted steps + ncell][stash words]
 };
 
 // lanes per group of the grouped one-cell-per-lane adjoint (device: kAdjGroup)

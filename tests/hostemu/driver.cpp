@@ -99,7 +99,8 @@ int main(int argc, char** argv)
     } else if (mode == 3) {
         double* gT = rd<double>(in, n);
         double* gY = rd<double>(in, n * ns);
-        const int K = 4;
+        // checkpoint interval: 4, or EMU_ADJ_K (1 runs the trail path)
+        const int K = getenv("EMU_ADJ_K") ? atoi(getenv("EMU_ADJ_K")) : 4;
         // sizing pass: the plain kernel on copies gives every cell's accepted steps
         double* Tw = (double*)malloc(sizeof(double) * n);
         double* Yw = (double*)malloc(sizeof(double) * n * ns);
@@ -129,10 +130,12 @@ int main(int argc, char** argv)
         double* gY0 = (double*)calloc(n * ns + 1, sizeof(double));
         double* Te = (double*)calloc(n + 1, sizeof(double));
         double* Ye = (double*)calloc(n * ns + 1, sizeof(double));
-        // the K-step stash of every lane, as the library gives the lane form
-        double* stash = (double*)calloc((size_t)nslot * K * chem::StashLayout::WORDS, sizeof(double));
+        // the K-step stash of every lane (K > 1) or the trail of every step
+        // (K = 1), as the library gives the lane form
+        double* stash = K > 1 ? (double*)calloc((size_t)nslot * K * chem::StashLayout::WORDS, sizeof(double)) : nullptr;
+        double* trail = K == 1 ? (double*)calloc((size_t)(th + n) * chem::StashLayout::WORDS, sizeof(double)) : nullptr;
         g_aa = AdjointArgs{par, T, p, Y, n, gT, gY, gT0, gY0, gpar, nslot, Te, Ye, off, off + n, na_fwd, order,
-                           nullptr, hs, ck, st, na, nj, step, K, 0, 0, stash};
+                           nullptr, hs, ck, st, na, nj, step, K, 0, 0, stash, trail};
         launch_lanes(nslot, [] { chem_adjoint(g_aa); });
         double* gp = (double*)calloc(3 * nr, sizeof(double));
         for (long c = 0; c < nslot; ++c)

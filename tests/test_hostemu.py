@@ -151,9 +151,13 @@ def test_adjoint_clean_and_matches_oracle(drivers, oracle_lib, name):
     gY = rng.standard_normal((n, ns))
     dt, rtol, atol = 1e-8, 1e-8, 1e-12
     outs = {tag: hb.run(exes[(name, tag)], wd, 3, par, T, p, Y, dt, rtol, atol, gT, gY) for tag in BUILDS}
+    # checkpoints at every step: the reverse sweep reads the forward rerun's
+    # trail instead of the segment replay's stash; bitwise the same
+    trail = hb.run(exes[(name, "pattern")], wd, 3, par, T, p, Y, dt, rtol, atol, gT, gY, env={"EMU_ADJ_K": "1"})
     for k in ("gT0", "gY0", "gpar"):
         assert np.array_equal(outs["pattern"][k], outs["zero"][k]), k
         assert np.array_equal(outs["pattern"][k], outs["msan"][k]), k
+        assert np.array_equal(outs["pattern"][k], trail[k], equal_nan=True), k
     o = outs["pattern"]
     om = oracle_lib.Mechanism(mech_path(name))
     oT0, oY0, oa, ob, oe = om.adjoint(T, p, Y, dt, rtol, atol, gT, gY)
