@@ -38,6 +38,20 @@ constexpr int NACT = mech::NACT;
 
 __device__ __forceinline__ constexpr int P(int a) { return mech::PERM[a]; }
 
+// ---- per-lane LDS: the RODAS4 stage vectors u_1..u_5 ----
+// A workgroup's dynamic LDS holds, for each of its waves, 5 N doubles per
+// lane, lane-interleaved: word w of lane l at w * 64 + l (u_s component k is
+// word s N + k).  The 64 lanes of a wave touch 64 consecutive doubles (no
+// bank conflicts) and every word sits at a compile-time offset from the
+// lane's base, whatever the workgroup size.
+constexpr int kLaneWords = 5 * N;
+constexpr int kLaneStride = 64;
+
+__device__ __forceinline__ double* lane_lds(double* lds)
+{
+    return lds + (threadIdx.x / kLaneStride) * (kLaneStride * kLaneWords) + threadIdx.x % kLaneStride;
+}
+
 __device__ __forceinline__ unsigned lu_factor(double (&A)[N][N], int (&piv)[N], bool& ok)
 {
     unsigned swaps = 0u;
@@ -155,8 +169,8 @@ struct StashLayout {
 
 // One RODAS4 step from y with step h.  Returns false if the step matrix is
 // singular or anything is not finite; otherwise ynew and the RMS error norm.
-// The stage vectors u_1..u_5 live in LDS (ul[(s*N + k) * ls], one column per
-// lane); the matrix factors, y and the current stage stay in registers.
+// The stage vectors u_1..u_5 live in the lane's LDS words ul (lane_lds); the
+// matrix factors, y and the current stage stay in registers.
 // With STASH the step also leaves what its adjoint needs in `stash` (see
 // StashLayout; nothing if it is null): the factors of M, the pivots, the swap
 // mask and u_1..u_6, bitwise the values the adjoint would recompute.
@@ -164,7 +178,7 @@ template <bool STASH>
 __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, double p, double ip,
                                               const double (&y)[N], double h, double rtol,
                                               double atol, double (&ynew)[N], double& errn,
-                                              double* __restrict__ ul, int ls, double* __restrict__ stash)
+                                              double* __restrict__ ul, double* __restrict__ stash)
 {
     double M[N][N], f[N];
     mech::rhs_jac(par, p, ip, y, f, M);
@@ -193,7 +207,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
 
     lu_solve(M, piv, swaps, f);
 #pragma unroll
-    for (int k = 0; k < N; ++k) ul[k * ls] = f[k];
+    for (int k = 0; k < N; ++k) ul[k * kLaneStride] = f[k];
     if constexpr (STASH) {
         if (stash)
 #pragma unroll
@@ -208,7 +222,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
             double v = y[k], w = 0.0;
 #pragma unroll
             for (int j = 0; j < s; ++j) {
-                const double uj = ul[(j * N + k) * ls];
+                const double uj = ul[(j * N + k) * kLaneStride];
                 v = fma(RA[s][j], uj, v);
                 w = fma(RC[s][j], uj, w);
             }
@@ -225,7 +239,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
         lu_solve(M, piv, swaps, u);
         if (s < Rodas4::S - 1) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) ul[(s * N + k) * ls] = u[k];
+            for (int k = 0; k < N; ++k) ul[(s * N + k) * kLaneStride] = u[k];
         }
         if constexpr (STASH) {
             if (stash)
@@ -249,9 +263,9 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
 __device__ __forceinline__ bool ros_step(const double* __restrict__ par, double p, double ip,
                                          const double (&y)[N], double h, double rtol,
                                          double atol, double (&ynew)[N], double& errn,
-                                         double* __restrict__ ul, int ls)
+                                         double* __restrict__ ul)
 {
-    return ros_step_impl<false>(par, p, ip, y, h, rtol, atol, ynew, errn, ul, ls, nullptr);
+    return ros_step_impl<false>(par, p, ip, y, h, rtol, atol, ynew, errn, ul, nullptr);
 }
 
 // Per-lane integration state.
@@ -290,7 +304,7 @@ __device__ __forceinline__ void cell_begin(Cell& c, double T, double p, const do
 // `stash` (nullable), see ros_step_impl.
 template <bool STASH = false>
 __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict__ par, const StepArgs& a,
-                                               double* __restrict__ ul, int ls, double* __restrict__ stash = nullptr)
+                                               double* __restrict__ ul, double* __restrict__ stash = nullptr)
 {
     if (c.done) return 0.0;
     if (c.nacc + c.nrej >= a.max_substeps) { c.status = CELL_MAXSTEPS; c.done = true; return 0.0; }
@@ -299,7 +313,7 @@ __device__ __forceinline__ double cell_attempt(Cell& c, const double* __restrict
     double h = c.h;
     if (h >= a.dt - c.t) { h = a.dt - c.t; last = true; }
     double ynew[N], en;
-    const bool ok = ros_step_impl<STASH>(par, c.p, c.ip, c.y, h, a.rtol, a.atol, ynew, en, ul, ls, stash);
+    const bool ok = ros_step_impl<STASH>(par, c.p, c.ip, c.y, h, a.rtol, a.atol, ynew, en, ul, stash);
     if (ok && en <= 1.0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) c.y[k] = ynew[k];
@@ -344,7 +358,8 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_plain(chem::IntegrateAr
     extern __shared__ double lds[];
     Cell c;
     cell_begin(c, a.T[cell], a.p[cell], a.Y + cell * NS, 1, a.h0 ? a.h0[cell] : a.step.dt);
-    while (!c.done) cell_attempt(c, a.par, a.step, lds + threadIdx.x, blockDim.x);
+    double* const ul = lane_lds(lds);
+    while (!c.done) cell_attempt(c, a.par, a.step, ul);
     cell_store(c, a.T, a.Y, cell, a.status, a.nacc, a.nrej);
 }
 
@@ -399,8 +414,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_fixed_step(FixedStepArg
 #pragma unroll
     for (int k = 0; k < NS; ++k) y[1 + k] = a.Y[cell * NS + k];
     const double p = a.p[cell];
-    const bool ok = ros_step(a.par, p, 1.0 / p, y, a.h, a.rtol, a.atol, yn, en, lds + threadIdx.x,
-                             blockDim.x);
+    const bool ok = ros_step(a.par, p, 1.0 / p, y, a.h, a.rtol, a.atol, yn, en, lane_lds(lds));
 #pragma unroll
     for (int k = 0; k < N; ++k) a.ynew[cell * N + k] = yn[k];
     a.err[cell] = en;
@@ -512,6 +526,7 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
 {
     using namespace chem;
     extern __shared__ double lds[];
+    double* const ul = lane_lds(lds);
     const int lane = threadIdx.x & 63;
     const long total = blk->total;
     const int nq = blk->nq;
@@ -571,7 +586,7 @@ __device__ __forceinline__ void persistent_body(const PersistBlock* __restrict__
             continue;
         }
         if (have) {
-            cell_attempt(c, par, step, lds + threadIdx.x, blockDim.x);
+            cell_attempt(c, par, step, ul);
             if (c.done) {
                 const FieldDesc& fd = blk->fields[fidx];
                 cell_store(c, fd.T, fd.Y, local, fd.status, fd.nacc, fd.nrej);
@@ -798,8 +813,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
     const long lane = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (lane >= a.nslot) return;
     extern __shared__ double lds[];
-    double* ul = lds + threadIdx.x;
-    const int ls = blockDim.x;
+    double* const ul = lane_lds(lds);
     double gA[mech::NR], gb[mech::NR], gE[mech::NR];
     for (int j = 0; j < mech::NR; ++j) { gA[j] = 0.0; gb[j] = 0.0; gE[j] = 0.0; }
     const long glanes = (long)kAdjGroup * a.ngroup;
@@ -838,7 +852,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
             double* slot = a.trail && c.nacc <= cap
                                ? a.trail + (a.off_h[cell] + cell + c.nacc) * (long)StashLayout::WORDS
                                : nullptr;
-            const double hacc = cell_attempt<true>(c, a.par, a.step, ul, ls, slot);
+            const double hacc = cell_attempt<true>(c, a.par, a.step, ul, slot);
             if (hacc > 0.0) {
                 if (c.nacc > cap) { c.status = CELL_NONFINITE; c.done = true; break; }
                 if (lead) hs[c.nacc - 1] = hacc;
@@ -879,7 +893,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
                 double* st = a.stash + lane * (long)a.K * StashLayout::WORDS;
                 for (int i = first; i <= last; ++i) {
                     double yn[N], en;
-                    ros_step_impl<true>(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls,
+                    ros_step_impl<true>(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul,
                                         st + (i - first) * StashLayout::WORDS);
                     if (i < last)
                         for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
@@ -890,7 +904,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) chem_adjoint(AdjointArgs a)
             } else {
                 for (int i = first; i < last; ++i) {
                     double yn[N], en;
-                    ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul, ls);
+                    ros_step(a.par, p, ip, ys[i - first], hs[i], a.step.rtol, a.step.atol, yn, en, ul);
                     for (int k = 0; k < N; ++k) ys[i - first + 1][k] = yn[k];
                 }
                 for (int i = last; i >= first; --i)

@@ -45,6 +45,9 @@ def host_source(text: str) -> str:
     text = text.replace('asm("v_cvt_i32_f64 %0, %1" : "=v"(n) : "v"(nd));', "n = emu_cvt_i32_sat(nd);")
     text = text.replace("__attribute__((address_space(4)))", "")
     text = text.replace("extern __shared__ double lds[];", "double* lds = emu_lds;")
+    # one lane per workgroup: the lane's LDS words are consecutive
+    assert "constexpr int kLaneStride = 64;" in text
+    text = text.replace("constexpr int kLaneStride = 64;", "constexpr int kLaneStride = 1;")
     assert "asm" not in re.sub(r"//.*", "", text).replace("__asm", ""), "unhandled inline asm"
     return text
 
