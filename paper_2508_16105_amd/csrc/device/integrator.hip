@@ -120,6 +120,15 @@ __device__ __forceinline__ int opaque_index(int p)
     return p;
 }
 
+// A wave-uniform value passed through an empty asm at each use, so that the
+// tests of its bits are made where they are needed (scalar instructions)
+// rather than once per step as lane masks that live across all six solves.
+__device__ __forceinline__ unsigned opaque_uniform(unsigned x)
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
                                          double (&b)[N])
 {
@@ -192,7 +201,9 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
     }
     int piv[N];
     bool ok;
-    const unsigned swaps = lu_factor(M, piv, ok);
+    // the swap mask is the same in every active lane (lu_factor builds it from
+    // __any), so it is read into a scalar register once
+    const unsigned swaps = __builtin_amdgcn_readfirstlane(lu_factor(M, piv, ok));
     if constexpr (STASH) {
         if (stash) {
 #pragma unroll
@@ -205,7 +216,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
         }
     }
 
-    lu_solve(M, piv, swaps, f);
+    lu_solve(M, piv, opaque_uniform(swaps), f);
 #pragma unroll
     for (int k = 0; k < N; ++k) ul[k * kLaneStride] = f[k];
     if constexpr (STASH) {
@@ -236,7 +247,7 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
         mech::rhs(par, p, ip, Ys, u);
 #pragma unroll
         for (int k = 0; k < N; ++k) u[k] = fma(acc[k], hinv, u[k]);
-        lu_solve(M, piv, swaps, u);
+        lu_solve(M, piv, opaque_uniform(swaps), u);
         if (s < Rodas4::S - 1) {
 #pragma unroll
             for (int k = 0; k < N; ++k) ul[(s * N + k) * kLaneStride] = u[k];
