@@ -353,9 +353,10 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
 #pragma unroll
         for (int k = 0; k < NS; ++k) Y[cell * NS + k] = c.y[1 + k];
     }
-    status[cell] = c.status;
-    nacc[cell] = c.nacc;
-    nrej[cell] = c.nrej;
+    // the per-cell counters only where someone reads them (null: not asked for)
+    if (status) status[cell] = c.status;
+    if (nacc) nacc[cell] = c.nacc;
+    if (nrej) nrej[cell] = c.nrej;
 }
 
 }  // namespace chem

@@ -785,10 +785,10 @@ __device__ __forceinline__ void cell_store(const Cell& c, double* __restrict__ T
         if (i == 0) T[cell] = c.y;
         else if (i <= NS) Y[cell * NS + i - 1] = c.y;
     }
-    if (i == 0) {
-        status[cell] = c.status;
-        nacc[cell] = c.nacc;
-        nrej[cell] = c.nrej;
+    if (i == 0) {   // the per-cell counters only where someone reads them (null: not asked for)
+        if (status) status[cell] = c.status;
+        if (nacc) nacc[cell] = c.nacc;
+        if (nrej) nrej[cell] = c.nrej;
     }
 }
 

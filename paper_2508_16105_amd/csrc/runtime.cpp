@@ -236,12 +236,13 @@ int run_plain(chem_mechanism* m, int64_t ncell, double* T, const double* p, doub
 {
     DeviceState* d;
     if (int rc = device_state(m, stream, &d)) return rc;
-    // per-cell counters the caller did not ask for go to the workspace
-    if (!status || !nacc || !nrej)
+    // per-cell counters the caller did not ask for go to the workspace when the
+    // statistics need them, and are not written otherwise
+    if (stats && (!status || !nacc || !nrej))
         if (int rc = grow(&d->cells_i32, &d->cells_cap, 3 * (size_t)ncell, "workspace")) return rc;
-    int32_t* st = status ? status : d->cells_i32;
-    int32_t* na = nacc ? nacc : d->cells_i32 + ncell;
-    int32_t* nr = nrej ? nrej : d->cells_i32 + 2 * ncell;
+    int32_t* st = status ? status : stats ? d->cells_i32 : nullptr;
+    int32_t* na = nacc ? nacc : stats ? d->cells_i32 + ncell : nullptr;
+    int32_t* nr = nrej ? nrej : stats ? d->cells_i32 + 2 * ncell : nullptr;
     IntegrateArgs a{d->par, T, p, Y, (long)ncell, o.h0, st, na, nr, step_args(dt, rtol, atol, o)};
     if (stats) HIPCHECK(hipEventRecord(d->ev0, stream), "event");
     // one lane per cell, or one group of G lanes per cell in the wave-cooperative form
@@ -333,8 +334,10 @@ int launch_graph(DeviceState& d, const LaunchConfig& c, hipStream_t stream)
     return 0;
 }
 
+// counts: the launch's statistics are wanted, so the per-cell counters the
+// caller did not ask for go to the workspace; otherwise they are not written.
 int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<FieldDesc>& out,
-                int64_t& total)
+                int64_t& total, bool counts)
 {
     total = 0;
     for (int f = 0; f < nfield; ++f) total += fv[f].ncell;
@@ -349,9 +352,9 @@ int fill_fields(DeviceState& d, const FieldView* fv, int nfield, std::vector<Fie
         x.T = fv[f].T;
         x.p = fv[f].p;
         x.Y = fv[f].Y;
-        x.status = fv[f].status ? fv[f].status : d.cells_i32 + start;
-        x.nacc = fv[f].nacc ? fv[f].nacc : d.cells_i32 + total + start;
-        x.nrej = fv[f].nrej ? fv[f].nrej : d.cells_i32 + 2 * total + start;
+        x.status = fv[f].status ? fv[f].status : counts ? d.cells_i32 + start : nullptr;
+        x.nacc = fv[f].nacc ? fv[f].nacc : counts ? d.cells_i32 + total + start : nullptr;
+        x.nrej = fv[f].nrej ? fv[f].nrej : counts ? d.cells_i32 + 2 * total + start : nullptr;
         x.cost = fv[f].cost;
         x.ncell = (long)fv[f].ncell;
         x.start = (long)start;
@@ -554,7 +557,7 @@ int run_persistent_wide(chem_mechanism* m, const FieldView* fv, int nfield, doub
         if (fv[f].h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the persistent form");
     std::vector<FieldDesc> fields;
     int64_t total = 0;
-    if (int rc = fill_fields(*d, fv, nfield, fields, total)) return rc;
+    if (int rc = fill_fields(*d, fv, nfield, fields, total, stats != nullptr)) return rc;
     const StepArgs s = step_args(dt, rtol, atol, o);
     LaunchConfig c{64, 1, 1};
     if (int rc = write_block(*d, fields, header_for(*d, total, nfield, c, s, CHEM_ORDER_NATURAL), stream)) return rc;
@@ -595,7 +598,7 @@ int run_persistent(chem_mechanism* m, const FieldView* fv, int nfield, double dt
         if (fv[f].h0) return set_error(CHEM_E_INVAL, "h0 is not supported by the persistent form");
     std::vector<FieldDesc> fields;
     int64_t total = 0;
-    if (int rc = fill_fields(*d, fv, nfield, fields, total)) return rc;
+    if (int rc = fill_fields(*d, fv, nfield, fields, total, stats != nullptr)) return rc;
     const StepArgs s = step_args(dt, rtol, atol, o);
     LaunchConfig c;
     int order = o.order;
