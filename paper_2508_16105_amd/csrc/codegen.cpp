@@ -604,9 +604,9 @@ struct Emitter {
                 if (falloff) o << "    const S qA = q * (Pr * ipr1 - dF_dPr);\n";
                 else o << "    const S qA = q;\n";
                 o << "    const S g = wsum * qA;\n"
-                     "    chem_math::param_acc(gA[" << j << "], g, gsc);\n"
-                     "    chem_math::param_acc(gb[" << j << "], g * lnT, gsc);\n"
-                     "    chem_math::param_acc(gE[" << j << "], g * (-iT * " << lit(1.0 / kRu) << "), gsc);\n  }\n";
+                     "    chem_math::param_acc(gA[" << j << " * GS], g, gsc);\n"
+                     "    chem_math::param_acc(gb[" << j << " * GS], g * lnT, gsc);\n"
+                     "    chem_math::param_acc(gE[" << j << " * GS], g * (-iT * " << lit(1.0 / kRu) << "), gsc);\n  }\n";
                 return;
             }
             for (int k = 0; k < ns; ++k) {
@@ -755,8 +755,9 @@ struct Emitter {
         // SwY = sum_j wY_j s_j, HS = sum_j hs_j s_j, wYT = sum_j wY_j dq_j/dT,
         // HwT = sum_j hs_j dq_j/dT, s_j = sum_m dq_j/dC_m C_m.
         // (the parameter products go to double accumulators, scaled by gsc; for
-        // a dual S only their tangent is added, see chem_math::param_acc)
-        o << "template <class S>\n__device__ __forceinline__ void jtv_param(const double* __restrict__ par, double p, "
+        // a dual S only their tangent is added, see chem_math::param_acc; GS is
+        // the accumulators' element stride)
+        o << "template <class S, int GS = 1>\n__device__ __forceinline__ void jtv_param(const double* __restrict__ par, double p, "
              "double ip, const S (&y)[N], const double (&w)[N], S (&v)[N], double* __restrict__ gA, "
              "double* __restrict__ gb, double* __restrict__ gE, double gsc)\n{\n";
         prologue(true);

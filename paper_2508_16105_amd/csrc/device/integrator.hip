@@ -698,6 +698,16 @@ __device__ __forceinline__ void lu_solve_t(const double (&A)[N][N], const int (&
 // FROM_STASH: the factors, pivots and stage vectors of the step come from
 // what ros_step_impl<true> left for it (the same values, bitwise), and only
 // the stage states are formed again from them.
+// gA, gb, gE: the lane's parameter-gradient accumulators (private memory).
+// While the step runs they are held in the lane's LDS words instead, when the
+// 3 NR of them fit (kAdjParamsInLds): the step's dozen Jacobian-transpose
+// products each add to all of them, and a read-modify-write of private memory
+// waits on the cache hierarchy while one of LDS does not; the caller launches
+// the adjoint with that much LDS per lane (max(5 N, 3 NR) words), and the
+// stage-vector words are free during a step adjoint.
+constexpr bool kAdjParamsInLds = 3 * mech::NR <= 80;
+constexpr int kAdjParamStride = kAdjParamsInLds ? kLaneStride : 1;
+
 template <bool FROM_STASH>
 __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double p, double ip,
                                           const double (&y)[N], double h, double (&lam)[N],
@@ -752,6 +762,19 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
             lu_solve(M, piv, swaps, u[s]);
         }
     }
+    double *qA = gA, *qb = gb, *qE = gE;
+    if constexpr (kAdjParamsInLds) {
+        extern __shared__ double lds[];
+        double* const gl = lane_lds(lds);
+        qA = gl;
+        qb = gl + mech::NR * kAdjParamStride;
+        qE = gl + 2 * mech::NR * kAdjParamStride;
+        for (int j = 0; j < mech::NR; ++j) {
+            qA[j * kAdjParamStride] = gA[j];
+            qb[j * kAdjParamStride] = gb[j];
+            qE[j * kAdjParamStride] = gE[j];
+        }
+    }
     // reverse over the stages: Ybar_s = J(Y_s)^T w_s and the parameter products
     // in one pass of the generated Jacobian-transpose product
     const double mw[Rodas4::S] = {RA[5][0], RA[5][1], RA[5][2], RA[5][3], 1.0, 1.0};
@@ -765,7 +788,7 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
         for (int k = 0; k < N; ++k) w[s][k] = ub[s][k];
         lu_solve_t(M, piv, swaps, w[s]);
         double Yb[N];
-        mech::jtv_param(par, p, ip, Ys[s], w[s], Yb, gA, gb, gE, gsc);
+        mech::jtv_param<double, kAdjParamStride>(par, p, ip, Ys[s], w[s], Yb, qA, qb, qE, gsc);
         for (int k = 0; k < N; ++k) yb[k] += Yb[k];
         for (int j = 0; j < s; ++j)
             for (int k = 0; k < N; ++k) ub[j][k] = fma(RA[s][j], Yb[k], fma(RC[s][j] * hinv, w[s][k], ub[j][k]));
@@ -794,7 +817,7 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
                 wd[k] = ws;
             }
         }
-        mech::jtv_param(par, p, ip, yd, wd, vd, gA, gb, gE, 1.0);
+        mech::jtv_param<Dual, kAdjParamStride>(par, p, ip, yd, wd, vd, qA, qb, qE, 1.0);
         for (int k = 0; k < N; ++k) sec[k] += vd[k].d;
     }
     if (jd >= 0) {
@@ -805,6 +828,13 @@ __device__ __noinline__ void step_adjoint(const double* __restrict__ par, double
             for (int k = 0; k < N; ++k) sec[k] += __shfl_xor(sec[k], m, kAdjGroup);
     }
     for (int k = 0; k < N; ++k) lam[k] = yb[k] + sec[k];
+    if constexpr (kAdjParamsInLds) {
+        for (int j = 0; j < mech::NR; ++j) {
+            gA[j] = qA[j * kAdjParamStride];
+            gb[j] = qb[j * kAdjParamStride];
+            gE[j] = qE[j * kAdjParamStride];
+        }
+    }
 }
 
 }  // namespace chem

@@ -957,7 +957,11 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         const int64_t waves_per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (160 * 1024) / std::max(1u, ashmem)));
         nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * waves_per_cu * m->layout.cells_per_wave());
     } else {
-        ashmem = d->stage_lds(64);
+        // the stage vectors (5 n doubles a lane), and during a step adjoint the
+        // 3 nr parameter accumulators when they fit 80 doubles a lane (the
+        // device code's kAdjParamsInLds)
+        const int words = std::max(5 * n, 3 * nr <= 80 ? 3 * nr : 0);
+        ashmem = (unsigned)(64 * words * sizeof(double));
         nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * 4 * 64);
     }
     // One cell per lane: the most expensive cells (those within a fraction of

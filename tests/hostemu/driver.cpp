@@ -34,11 +34,13 @@ template <class T> static void wr(FILE* f, const T* p, size_t n)
 }
 
 // one lane per workgroup; the LDS of one lane is what the library gives it:
-// the stage vectors u_1..u_5, 5 N doubles (an exact heap block, so the
-// address sanitizer sees any access beyond it)
-static void launch_lanes(long n, void (*body)())
+// the stage vectors u_1..u_5, 5 N doubles, or in the adjoint the 3 NR
+// parameter accumulators if they fit 80 doubles and are more (an exact heap
+// block, so the address sanitizer sees any access beyond it)
+static void launch_lanes(long n, void (*body)(), bool adjoint = false)
 {
-    double* lds = (double*)malloc(sizeof(double) * 5 * mech::N);
+    const int words = adjoint && 3 * mech::NR <= 80 && 3 * mech::NR > 5 * mech::N ? 3 * mech::NR : 5 * mech::N;
+    double* lds = (double*)malloc(sizeof(double) * words);
     emu_lds = lds;
     blockDim = {1, 1, 1};
     threadIdx = {0, 0, 0};
@@ -136,7 +138,7 @@ int main(int argc, char** argv)
         double* trail = K == 1 ? (double*)calloc((size_t)(th + n) * chem::StashLayout::WORDS, sizeof(double)) : nullptr;
         g_aa = AdjointArgs{par, T, p, Y, n, gT, gY, gT0, gY0, gpar, nslot, Te, Ye, off, off + n, na_fwd, order,
                            nullptr, hs, ck, st, na, nj, step, K, 0, 0, stash, trail};
-        launch_lanes(nslot, [] { chem_adjoint(g_aa); });
+        launch_lanes(nslot, [] { chem_adjoint(g_aa); }, true);
         double* gp = (double*)calloc(3 * nr, sizeof(double));
         for (long c = 0; c < nslot; ++c)
             for (int j = 0; j < 3 * nr; ++j) gp[j] += gpar[c * 3 * nr + j];
