@@ -38,18 +38,67 @@ constexpr int NACT = mech::NACT;
 
 __device__ __forceinline__ constexpr int P(int a) { return mech::PERM[a]; }
 
-// ---- per-lane LDS: the RODAS4 stage vectors u_1..u_5 ----
-// A workgroup's dynamic LDS holds, for each of its waves, 5 N doubles per
-// lane, lane-interleaved: word w of lane l at w * 64 + l (u_s component k is
-// word s N + k).  The 64 lanes of a wave touch 64 consecutive doubles (no
-// bank conflicts) and every word sits at a compile-time offset from the
-// lane's base, whatever the workgroup size.
-constexpr int kLaneWords = 5 * N;
+// ---- per-lane LDS ----
+// A workgroup's dynamic LDS holds, for each of its waves, kLaneWords doubles
+// per lane, lane-interleaved: word w of lane l at w * 64 + l.  The 64 lanes
+// of a wave touch 64 consecutive doubles (no bank conflicts) and every word
+// sits at a compile-time offset from the lane's base, whatever the workgroup
+// size.  The words hold the RODAS4 stage vectors u_1..u_5 (u_s component k
+// at word s N + k), or, when the step matrix's factors do not fit the lane's
+// registers (kFactorsInLds), the first factor entries in the order the solves
+// read them, the stage vectors then going to private memory.
 constexpr int kLaneStride = 64;
+// entries of the LU factors the solves read: L below the diagonal of the
+// first NACT positions, and per position a its diagonal and min(a, NACT) of U
+constexpr int kFactorEntries = NACT * (NACT - 1) / 2 + N + (NACT * (NACT - 1)) / 2 + (N - NACT) * NACT;
+constexpr bool kFactorsInLds = N >= 12;
+constexpr int kLdsBudget = 80;     // doubles a lane: 160 KB over four 64-lane waves
+constexpr int kFactorsLds = kFactorsInLds ? (kFactorEntries < kLdsBudget ? kFactorEntries : kLdsBudget) : 0;
+constexpr int kLaneWords = kFactorsInLds ? kFactorsLds : 5 * N;
 
 __device__ __forceinline__ double* lane_lds(double* lds)
 {
     return lds + (threadIdx.x / kLaneStride) * (kLaneStride * kLaneWords) + threadIdx.x % kLaneStride;
+}
+
+// slot[i][j]: the LDS word of factor entry (i, j), or -1 if it stays in registers
+struct FactorSlots {
+    int slot[N][N];
+};
+
+__host__ __device__ constexpr FactorSlots factor_slots(int count)
+{
+    FactorSlots m{};
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) m.slot[i][j] = -1;
+    int s = 0;
+    for (int a = 0; a < NACT; ++a)                 // forward substitution: L by columns
+        for (int c = a + 1; c < NACT; ++c) {
+            if (s < count) m.slot[mech::PERM[c]][mech::PERM[a]] = s;
+            ++s;
+        }
+    for (int a = N - 1; a >= 0; --a) {             // back substitution: U by columns
+        const int k = mech::PERM[a];
+        if (s < count) m.slot[k][k] = s;
+        ++s;
+        for (int c = 0; c < (a < NACT ? a : NACT); ++c) {
+            if (s < count) m.slot[mech::PERM[c]][k] = s;
+            ++s;
+        }
+    }
+    return m;
+}
+
+__device__ constexpr FactorSlots kFactorSlots = factor_slots(kFactorsLds);
+
+// factor entry (i, j): from the lane's LDS words if FL and it has a slot there
+template <bool FL>
+__device__ __forceinline__ double factor(const double (&A)[N][N], const double* __restrict__ fl, int i, int j)
+{
+    if constexpr (FL) {
+        if (kFactorSlots.slot[i][j] >= 0) return fl[kFactorSlots.slot[i][j] * kLaneStride];
+    }
+    return A[i][j];
 }
 
 __device__ __forceinline__ unsigned lu_factor(double (&A)[N][N], int (&piv)[N], bool& ok)
@@ -129,8 +178,10 @@ __device__ __forceinline__ unsigned opaque_uniform(unsigned x)
     return x;
 }
 
+// FL: the factor entries with an LDS slot are read from the lane's words fl.
+template <bool FL = false>
 __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&piv)[N], unsigned swaps,
-                                         double (&b)[N])
+                                         double (&b)[N], const double* __restrict__ fl = nullptr)
 {
 #pragma unroll
     for (int a = 0; a < NACT; ++a) {
@@ -149,17 +200,17 @@ __device__ __forceinline__ void lu_solve(const double (&A)[N][N], const int (&pi
 #pragma unroll
         for (int c = a + 1; c < NACT; ++c) {
             const int i = P(c);
-            b[i] = fma(-A[i][k], b[k], b[i]);
+            b[i] = fma(-factor<FL>(A, fl, i, k), b[k], b[i]);
         }
     }
 #pragma unroll
     for (int a = N - 1; a >= 0; --a) {
         const int k = P(a);
-        b[k] *= A[k][k];
+        b[k] *= factor<FL>(A, fl, k, k);
 #pragma unroll
         for (int c = 0; c < (a < NACT ? a : NACT); ++c) {
             const int r = P(c);
-            b[r] = fma(-A[r][k], b[k], b[r]);
+            b[r] = fma(-factor<FL>(A, fl, r, k), b[k], b[r]);
         }
     }
 }
@@ -204,6 +255,13 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
     // the swap mask is the same in every active lane (lu_factor builds it from
     // __any), so it is read into a scalar register once
     const unsigned swaps = __builtin_amdgcn_readfirstlane(lu_factor(M, piv, ok));
+    if constexpr (kFactorsInLds) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (kFactorSlots.slot[i][j] >= 0) ul[kFactorSlots.slot[i][j] * kLaneStride] = M[i][j];
+    }
     if constexpr (STASH) {
         if (stash) {
 #pragma unroll
@@ -216,9 +274,16 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
         }
     }
 
-    lu_solve(M, piv, opaque_uniform(swaps), f);
+    // the stage vectors when the factors take the LDS words: private memory
+    // (the indices pass through an empty asm so the array is not promoted to
+    // registers, which the factors need)
+    double us[kFactorsInLds ? Rodas4::S - 1 : 1][N];
+    lu_solve<kFactorsInLds>(M, piv, opaque_uniform(swaps), f, ul);
 #pragma unroll
-    for (int k = 0; k < N; ++k) ul[k * kLaneStride] = f[k];
+    for (int k = 0; k < N; ++k) {
+        if constexpr (kFactorsInLds) us[opaque_index(0)][k] = f[k];
+        else ul[k * kLaneStride] = f[k];
+    }
     if constexpr (STASH) {
         if (stash)
 #pragma unroll
@@ -233,7 +298,9 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
             double v = y[k], w = 0.0;
 #pragma unroll
             for (int j = 0; j < s; ++j) {
-                const double uj = ul[(j * N + k) * kLaneStride];
+                double uj;
+                if constexpr (kFactorsInLds) uj = us[opaque_index(j)][k];
+                else uj = ul[(j * N + k) * kLaneStride];
                 v = fma(RA[s][j], uj, v);
                 w = fma(RC[s][j], uj, w);
             }
@@ -247,10 +314,13 @@ __device__ __forceinline__ bool ros_step_impl(const double* __restrict__ par, do
         mech::rhs(par, p, ip, Ys, u);
 #pragma unroll
         for (int k = 0; k < N; ++k) u[k] = fma(acc[k], hinv, u[k]);
-        lu_solve(M, piv, opaque_uniform(swaps), u);
+        lu_solve<kFactorsInLds>(M, piv, opaque_uniform(swaps), u, ul);
         if (s < Rodas4::S - 1) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) ul[(s * N + k) * kLaneStride] = u[k];
+            for (int k = 0; k < N; ++k) {
+                if constexpr (kFactorsInLds) us[opaque_index(s)][k] = u[k];
+                else ul[(s * N + k) * kLaneStride] = u[k];
+            }
         }
         if constexpr (STASH) {
             if (stash)

@@ -960,7 +960,7 @@ int run_adjoint(chem_mechanism* m, int64_t ncell, const double* T0, const double
         // the stage vectors (5 n doubles a lane), and during a step adjoint the
         // 3 nr parameter accumulators when they fit 80 doubles a lane (the
         // device code's kAdjParamsInLds)
-        const int words = std::max(5 * n, 3 * nr <= 80 ? 3 * nr : 0);
+        const int words = std::max(d->lane_words(), 3 * nr <= 80 ? 3 * nr : 0);
         ashmem = (unsigned)(64 * words * sizeof(double));
         nslot = std::min<int64_t>(ncell, (int64_t)d->num_cu * 4 * 64);
     }

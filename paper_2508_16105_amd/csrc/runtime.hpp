@@ -218,8 +218,11 @@ struct DeviceState {
     size_t euler_cap = 0;                // cells
     unsigned long long* euler_flags = nullptr;   // 1D driver: bad flag, max CFL (bits)
     int n = 0;                           // state size ns + 1
-    // LDS for the RODAS4 stage vectors u_1..u_5 of every lane of a workgroup
-    unsigned stage_lds(int block) const { return (unsigned)(block * 5 * n * sizeof(double)); }
+    // LDS doubles a lane of the one-cell-per-lane kernels holds: the RODAS4
+    // stage vectors u_1..u_5, or from 12 unknowns on up to 80 entries of the
+    // LU factors (the device code's kLaneWords never exceeds this)
+    int lane_words() const { return n >= 12 ? 80 : 5 * n; }
+    unsigned stage_lds(int block) const { return (unsigned)(block * lane_words() * sizeof(double)); }
 };
 
 }  // namespace chemmi

@@ -34,12 +34,13 @@ template <class T> static void wr(FILE* f, const T* p, size_t n)
 }
 
 // one lane per workgroup; the LDS of one lane is what the library gives it:
-// the stage vectors u_1..u_5, 5 N doubles, or in the adjoint the 3 NR
-// parameter accumulators if they fit 80 doubles and are more (an exact heap
+// its LDS words (the stage vectors or the LU factor entries), or in the
+// adjoint the 3 NR parameter accumulators if they are more (an exact heap
 // block, so the address sanitizer sees any access beyond it)
 static void launch_lanes(long n, void (*body)(), bool adjoint = false)
 {
-    const int words = adjoint && 3 * mech::NR <= 80 && 3 * mech::NR > 5 * mech::N ? 3 * mech::NR : 5 * mech::N;
+    const int words = adjoint && chem::kAdjParamsInLds && 3 * mech::NR > chem::kLaneWords ? 3 * mech::NR
+                                                                                           : chem::kLaneWords;
     double* lds = (double*)malloc(sizeof(double) * words);
     emu_lds = lds;
     blockDim = {1, 1, 1};
