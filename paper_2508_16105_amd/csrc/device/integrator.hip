@@ -51,6 +51,10 @@ constexpr int kLaneStride = 64;
 // entries of the LU factors the solves read: L below the diagonal of the
 // first NACT positions, and per position a its diagonal and min(a, NACT) of U
 constexpr int kFactorEntries = NACT * (NACT - 1) / 2 + N + (NACT * (NACT - 1)) / 2 + (N - NACT) * NACT;
+// From 12 unknowns the factors no longer fit beside the source-term temporaries
+// and spill to private memory (measured at 14: 1.4 KB a lane), where every
+// solve waits on them; below, they stay in accumulation registers, whose two
+// moves per read cost less than an LDS load in the solve's chain (m9).
 constexpr bool kFactorsInLds = N >= 12;
 constexpr int kLdsBudget = 80;     // doubles a lane: 160 KB over four 64-lane waves
 constexpr int kFactorsLds = kFactorsInLds ? (kFactorEntries < kLdsBudget ? kFactorEntries : kLdsBudget) : 0;
